@@ -1,0 +1,185 @@
+/*
+ * powerlu.h -- C ABI of libpowerlu, an MI355X (gfx950) implementation of
+ * PowerLU and PowerLU_FP: randomized LU low-rank approximation with any number
+ * of passes v >= 2 over the input matrix (B. Zhang, M. Mascagni,
+ * "Pass-Efficient Randomized LU Algorithms for Computing Low-Rank Matrix
+ * Approximation", arXiv:2002.07138).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Matrices are float32, row-major, with an explicit leading dimension
+ *    (elements between the starts of consecutive rows).  Leading dimensions
+ *    must be >= the row length and, for the fast paths, multiples of 4;
+ *    device pointers must be 16-byte aligned.
+ *  - Pointers named in an entry point's comment as "device" point to memory on
+ *    the handle's device (hipMalloc / torch CUDA tensors); "host" pointers are
+ *    ordinary host memory.  The caller owns all of them; the library never
+ *    frees caller memory and never writes to the input matrix A.
+ *  - Every call is asynchronous on the handle's stream unless it takes a
+ *    non-NULL plu_info*, in which case it synchronizes that stream and fills
+ *    the struct before returning.
+ *  - Permutations are 0-based int32 vectors: p (length m) and q (length n)
+ *    such that A[p[i], q[j]] ~= sum_t L[i, t] * U[t, j]  (the paper's
+ *    P A Q ~= L U, eq. powerlufinal in Sec. 3.1, written in index form).
+ *  - L (m x k) is lower trapezoidal with diag(L) = diag(U2); U (k x n) is unit
+ *    upper trapezoidal with |u_ij| <= 1 (U = L2^T, Alg. 5 step 8).
+ *  - Return value: 0 on success; -i when argument i (1-based) is invalid;
+ *    a positive PLU_* code otherwise.  The library keeps workspace on the
+ *    handle and grows it on demand (PLU_ERR_OOM if that fails).
+ */
+#ifndef POWERLU_H
+#define POWERLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PLU_OK = 0,
+  PLU_WARN_ZERO_PIVOT = 1,     /* an LU step met an exactly zero pivot column (LAPACK getrf INFO > 0) */
+  PLU_TOL_NOT_REACHED = 2,     /* fixed precision: eps not met with l columns; rank-l result returned */
+  PLU_ERR_NONFINITE = 3,       /* A holds NaN or Inf */
+  PLU_ERR_OOM = 4,             /* device workspace allocation failed */
+  PLU_ERR_HIP = 5,             /* a HIP runtime call failed */
+  PLU_ERR_NOT_IMPLEMENTED = 6,
+  PLU_ERR_TIMEOUT = 7,         /* a device-side wait in the cooperative LU panel exceeded its bound */
+  PLU_PENDING = 8              /* server: request not finished yet */
+};
+
+typedef enum { PLU_PREC_FP32 = 0, PLU_PREC_BF16 = 1 } plu_prec;
+
+typedef struct plu_handle_s* plu_handle;
+
+/* Filled on request after the stream has synchronized. */
+typedef struct {
+  int32_t status;            /* same code the call returned */
+  int32_t rank;              /* k used for L and U */
+  int32_t passes;            /* passes over A actually made (= v) */
+  int32_t zero_pivot_step;   /* first zero pivot over the final two LU steps, -1 if none */
+  int32_t tol_reached;       /* fixed precision: 1 if E <= eps^2 ||A||_F^2 */
+  int32_t l;                 /* sketch width used */
+  double normA2;             /* ||A||_F^2, float64 accumulation */
+  double E_final;            /* fixed precision: indicator E_k (Thm 4.3) */
+  float min_pivot_gap;       /* min over the final two LU steps of (|top1|-|top2|)/|top1| */
+  float pad_;
+} plu_info;
+
+/* Handle bound to one device and one stream (hip_stream NULL = null stream).
+ * Not thread-safe: one host thread per handle. */
+int plu_create(plu_handle* h, int device, void* hip_stream);
+int plu_destroy(plu_handle h);
+int plu_set_stream(plu_handle h, void* hip_stream);
+/* Bytes of device workspace the handle will hold for a fixed-rank or
+ * fixed-precision call of this shape and sketch width l. */
+int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, size_t* bytes);
+const char* plu_status_string(int status);
+
+/* ---- Fixed-rank problem (Def. 1.1, Sec. 1) solved by PowerLU: Alg. 5 with
+ * its steps 1-2 replaced by Alg. 7 (Sec. 3.4).
+ *   A      device, m x n, lda.
+ *   k      target rank, 1 <= k;  p_over >= 0 oversampling (the paper's q);
+ *          l = k + p_over must satisfy l < min(m, n) (Alg. 7 REQUIRE).
+ *   v      passes over A, v >= 2.
+ *   prec   arithmetic of the v-1 passes inside Alg. 7: FP32 (MFMA fp32) or
+ *          BF16 (A and the iterate rounded to bf16, fp32 accumulation).  The
+ *          final pass Y = A V(:,1:k) always runs in FP32.
+ *   Omega  device, nullable.  (v even ? m : n) x l Gaussian test matrix with
+ *          leading dimension l.  NULL draws it on the device from `seed` with
+ *          the Philox4x32-10 layout of plu_gaussian.
+ *   p, q   device int32 outputs, lengths m and n.
+ *   L, U   device outputs: L m x k (ldl >= k), U k x n (ldu >= n).
+ *   info   host, nullable (non-NULL synchronizes).                        */
+int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
+                   int32_t k, int32_t p_over, int32_t v, int32_t prec,
+                   const float* Omega, uint64_t seed,
+                   int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                   plu_info* info);
+
+/* ---- Fixed-precision problem (Sec. 1, last paragraph of Def. 1.1's
+ * discussion) solved by PowerLU_FP: Alg. 9 on top of Alg. 8 (block rule) or
+ * Alg. 11 (column rule, column_exact = 1), with the error indicator of
+ * Thm 4.3 accumulated in float64 and the stopping test E <= eps^2 ||A||_F^2.
+ *   eps    > 0 relative Frobenius tolerance.
+ *   b      block size >= 1; l (sketch width) must be a multiple of b and
+ *          < min(m, n); l = 0 selects min(50 b, b * floor((min(m,n)-1)/b)).
+ *   L, U   device outputs with room for l columns / rows: L m x l (ldl >= l),
+ *          U l x n (ldu >= n); only the leading rank columns/rows are written.
+ *   rank_out host int32*, nullable: receives k (the call synchronizes to read
+ *          it; the rank is also in info).
+ * If eps is not met within l columns the rank-l factorization is returned
+ * with PLU_TOL_NOT_REACHED.  A zero matrix gives rank 0.                  */
+int plu_fixed_precision(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
+                        double eps, int32_t b, int32_t l, int32_t v, int32_t column_exact,
+                        int32_t prec, const float* Omega, uint64_t seed,
+                        int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                        int32_t* rank_out, plu_info* info);
+
+/* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
+ * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
+ *   all matrix/vector pointers device; rel_resid host.  Synchronizes.     */
+int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
+                 const int32_t* p, const int32_t* q, int32_t k,
+                 const float* L, int64_t ldl, const float* U, int64_t ldu,
+                 double* rel_resid);
+
+/* ================= Building blocks (one call per step of the path) ======= */
+
+/* Gaussian test matrix (Sec. 1; Alg. 7 lines 2 and 9): out (device,
+ * rows x cols, ldo) filled with N(0,1) values.  Element e = i*cols + j is
+ * word e%4 of Philox4x32-10 block e/4 (Salmon et al., SC'11) with counter
+ * (e/4 mod 2^32, e/4 div 2^32, 0, 0) and key (seed mod 2^32, seed div 2^32);
+ * words map to (0,1] as u = ((x >> 8) + 1) 2^-24 and pairs (w0,w1), (w2,w3)
+ * become (r cos t, r sin t) with r = sqrt(-2 ln u_a), t = 2 pi u_b.       */
+int plu_gaussian(plu_handle h, int64_t rows, int64_t cols, uint64_t seed,
+                 float* out, int64_t ldo);
+
+/* One pass over A (the matrix products of Alg. 7 and Alg. 5 step 3):
+ * trans = 0: out (m x l) = A X with X n x l;  trans = 1: out (n x l) = A^T X
+ * with X m x l.  All device.  normA2_out: device double*, nullable; receives
+ * ||A||_F^2 accumulated in float64 while A streams through (Alg. 8 line 1).
+ * prec: PLU_PREC_FP32 or PLU_PREC_BF16 (operands rounded to bf16).       */
+int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, int64_t lda,
+             int32_t l, const float* X, int64_t ldx, float* out, int64_t ldo,
+             int32_t prec, double* normA2_out);
+
+/* LU with partial pivoting of a tall M x c matrix (M >= c), the paper's
+ * lu(.) (Sec. 2 notation): pivots are the first maximum |value| in LAPACK's
+ * current row order.  F (device, in/out, ldf) is replaced by V = P^T L, the
+ * unit lower trapezoidal factor placed back in F's own row order (the
+ * two-output form [V, ~] = lu(X) of Alg. 6/7).  perm (device int32, length
+ * M, nullable) receives the row order: F_in[perm] = L U.  Ufac (device,
+ * c x c, ldu, nullable) receives U (upper triangular, zeros below).
+ * info (host, nullable): zero_pivot_step and min_pivot_gap.               */
+int plu_getrf(plu_handle h, int64_t M, int32_t c, float* F, int64_t ldf,
+              int32_t* perm, float* Ufac, int64_t ldu, plu_info* info);
+
+/* Thin QR basis (the paper's [V, ~] = qr(X), Alg. 6 line 5 / Alg. 7 lines 6
+ * and 15): X (device, M x c, ldx, M > c) is replaced by an orthonormal Q
+ * with Range(Q(:,1:j)) = Range(X(:,1:j)) for every j (column signs are
+ * unspecified).                                                           */
+int plu_thin_qr(plu_handle h, int64_t M, int32_t c, float* X, int64_t ldx);
+
+/* Alg. 7 alone: V (device, n x l, ldv) = orthonormal basis after v-1 passes.
+ * Omega as in plu_fixed_rank (nullable -> drawn from seed).              */
+int plu_range_basis(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
+                    int32_t l, int32_t v, int32_t prec, const float* Omega, uint64_t seed,
+                    float* V, int64_t ldv);
+
+/* Thm 4.3 indicator and the Alg. 8 / Alg. 11 rule on G = A V (device,
+ * m x l, ldg): column norms^2 in float64, E_j = normA2 - sum_{i<=j}, k = the
+ * first column (column_exact) or block end (else) with E_j <= eps^2 normA2.
+ * k_out, E_out (host) receive k and E_k; colnorm2 (host, length l,
+ * nullable) the column norms.  Returns PLU_TOL_NOT_REACHED when no column
+ * qualifies (k = l).  Synchronizes.                                       */
+int plu_rank_rule(plu_handle h, int64_t m, int32_t l, const float* G, int64_t ldg,
+                  double normA2, double eps, int32_t b, int32_t column_exact,
+                  int32_t* k_out, double* E_out, double* colnorm2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POWERLU_H */

@@ -1,0 +1,285 @@
+"""Python binding of libpowerlu (PowerLU / PowerLU_FP on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library (``libpowerlu.so`` next to this file, built by ``build.py``).  torch is
+used for device memory and the current stream.  If the library is missing the
+import of any entry point raises: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpowerlu.so")
+
+PLU_OK = 0
+PLU_WARN_ZERO_PIVOT = 1
+PLU_TOL_NOT_REACHED = 2
+PLU_ERR_NONFINITE = 3
+PLU_ERR_OOM = 4
+PLU_ERR_HIP = 5
+PLU_ERR_NOT_IMPLEMENTED = 6
+PLU_ERR_TIMEOUT = 7
+PLU_PENDING = 8
+PREC_FP32 = 0
+PREC_BF16 = 1
+
+_ENTRY_POINTS = [
+    "plu_create", "plu_destroy", "plu_set_stream", "plu_workspace_size", "plu_status_string",
+    "plu_fixed_rank", "plu_fixed_precision", "plu_residual", "plu_gaussian", "plu_pass",
+    "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule",
+]
+
+
+class PluInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("rank", ctypes.c_int32), ("passes", ctypes.c_int32),
+        ("zero_pivot_step", ctypes.c_int32), ("tol_reached", ctypes.c_int32),
+        ("l", ctypes.c_int32), ("normA2", ctypes.c_double), ("E_final", ctypes.c_double),
+        ("min_pivot_gap", ctypes.c_float), ("pad_", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
+class PowerLUError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib().plu_status_string(code).decode() if code > 0 else f"invalid argument {-code}"
+        super().__init__(f"{where}: status {code} ({msg})")
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libpowerlu.so not found at {LIB_PATH}; run build.py "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint64, ctypes.c_double)
+        pinfo = ctypes.POINTER(PluInfo)
+        sig = {
+            "plu_create": [ctypes.POINTER(vp), ctypes.c_int, vp],
+            "plu_destroy": [vp],
+            "plu_set_stream": [vp, vp],
+            "plu_workspace_size": [vp, i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "plu_status_string": [ctypes.c_int],
+            "plu_fixed_rank": [vp, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
+                               vp, vp, vp, i64, vp, i64, pinfo],
+            "plu_fixed_precision": [vp, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, vp, u64,
+                                    vp, vp, vp, i64, vp, i64, ctypes.POINTER(i32), pinfo],
+            "plu_residual": [vp, i64, i64, vp, i64, vp, vp, i32, vp, i64, vp, i64,
+                             ctypes.POINTER(dbl)],
+            "plu_gaussian": [vp, i64, i64, u64, vp, i64],
+            "plu_pass": [vp, i32, i64, i64, vp, i64, i32, vp, i64, vp, i64, i32, vp],
+            "plu_getrf": [vp, i64, i32, vp, i64, vp, vp, i64, pinfo],
+            "plu_thin_qr": [vp, i64, i32, vp, i64],
+            "plu_range_basis": [vp, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, i64],
+            "plu_rank_rule": [vp, i64, i32, vp, i64, dbl, dbl, i32, i32, ctypes.POINTER(i32),
+                              ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "plu_status_string" else ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (raises if it was not built)."""
+    return _lib()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_mat(t, name, dtype="float32"):
+    import torch
+    if t is None:
+        return
+    want = {"float32": torch.float32, "int32": torch.int32, "float64": torch.float64}[dtype]
+    if t.dtype != want:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError(f"{name}: expected a device tensor")
+    if t.dim() == 2 and t.stride(1) != 1:
+        raise ValueError(f"{name}: rows must be contiguous (row-major)")
+
+
+def _ld(t):
+    return t.stride(0) if t.dim() == 2 else 1
+
+
+@dataclass
+class Factors:
+    p: "object"
+    q: "object"
+    L: "object"
+    U: "object"
+    rank: int
+    info: dict
+
+
+class Handle:
+    """One libpowerlu handle bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = device
+        lib = _lib()
+        h = ctypes.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        rc = lib.plu_create(ctypes.byref(h), device, ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise PowerLUError(rc, "plu_create")
+        self._h = h
+        self._stream = s
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().plu_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._stream = stream
+        rc = _lib().plu_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise PowerLUError(rc, "plu_set_stream")
+
+    def _rc(self, rc, where, ok=(PLU_OK,)):
+        if rc not in ok:
+            raise PowerLUError(rc, where)
+        return rc
+
+    # ---------------------------------------------------------------- steps
+    def gaussian(self, rows, cols, seed, out=None):
+        t = self._torch
+        if out is None:
+            out = t.empty((rows, cols), dtype=t.float32, device=f"cuda:{self.device}")
+        _check_mat(out, "out")
+        self._rc(_lib().plu_gaussian(self._h, rows, cols, seed, _ptr(out), _ld(out)), "plu_gaussian")
+        return out
+
+    def pass_(self, A, X, trans=False, out=None, prec=PREC_FP32, normA2=None):
+        t = self._torch
+        _check_mat(A, "A"); _check_mat(X, "X")
+        m, n = A.shape
+        l = X.shape[1]
+        rows = n if trans else m
+        if out is None:
+            out = t.empty((rows, l), dtype=t.float32, device=A.device)
+        _check_mat(out, "out")
+        if normA2 is not None:
+            _check_mat(normA2, "normA2", "float64")
+        self._rc(_lib().plu_pass(self._h, 1 if trans else 0, m, n, _ptr(A), _ld(A), l, _ptr(X),
+                                 _ld(X), _ptr(out), _ld(out), prec, _ptr(normA2)), "plu_pass")
+        return out
+
+    def getrf(self, F, want_perm=True, want_u=True, sync_info=True):
+        """In place: F -> V = P^T L.  Returns (perm, U, info)."""
+        t = self._torch
+        _check_mat(F, "F")
+        M, c = F.shape
+        perm = t.empty(M, dtype=t.int32, device=F.device) if want_perm else None
+        U = t.empty((c, c), dtype=t.float32, device=F.device) if want_u else None
+        info = PluInfo()
+        rc = _lib().plu_getrf(self._h, M, c, _ptr(F), _ld(F), _ptr(perm), _ptr(U),
+                              _ld(U) if U is not None else 0,
+                              ctypes.byref(info) if sync_info else None)
+        self._rc(rc, "plu_getrf", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
+        return perm, U, (info.as_dict() if sync_info else None)
+
+    def thin_qr(self, X):
+        _check_mat(X, "X")
+        M, c = X.shape
+        self._rc(_lib().plu_thin_qr(self._h, M, c, _ptr(X), _ld(X)), "plu_thin_qr")
+        return X
+
+    def range_basis(self, A, l, v, Omega=None, seed=0, prec=PREC_FP32):
+        t = self._torch
+        _check_mat(A, "A"); _check_mat(Omega, "Omega")
+        m, n = A.shape
+        V = t.empty((n, l), dtype=t.float32, device=A.device)
+        self._rc(_lib().plu_range_basis(self._h, m, n, _ptr(A), _ld(A), l, v, prec, _ptr(Omega),
+                                        seed, _ptr(V), _ld(V)), "plu_range_basis")
+        return V
+
+    def rank_rule(self, G, normA2, eps, b, column_exact=True):
+        _check_mat(G, "G")
+        m, l = G.shape
+        k = ctypes.c_int32()
+        E = ctypes.c_double()
+        cn = (ctypes.c_double * l)()
+        rc = _lib().plu_rank_rule(self._h, m, l, _ptr(G), _ld(G), float(normA2), float(eps), b,
+                                  1 if column_exact else 0, ctypes.byref(k), ctypes.byref(E), cn)
+        self._rc(rc, "plu_rank_rule", ok=(PLU_OK, PLU_TOL_NOT_REACHED))
+        return k.value, E.value, list(cn), rc == PLU_OK
+
+    # ------------------------------------------------------------- problems
+    def fixed_rank(self, A, k, p_over, v, Omega=None, seed=0, prec=PREC_FP32, sync_info=True,
+                   out=None):
+        t = self._torch
+        _check_mat(A, "A"); _check_mat(Omega, "Omega")
+        m, n = A.shape
+        dev = A.device
+        if out is None:
+            p = t.empty(m, dtype=t.int32, device=dev)
+            q = t.empty(n, dtype=t.int32, device=dev)
+            L = t.empty((m, k), dtype=t.float32, device=dev)
+            U = t.empty((k, n), dtype=t.float32, device=dev)
+        else:
+            p, q, L, U = out
+        info = PluInfo()
+        rc = _lib().plu_fixed_rank(self._h, m, n, _ptr(A), _ld(A), k, p_over, v, prec,
+                                   _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U),
+                                   _ld(U), ctypes.byref(info) if sync_info else None)
+        self._rc(rc, "plu_fixed_rank", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
+        return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
+
+    def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,
+                        prec=PREC_FP32):
+        t = self._torch
+        _check_mat(A, "A"); _check_mat(Omega, "Omega")
+        m, n = A.shape
+        dev = A.device
+        lcap = l if l else min(50 * b, b * ((min(m, n) - 1) // b))
+        p = t.empty(m, dtype=t.int32, device=dev)
+        q = t.empty(n, dtype=t.int32, device=dev)
+        L = t.empty((m, lcap), dtype=t.float32, device=dev)
+        U = t.empty((lcap, n), dtype=t.float32, device=dev)
+        k = ctypes.c_int32()
+        info = PluInfo()
+        rc = _lib().plu_fixed_precision(self._h, m, n, _ptr(A), _ld(A), float(eps), b, l, v,
+                                        1 if column_exact else 0, prec, _ptr(Omega), seed,
+                                        _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
+                                        ctypes.byref(k), ctypes.byref(info))
+        self._rc(rc, "plu_fixed_precision", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT, PLU_TOL_NOT_REACHED))
+        kk = k.value
+        return Factors(p, q, L[:, :kk], U[:kk], kk, info.as_dict())
+
+    def residual(self, A, f: Factors):
+        _check_mat(A, "A")
+        m, n = A.shape
+        r = ctypes.c_double()
+        L, U = f.L, f.U
+        self._rc(_lib().plu_residual(self._h, m, n, _ptr(A), _ld(A), _ptr(f.p), _ptr(f.q), f.rank,
+                                     _ptr(L), _ld(L), _ptr(U), _ld(U), ctypes.byref(r)),
+                 "plu_residual")
+        return r.value

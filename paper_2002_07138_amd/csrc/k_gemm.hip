@@ -1,0 +1,376 @@
+// Pass kernels: one streaming pass over A producing A X or A^T X (the matrix
+// products of Alg. 7 and of Alg. 5 step 3 / Alg. 8 step 3), on FP32 MFMA.
+//
+// Work decomposition (per workgroup of 256 threads = 4 waves):
+//   * 256 rows of the kept dimension P (64 per wave, 4 MFMA row tiles),
+//   * NT*16 columns of the sketch (NT <= 8 MFMA column tiles),
+//   * a contiguous range of the reduced dimension R, walked 32 at a time
+//     through LDS with the next stage prefetched into registers.
+// v_mfma_f32_16x16x4f32 is fed with a permuted reduction order: lane (r, g)
+// of a 16x16x4 step s uses reduction index 4g + s inside a 16-wide group, so
+// one 16-byte LDS read of A gives a lane its operands for four consecutive
+// MFMAs in mode N.  Both operands use the same permutation, so the sum is
+// unchanged.  Split partials are reduced by a second kernel in a fixed order,
+// so results do not depend on scheduling.
+#include "plu_internal.h"
+
+#include <algorithm>
+
+namespace plu {
+
+namespace {
+
+constexpr int BP = GEMM_BP;
+constexpr int BK = GEMM_BK;
+constexpr int AST_N = BK + 4;   // mode N A tile: [BP][BK+4]  (row p, reduction r)
+constexpr int AST_T = BP + 4;   // mode T A tile: [BK][BP+4]  (reduction r, row p)
+
+__device__ __forceinline__ double block_sum_double(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = (red[0] + red[1]) + (red[2] + red[3]);
+  return t;
+}
+
+__device__ __forceinline__ f32x4 load4(const float* src, int64_t idx, int64_t lim, int vec) {
+  // src[idx .. idx+3], entries at or beyond lim read as zero.  vec (uniform)
+  // says src + idx is 16-byte aligned, so the full case is one vector load.
+  f32x4 v = {0.f, 0.f, 0.f, 0.f};
+  if (vec && idx + 3 < lim) {
+    v = *reinterpret_cast<const f32x4*>(src + idx);
+  } else {
+    if (idx + 0 < lim) v.x = src[idx + 0];
+    if (idx + 1 < lim) v.y = src[idx + 1];
+    if (idx + 2 < lim) v.z = src[idx + 2];
+    if (idx + 3 < lim) v.w = src[idx + 3];
+  }
+  return v;
+}
+
+template <int MODE, int NT, int EPI>
+__global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
+  constexpr int XC = NT * 16;
+  constexpr int XST = XC + 4;
+  constexpr int A_ELEMS = (MODE == 0) ? BP * AST_N : BK * AST_T;
+  constexpr int XV = BK * NT * 4;            // float4 slots in the X tile
+  constexpr int XIT = (XV + 255) / 256;
+  __shared__ __attribute__((aligned(16))) float As[A_ELEMS];
+  __shared__ __attribute__((aligned(16))) float Xs[BK * XST];
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, pr = lane & 15, g4 = lane >> 4;
+  const int split = blockIdx.x % g.nsplit;
+  const int64_t p0 = (int64_t)(blockIdx.x / g.nsplit) * BP;
+  const int64_t c0 = (int64_t)blockIdx.y * XC;
+  const int64_t rb = (int64_t)split * g.rsplit;
+  const int64_t re = (rb + g.rsplit < g.R) ? rb + g.rsplit : g.R;
+  const bool do_ss = (g.sumsq_part != nullptr) && blockIdx.y == 0;
+  double ss = 0.0;
+
+  f32x4 ra[8];
+  f32x4 rx[XIT];
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto gload = [&](int64_t r) {
+    if (MODE == 0) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int row = it * 32 + (tid >> 3);
+        const int col = (tid & 7) * 4;
+        const int64_t p = p0 + row;
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (p < g.P) {
+          const int64_t srow = g.arow ? (int64_t)g.arow[p] : p;
+          v = load4(g.A + srow * g.lda, r + col, re, g.avec);
+        }
+        ra[it] = v;
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int row = it * 4 + (tid >> 6);
+        const int col = (tid & 63) * 4;
+        const int64_t rr = r + row;
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (rr < re) v = load4(g.A + rr * g.lda, p0 + col, g.P, g.avec);
+        ra[it] = v;
+      }
+    }
+    if (do_ss) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const double a0 = ra[it].x, a1 = ra[it].y, a2 = ra[it].z, a3 = ra[it].w;
+        ss = fma(a0, a0, ss); ss = fma(a1, a1, ss); ss = fma(a2, a2, ss); ss = fma(a3, a3, ss);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int idx = it * 256 + tid;
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (idx < XV) {
+        const int row = idx / (NT * 4);
+        const int col = (idx % (NT * 4)) * 4;
+        const int64_t rr = r + row;
+        if (rr < re) v = load4(g.X + rr * g.ldx, c0 + col, g.C, g.xvec);
+      }
+      rx[it] = v;
+    }
+  };
+
+  auto sstore = [&]() {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      if (MODE == 0) {
+        const int row = it * 32 + (tid >> 3);
+        const int col = (tid & 7) * 4;
+        *reinterpret_cast<f32x4*>(&As[row * AST_N + col]) = ra[it];
+      } else {
+        const int row = it * 4 + (tid >> 6);
+        const int col = (tid & 63) * 4;
+        *reinterpret_cast<f32x4*>(&As[row * AST_T + col]) = ra[it];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < XIT; ++it) {
+      const int idx = it * 256 + tid;
+      if (idx < XV) {
+        const int row = idx / (NT * 4);
+        const int col = (idx % (NT * 4)) * 4;
+        *reinterpret_cast<f32x4*>(&Xs[row * XST + col]) = rx[it];
+      }
+    }
+  };
+
+  auto compute = [&]() {
+#pragma unroll
+    for (int kk = 0; kk < BK / 16; ++kk) {
+      if (MODE == 0) {
+        f32x4 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[i] = *reinterpret_cast<const f32x4*>(
+              &As[(wave * 64 + i * 16 + pr) * AST_N + kk * 16 + g4 * 4]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          float b[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) b[j] = Xs[(kk * 16 + g4 * 4 + s) * XST + j * 16 + pr];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j], acc[i][j], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          float a[4], b[NT];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = As[(kk * 16 + g4 * 4 + s) * AST_T + wave * 64 + i * 16 + pr];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) b[j] = Xs[(kk * 16 + g4 * 4 + s) * XST + j * 16 + pr];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  if (rb < re) {
+    gload(rb);
+    for (int64_t r = rb; r < re; r += BK) {
+      __syncthreads();
+      sstore();
+      __syncthreads();
+      if (r + BK < re) gload(r + BK);
+      compute();
+    }
+  }
+
+  // Epilogue: acc[i][j][e] is out[p][c] with p = p0 + 64 wave + 16 i + 4 g4 + e,
+  // c = c0 + 16 j + pr (the 16x16 MFMA output layout).
+  double rs = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = p0 + wave * 64 + i * 16 + g4 * 4 + e;
+      if (p >= g.P) continue;
+      bool rowok = true;
+      if (EPI == EPI_SUB && g.rowmask) rowok = g.rowmask[p] < 0;
+      if (!rowok) continue;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int64_t c = c0 + j * 16 + pr;
+        if (c >= g.C) continue;
+        const float v = acc[i][j][e];
+        if (EPI == EPI_STORE) {
+          g.out[p * g.ldo + c] = v;
+        } else if (EPI == EPI_PART) {
+          g.out[(int64_t)split * g.part_stride + p * g.ldo + c] = v;
+        } else if (EPI == EPI_SUB) {
+          g.out[p * g.ldo + c] -= v;
+        } else {
+          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + g.qidx[c]] - (double)v;
+          rs = fma(d, d, rs);
+        }
+      }
+    }
+  }
+  const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  if (g.sumsq_part != nullptr && blockIdx.y == 0) {
+    const double t = block_sum_double(ss, red);
+    if (tid == 0) g.sumsq_part[blockIdx.x] = t;
+  }
+  if (EPI == EPI_RESID) {
+    const double t = block_sum_double(rs, red);
+    if (tid == 0) g.resid_part[wg] = t;
+  }
+}
+
+template <int MODE, int EPI>
+hipError_t launch_nt(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
+  switch (nt) {
+#define PLU_NT_CASE(N) \
+  case N: hipLaunchKernelGGL((k_pass<MODE, N, EPI>), grid, dim3(256), 0, s, a); break;
+    PLU_NT_CASE(1) PLU_NT_CASE(2) PLU_NT_CASE(3) PLU_NT_CASE(4)
+    PLU_NT_CASE(5) PLU_NT_CASE(6) PLU_NT_CASE(7) PLU_NT_CASE(8)
+#undef PLU_NT_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ part,
+                                                      int64_t part_stride, int nsplit,
+                                                      float* out, int64_t ldo, int64_t P,
+                                                      int64_t C, double* colsq_part, int rb) {
+  const int64_t c = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  const int64_t pb = blockIdx.x;
+  if (c >= C) return;
+  const int64_t pe = (pb * rb + rb < P) ? pb * rb + rb : P;
+  double cs = 0.0;
+  for (int64_t p = pb * rb; p < pe; ++p) {
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * part_stride + p * ldo + c];
+    if (out) out[p * ldo + c] = s;
+    const double d = s;
+    cs = fma(d, d, cs);
+  }
+  if (colsq_part) colsq_part[pb * C + c] = cs;
+}
+
+__global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int64_t n, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += in[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_matrix(const float* A, int64_t lda, int64_t m,
+                                                     int64_t n, double* part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const float* row = A + i * lda;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+      const double d = row[j];
+      s = fma(d, d, s);
+    }
+  }
+  const double t = block_sum_double(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+}  // namespace
+
+GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wgs) {
+  GemmPlan pl;
+  pl.pblocks = (int)((P + BP - 1) / BP);
+  const int64_t cb = (C + 127) / 128;
+  pl.cblocks = (int)cb;
+  const int64_t cpb = (C + cb - 1) / cb;          // columns per block, balanced
+  pl.nt = (int)((cpb + 15) / 16);
+  if (pl.nt < 1) pl.nt = 1;
+  const int64_t base = (int64_t)pl.pblocks * pl.cblocks;
+  int64_t ns = (target_wgs + base - 1) / base;
+  const int64_t max_by_depth = std::max<int64_t>(1, R / 512);   // keep >= 512 of R per split
+  ns = std::min<int64_t>(ns, max_by_depth);
+  ns = std::min<int64_t>(ns, max_split);
+  if (ns < 1) ns = 1;
+  int64_t rs = (R + ns - 1) / ns;
+  rs = ((rs + BK - 1) / BK) * BK;
+  ns = (R + rs - 1) / rs;
+  if (ns < 1) ns = 1;
+  pl.nsplit = (int)ns;
+  pl.rsplit = rs > 0 ? rs : BK;
+  return pl;
+}
+
+hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const GemmPlan& pl,
+                       hipStream_t s) {
+  if (bf16) return hipErrorInvalidValue;
+  GemmArgs g = a;
+  g.avec = ((reinterpret_cast<uintptr_t>(g.A) & 15u) == 0 && (g.lda & 3) == 0) ? 1 : 0;
+  g.xvec = ((reinterpret_cast<uintptr_t>(g.X) & 15u) == 0 && (g.ldx & 3) == 0) ? 1 : 0;
+  g.nsplit = pl.nsplit;
+  g.rsplit = pl.rsplit;
+  // column blocks of nt*16 columns each
+  dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
+  if ((int64_t)pl.cblocks * pl.nt * 16 < g.C) return hipErrorInvalidValue;
+  if (mode == 0) {
+    switch (epi) {
+      case EPI_STORE: return launch_nt<0, EPI_STORE>(pl.nt, grid, g, s);
+      case EPI_PART: return launch_nt<0, EPI_PART>(pl.nt, grid, g, s);
+      case EPI_SUB: return launch_nt<0, EPI_SUB>(pl.nt, grid, g, s);
+      case EPI_RESID: return launch_nt<0, EPI_RESID>(pl.nt, grid, g, s);
+    }
+  } else {
+    switch (epi) {
+      case EPI_STORE: return launch_nt<1, EPI_STORE>(pl.nt, grid, g, s);
+      case EPI_PART: return launch_nt<1, EPI_PART>(pl.nt, grid, g, s);
+      case EPI_SUB: return launch_nt<1, EPI_SUB>(pl.nt, grid, g, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit, float* out,
+                                int64_t ldo, int64_t P, int64_t C, double* colsq_part,
+                                int rows_per_block, hipStream_t s) {
+  dim3 grid((unsigned)((P + rows_per_block - 1) / rows_per_block), (unsigned)((C + 255) / 256));
+  hipLaunchKernelGGL(k_splitk_reduce, grid, dim3(256), 0, s, part, part_stride, nsplit, out, ldo,
+                     P, C, colsq_part, rows_per_block);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_doubles(const double* in, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_doubles, dim3(1), dim3(256), 0, s, in, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_matrix(const float* A, int64_t lda, int64_t m, int64_t n, double* part,
+                               int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_matrix, dim3(nblocks), dim3(256), 0, s, A, lda, m, n, part);
+  return hipGetLastError();
+}
+
+}  // namespace plu

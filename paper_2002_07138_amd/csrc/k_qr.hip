@@ -1,0 +1,252 @@
+// Thin QR of a tall M x c iterate (the paper's [V, ~] = qr(X) in Alg. 6/7).
+//
+// Method: X = P^T L U (LU with partial pivoting, rows in place) gives
+// V0 = P^T L = X U^{-1}, a unit lower trapezoidal basis of the same column
+// space whose conditioning does not inherit X's (the ill-conditioning goes
+// to U).  V0 is then orthonormalized by block classical Gram-Schmidt with
+// reorthogonalization (BCGS2) over column blocks of 128, each block by
+// CholeskyQR2: Gram matrix accumulated in float64, Cholesky and triangular
+// inverse in float64 inside one workgroup, and the basis update V R^{-1} on
+// the FP32 MFMA pass kernel.  Every factor applied from the right is upper
+// triangular, so Range(Q(:,1:j)) = Range(X(:,1:j)) for all j: Q is the thin
+// Q factor of X up to column signs.
+#include "plu_internal.h"
+
+#include <cfloat>
+
+namespace plu {
+
+namespace {
+
+constexpr int QB = 128;   // column block of the Gram-Schmidt sweep
+
+// part[chunk][a][b] = sum over the chunk's rows of V[i][a] V[i][b] (float64).
+__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ V, int64_t ldv, int64_t M,
+                                             int bw, int64_t rows_per_chunk, double* part) {
+  __shared__ float S[64][QB + 1];
+  const int t = threadIdx.x;
+  const int ta = t >> 4, tb = t & 15;
+  double acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = (r0 + rows_per_chunk < M) ? r0 + rows_per_chunk : M;
+  for (int64_t rb = r0; rb < r1; rb += 64) {
+    __syncthreads();
+    for (int e = t; e < 64 * QB; e += 256) {
+      const int rr = e / QB, cc = e % QB;
+      const int64_t row = rb + rr;
+      S[rr][cc] = (row < r1 && cc < bw) ? V[row * ldv + cc] : 0.f;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 64; ++rr) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) av[i] = S[rr][ta + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bv[j] = S[rr][tb + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * bw * bw;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int a = ta + 16 * i;
+    if (a >= bw) continue;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int b = tb + 16 * j;
+      if (b < bw) out[a * bw + b] = acc[i][j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int nchunk, int bw,
+                                                    double* W) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= bw * bw) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * bw * bw + e];
+  W[e] = s;
+}
+
+// Cholesky W = L L^T (float64, in LDS), L^{-1} in place, R^{-1} = (L^{-1})^T
+// written as float32 (upper triangular, bw x bw, leading dimension ldr).
+__global__ __launch_bounds__(256) void k_chol_inv(const double* W, int bw, float* Rinv, int64_t ldr,
+                                                 double* Rinv64, int32_t* status) {
+  __shared__ double S[QB][QB + 1];
+  __shared__ double tmp[QB];
+  const int t = threadIdx.x;
+  for (int e = t; e < bw * bw; e += 256) S[e / bw][e % bw] = W[e];
+  __syncthreads();
+  for (int j = 0; j < bw; ++j) {
+    if (t == 0) {
+      double d = S[j][j];
+      if (!(d > 0.0)) {
+        status[2] = 1;
+        d = DBL_MIN;
+      }
+      S[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = S[j][j];
+    for (int i = j + 1 + t; i < bw; i += 256) S[i][j] /= piv;
+    __syncthreads();
+    const int n = bw - j - 1;
+    for (int e = t; e < n * n; e += 256) {
+      const int i = j + 1 + e / n, c = j + 1 + e % n;
+      if (c <= i) S[i][c] -= S[i][j] * S[c][j];
+    }
+    __syncthreads();
+  }
+  // in-place inverse of the lower factor, last column first
+  for (int j = bw - 1; j >= 0; --j) {
+    const double ljj = S[j][j];
+    for (int i = j + 1 + t; i < bw; i += 256) {
+      double acc = 0.0;
+      for (int c = j + 1; c <= i; ++c) acc = fma(S[i][c], S[c][j], acc);
+      tmp[i] = -acc / ljj;
+    }
+    __syncthreads();
+    for (int i = j + 1 + t; i < bw; i += 256) S[i][j] = tmp[i];
+    if (t == 0) S[j][j] = 1.0 / ljj;
+    __syncthreads();
+  }
+  for (int e = t; e < bw * bw; e += 256) {
+    const int r = e / bw, c = e % bw;   // Rinv[r][c] = Linv[c][r] for r <= c
+    const double v = (r <= c) ? S[c][r] : 0.0;
+    Rinv[(int64_t)r * ldr + c] = (float)v;
+    if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v;
+  }
+}
+
+// dst = src R^{-1} with float64 products and sums, rounded once to float32.
+// A wave owns 64 rows and one of four interleaved column groups; R^{-1}
+// (upper triangular, zeros below) is read with wave-uniform addresses.
+template <int CPT>
+__global__ __launch_bounds__(256) void k_apply_rinv64(const float* __restrict__ src, int64_t lds,
+                                                     int64_t M, int bw,
+                                                     const double* __restrict__ rinv,
+                                                     int64_t ldr, float* dst, int64_t ldd) {
+  __shared__ float Vs[64][QB + 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63, cg = t >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int e = t; e < 64 * bw; e += 256) {
+    const int rr = e / bw, cc = e % bw;
+    const int64_t row = r0 + rr;
+    Vs[rr][cc] = (row < M) ? src[row * lds + cc] : 0.f;
+  }
+  __syncthreads();
+  double acc[CPT];
+#pragma unroll
+  for (int jj = 0; jj < CPT; ++jj) acc[jj] = 0.0;
+  for (int tt = 0; tt < bw; ++tt) {
+    const double v = Vs[lane][tt];
+    const double* rr = rinv + (int64_t)tt * ldr + cg;
+#pragma unroll
+    for (int jj = 0; jj < CPT; ++jj) {
+      const int j = cg + 4 * jj;
+      if (j < bw) acc[jj] = fma(v, rr[4 * jj], acc[jj]);
+    }
+  }
+  const int64_t row = r0 + lane;
+  if (row < M) {
+#pragma unroll
+    for (int jj = 0; jj < CPT; ++jj) {
+      const int j = cg + 4 * jj;
+      if (j < bw) dst[row * ldd + j] = (float)acc[jj];
+    }
+  }
+}
+
+hipError_t gemm_any(int mode, int epi, GemmArgs g, const QrWork& qw, hipStream_t s) {
+  // EPI_STORE with automatic split-K through qw.part
+  const GemmPlan pl = plan_gemm(g.P, g.R, g.C, 64, 1024);
+  hipError_t e;
+  if (pl.nsplit > 1 && epi == EPI_STORE) {
+    if ((int64_t)pl.nsplit * g.P * g.ldo > qw.part_cap) return hipErrorInvalidValue;
+    float* out = g.out;
+    g.out = qw.part;
+    g.part_stride = g.P * g.ldo;
+    if ((e = launch_gemm(mode, EPI_PART, 0, g, pl, s)) != hipSuccess) return e;
+    return launch_splitk_reduce(qw.part, g.P * g.ldo, pl.nsplit, out, g.ldo, g.P, g.C, nullptr, 64,
+                                s);
+  }
+  GemmPlan p1 = pl;
+  if (epi != EPI_STORE) p1 = plan_gemm(g.P, g.R, g.C, 1, 1);
+  return launch_gemm(mode, epi, 0, g, p1, s);
+}
+
+hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float* dst, int64_t ldd,
+                        const QrWork& qw, bool fp64_apply, hipStream_t s) {
+  int nchunk = (int)((M + 255) / 256);
+  if (nchunk > qw.max_chunks) nchunk = qw.max_chunks;
+  int64_t rpc = (M + nchunk - 1) / nchunk;
+  rpc = ((rpc + 63) / 64) * 64;
+  nchunk = (int)((M + rpc - 1) / rpc);
+  hipLaunchKernelGGL(k_gram, dim3(nchunk), dim3(256), 0, s, src, lds, M, bw, rpc, qw.gram_part);
+  hipError_t e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((bw * bw + 255) / 256), dim3(256), 0, s, qw.gram_part,
+                     nchunk, bw, qw.gram);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, qw.gram, bw, qw.rinv, (int64_t)QB,
+                     fp64_apply ? qw.rinv64 : nullptr, qw.status);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (fp64_apply) {
+    hipLaunchKernelGGL(k_apply_rinv64<QB / 4>, dim3((unsigned)((M + 63) / 64)), dim3(256), 0, s,
+                       src, lds, M, bw, qw.rinv64, (int64_t)QB, dst, ldd);
+    return hipGetLastError();
+  }
+  GemmArgs g;
+  g.A = src; g.lda = lds;
+  g.X = qw.rinv; g.ldx = QB;
+  g.out = dst; g.ldo = ldd;
+  g.P = M; g.R = bw; g.C = bw;
+  return gemm_any(0, EPI_STORE, g, qw, s);
+}
+
+}  // namespace
+
+hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw,
+                       const QrWork& qw, hipStream_t s) {
+  hipError_t e;
+  // LU reorthogonalization: X <- P^T L
+  if ((e = getrf_run(X, ldx, M, c, gw, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
+  for (int j0 = 0; j0 < c; j0 += QB) {
+    const int bw = (c - j0 < QB) ? c - j0 : QB;
+    float* VJ = X + j0;
+    if (j0 > 0) {
+      for (int rep = 0; rep < 2; ++rep) {
+        // W = Q(:, :j0)^T V_J
+        GemmArgs g;
+        g.A = qw.q; g.lda = qw.ldq;
+        g.X = VJ; g.ldx = ldx;
+        g.out = qw.wproj; g.ldo = QB;
+        g.P = j0; g.R = M; g.C = bw;
+        if ((e = gemm_any(1, EPI_STORE, g, qw, s)) != hipSuccess) return e;
+        // V_J -= Q(:, :j0) W
+        GemmArgs h;
+        h.A = qw.q; h.lda = qw.ldq;
+        h.X = qw.wproj; h.ldx = QB;
+        h.out = VJ; h.ldo = ldx;
+        h.P = M; h.R = j0; h.C = bw;
+        if ((e = gemm_any(0, EPI_SUB, h, qw, s)) != hipSuccess) return e;
+      }
+    }
+    // first round on the MFMA pass kernel; the second (R nearly I) in float64
+    // so that the stored basis is orthonormal to about one fp32 rounding
+    if ((e = cholqr_round(VJ, ldx, M, bw, qw.tmp, QB, qw, false, s)) != hipSuccess) return e;
+    if ((e = cholqr_round(qw.tmp, QB, M, bw, qw.q + j0, qw.ldq, qw, true, s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace plu

@@ -1,0 +1,125 @@
+// Internal declarations shared by the libpowerlu translation units.
+// Everything here is gfx950 (CDNA4) device code or its host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace plu {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Pass GEMM (one pass over A): out = op(A) X, FP32 MFMA 16x16x4, fp32 accumulate.
+//   mode 0 ("N"): out[p][c] = sum_r A[p][r] X[r][c]   (A is P x R, row-major)
+//   mode 1 ("T"): out[p][c] = sum_r A[r][p] X[r][c]   (A is R x P, row-major)
+// The kept dimension P is tiled by 256 rows, the columns c by NT*16 (NT<=8),
+// the reduced dimension R by 32 per LDS stage and optionally split across
+// workgroups (partials reduced afterwards in a fixed order).
+// ---------------------------------------------------------------------------
+enum Epi { EPI_STORE = 0, EPI_PART = 1, EPI_SUB = 2, EPI_RESID = 3 };
+
+struct GemmArgs {
+  const float* A = nullptr; int64_t lda = 0;
+  const int32_t* arow = nullptr;      // mode 0 only: A row p is read from row arow[p]
+  const float* X = nullptr; int64_t ldx = 0;
+  const uint16_t* Ab = nullptr;       // bf16 copy of A (prec BF16), same lda
+  const uint16_t* Xb = nullptr;       // bf16 copy of X (prec BF16), same ldx
+  float* out = nullptr; int64_t ldo = 0;
+  int64_t part_stride = 0;            // EPI_PART: elements between split partials
+  int64_t P = 0, R = 0, C = 0;
+  int64_t rsplit = 0; int32_t nsplit = 1;
+  const int32_t* rowmask = nullptr;   // EPI_SUB: rows with rowmask[p] >= 0 are left alone
+  double* sumsq_part = nullptr;       // fused ||A||_F^2: one partial per workgroup (column block 0)
+  // EPI_RESID
+  const float* Aref = nullptr; int64_t ldaref = 0;
+  const int32_t* pidx = nullptr; const int32_t* qidx = nullptr;
+  double* resid_part = nullptr;
+  // set by launch_gemm: rows of A / X start 16-byte aligned (vector loads allowed)
+  int avec = 0, xvec = 0;
+};
+
+constexpr int GEMM_BP = 256;
+constexpr int GEMM_BK = 32;
+
+// Plans the split of R and launches; part must hold nsplit*P*ldo floats when
+// the plan splits.  Returns the number of sumsq partials written (grid size)
+// through *n_sumsq when sumsq_part is set.
+struct GemmPlan {
+  int pblocks, cblocks, nt, nsplit;
+  int64_t rsplit;
+};
+GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wgs);
+hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const GemmPlan& pl,
+                       hipStream_t s);
+hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit,
+                                float* out, int64_t ldo, int64_t P, int64_t C,
+                                double* colsq_part, int rows_per_block, hipStream_t s);
+hipError_t launch_sum_doubles(const double* in, int64_t n, double* out, hipStream_t s);
+hipError_t launch_sumsq_matrix(const float* A, int64_t lda, int64_t m, int64_t n,
+                               double* part, int nblocks, hipStream_t s);
+hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd,
+                          int64_t rows, int64_t cols, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Tall-skinny LU with partial pivoting (rows stay in place; see k_getrf.hip).
+// ---------------------------------------------------------------------------
+struct GetrfWork {
+  int32_t* piv_step;     // M
+  int32_t* pos;          // M
+  int32_t* piv_row;      // >= c
+  float* gaps;           // >= c
+  int32_t* zstep;        // first zero-pivot step (INT_MAX if none)
+  int32_t* abortf;       // timeout flag shared by every LU of a call (cleared by the caller)
+  unsigned long long* msg;
+  size_t msg_words;
+  float* u12;            // NB x ldu12 scratch for the blocked update
+  int64_t ldu12;
+  uint32_t* tag_counter; // host-side counter of panel launches (owned by the handle)
+  uint64_t timeout_ticks;
+  int max_waves;
+};
+size_t getrf_msg_words(int64_t M);
+// F: M x c (ldf).  On return F holds V = P^T L (unit lower, original row order).
+// perm (nullable): F_in[perm] = L U.  Uout (nullable): U (c x c) or U^T if utrans.
+hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w,
+                     int32_t* perm, float* Uout, int64_t ldu, int utrans, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Thin QR: LU reorthogonalization followed by block CholeskyQR2 (FP64 Gram,
+// FP64 Cholesky) with block classical Gram-Schmidt between blocks.
+// ---------------------------------------------------------------------------
+struct QrWork {
+  float* q;              // M x ldq output basis (may not alias X)
+  int64_t ldq;
+  float* tmp;            // M x 128
+  double* gram_part;     // nchunk x 128 x 128
+  int max_chunks;
+  double* gram;          // 128 x 128
+  float* rinv;           // 128 x 128
+  double* rinv64;        // 128 x 128
+  float* wproj;          // c x 128
+  float* part; int64_t part_cap;   // split-K partials (floats)
+  int32_t* status;       // [2] Cholesky breakdown flag
+};
+hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw,
+                       const QrWork& qw, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Misc kernels.
+// ---------------------------------------------------------------------------
+hipError_t launch_gaussian(float* out, int64_t ldo, int64_t rows, int64_t cols, uint64_t seed,
+                           hipStream_t s);
+hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ldd,
+                           int64_t rows, int64_t cols, int64_t cols_pad, hipStream_t s);
+hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,
+                                   int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s);
+hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,
+                            int nvblk, const double* normA2, double eps, int b, int col_mode,
+                            int32_t* kout, double* Eout, int32_t* tol, double* colnorm,
+                            hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
+
+}  // namespace plu
