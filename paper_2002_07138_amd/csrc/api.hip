@@ -30,8 +30,8 @@ struct plu_handle_s {
 namespace {
 
 constexpr int kQB = 128;
-constexpr int kMaxGramChunks = 128;
-constexpr int kTargetWgs = 1024;
+constexpr int kMaxGramChunks = 256;
+constexpr int kTargetWgs = 1024;  // concurrent pass workgroups: 4 per CU on 256 CUs
 constexpr int kMaxSplit = 16;
 
 inline int64_t ru4(int64_t x) { return (x + 3) & ~int64_t(3); }

@@ -2,7 +2,9 @@
 // products of Alg. 7 and of Alg. 5 step 3 / Alg. 8 step 3), on FP32 MFMA.
 //
 // Work decomposition (per workgroup of 256 threads = 4 waves):
-//   * 256 rows of the kept dimension P (64 per wave, 4 MFMA row tiles),
+//   * 128 rows of the kept dimension P (32 per wave, 2 MFMA row tiles; the
+//     small register footprint lets 4 workgroups share a CU, which is what
+//     hides the HBM latency of the streamed A tiles),
 //   * NT*16 columns of the sketch (NT <= 8 MFMA column tiles),
 //   * a contiguous range of the reduced dimension R, walked 32 at a time
 //     through LDS with the next stage prefetched into registers.
@@ -20,10 +22,8 @@ namespace plu {
 
 namespace {
 
-constexpr int BP = GEMM_BP;
-constexpr int BK = GEMM_BK;
-constexpr int AST_N = BK + 4;   // mode N A tile: [BP][BK+4]  (row p, reduction r)
-constexpr int AST_T = BP + 4;   // mode T A tile: [BK][BP+4]  (reduction r, row p)
+constexpr int BP = GEMM_BP;     // rows per workgroup of the default variant
+constexpr int BK = GEMM_BK;     // reduction depth per stage of the default variant
 
 __device__ __forceinline__ double block_sum_double(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -51,41 +51,60 @@ __device__ __forceinline__ f32x4 load4(const float* src, int64_t idx, int64_t li
   return v;
 }
 
-template <int MODE, int NT, int EPI>
-__global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
+// RT: 16-row MFMA tiles per wave (the workgroup covers BP = 64 RT rows);
+// BKT: reduction depth per LDS stage.
+template <int MODE, int NT, int EPI, int RT = GEMM_BP / 64, int BKT = GEMM_BK>
+__global__ __launch_bounds__(256, (NT * RT >= 32) ? 1 : 2) void k_pass(GemmArgs g) {
+  constexpr int BP = 64 * RT;
+  constexpr int BK = BKT;
+  constexpr int AST_N = BK + 4;   // mode N A tile: [BP][BK+4]  (row p, reduction r)
+  constexpr int AST_T = BP + 4;   // mode T A tile: [BK][BP+4]  (reduction r, row p)
   constexpr int XC = NT * 16;
   constexpr int XST = XC + 4;
   constexpr int A_ELEMS = (MODE == 0) ? BP * AST_N : BK * AST_T;
+  constexpr int AV = BP * BK / 4;            // float4 slots in the A tile
+  constexpr int AIT = AV / 256;
   constexpr int XV = BK * NT * 4;            // float4 slots in the X tile
   constexpr int XIT = (XV + 255) / 256;
+  static_assert(AV % 256 == 0, "A tile must split evenly over 256 threads");
   __shared__ __attribute__((aligned(16))) float As[A_ELEMS];
   __shared__ __attribute__((aligned(16))) float Xs[BK * XST];
   __shared__ double red[4];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, pr = lane & 15, g4 = lane >> 4;
-  const int split = blockIdx.x % g.nsplit;
-  const int64_t p0 = (int64_t)(blockIdx.x / g.nsplit) * BP;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of logical ids, ordered split-major, so the workgroups
+  // sharing an L2 also share the rows of X they stream.
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int npb = nwg / g.nsplit;
+  const int split = lid / npb;
+  const int64_t p0 = (int64_t)(lid % npb) * BP;
   const int64_t c0 = (int64_t)blockIdx.y * XC;
   const int64_t rb = (int64_t)split * g.rsplit;
   const int64_t re = (rb + g.rsplit < g.R) ? rb + g.rsplit : g.R;
   const bool do_ss = (g.sumsq_part != nullptr) && blockIdx.y == 0;
   double ss = 0.0;
 
-  f32x4 ra[8];
+  f32x4 ra[AIT];
   f32x4 rx[XIT];
-  f32x4 acc[4][NT];
+  f32x4 acc[RT][NT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   auto gload = [&](int64_t r) {
     if (MODE == 0) {
+      constexpr int TPR = BK / 4;            // threads per A row
+      constexpr int RPP = 256 / TPR;         // rows per pass
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int row = it * 32 + (tid >> 3);
-        const int col = (tid & 7) * 4;
+      for (int it = 0; it < AIT; ++it) {
+        const int row = it * RPP + tid / TPR;
+        const int col = (tid % TPR) * 4;
         const int64_t p = p0 + row;
         f32x4 v = {0.f, 0.f, 0.f, 0.f};
         if (p < g.P) {
@@ -95,10 +114,12 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
         ra[it] = v;
       }
     } else {
+      constexpr int TPR = BP / 4;
+      constexpr int RPP = 256 / TPR;
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int row = it * 4 + (tid >> 6);
-        const int col = (tid & 63) * 4;
+      for (int it = 0; it < AIT; ++it) {
+        const int row = it * RPP + tid / TPR;
+        const int col = (tid % TPR) * 4;
         const int64_t rr = r + row;
         f32x4 v = {0.f, 0.f, 0.f, 0.f};
         if (rr < re) v = load4(g.A + rr * g.lda, p0 + col, g.P, g.avec);
@@ -107,7 +128,7 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
     }
     if (do_ss) {
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
+      for (int it = 0; it < AIT; ++it) {
         const double a0 = ra[it].x, a1 = ra[it].y, a2 = ra[it].z, a3 = ra[it].w;
         ss = fma(a0, a0, ss); ss = fma(a1, a1, ss); ss = fma(a2, a2, ss); ss = fma(a3, a3, ss);
       }
@@ -128,14 +149,16 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
 
   auto sstore = [&]() {
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
+    for (int it = 0; it < AIT; ++it) {
       if (MODE == 0) {
-        const int row = it * 32 + (tid >> 3);
-        const int col = (tid & 7) * 4;
+        constexpr int TPR = BK / 4, RPP = 256 / TPR;
+        const int row = it * RPP + tid / TPR;
+        const int col = (tid % TPR) * 4;
         *reinterpret_cast<f32x4*>(&As[row * AST_N + col]) = ra[it];
       } else {
-        const int row = it * 4 + (tid >> 6);
-        const int col = (tid & 63) * 4;
+        constexpr int TPR = BP / 4, RPP = 256 / TPR;
+        const int row = it * RPP + tid / TPR;
+        const int col = (tid % TPR) * 4;
         *reinterpret_cast<f32x4*>(&As[row * AST_T + col]) = ra[it];
       }
     }
@@ -154,18 +177,18 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
 #pragma unroll
     for (int kk = 0; kk < BK / 16; ++kk) {
       if (MODE == 0) {
-        f32x4 a[4];
+        f32x4 a[RT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < RT; ++i)
           a[i] = *reinterpret_cast<const f32x4*>(
-              &As[(wave * 64 + i * 16 + pr) * AST_N + kk * 16 + g4 * 4]);
+              &As[(wave * 16 * RT + i * 16 + pr) * AST_N + kk * 16 + g4 * 4]);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           float b[NT];
 #pragma unroll
           for (int j = 0; j < NT; ++j) b[j] = Xs[(kk * 16 + g4 * 4 + s) * XST + j * 16 + pr];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int j = 0; j < NT; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j], acc[i][j], 0, 0, 0);
@@ -173,13 +196,14 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
       } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          float a[4], b[NT];
+          float a[RT], b[NT];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = As[(kk * 16 + g4 * 4 + s) * AST_T + wave * 64 + i * 16 + pr];
+          for (int i = 0; i < RT; ++i)
+            a[i] = As[(kk * 16 + g4 * 4 + s) * AST_T + wave * 16 * RT + i * 16 + pr];
 #pragma unroll
           for (int j = 0; j < NT; ++j) b[j] = Xs[(kk * 16 + g4 * 4 + s) * XST + j * 16 + pr];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int j = 0; j < NT; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -199,14 +223,14 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass(GemmArgs g) {
     }
   }
 
-  // Epilogue: acc[i][j][e] is out[p][c] with p = p0 + 64 wave + 16 i + 4 g4 + e,
+  // Epilogue: acc[i][j][e] is out[p][c] with p = p0 + 16 RT wave + 16 i + 4 g4 + e,
   // c = c0 + 16 j + pr (the 16x16 MFMA output layout).
   double rs = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < RT; ++i) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t p = p0 + wave * 64 + i * 16 + g4 * 4 + e;
+      const int64_t p = p0 + wave * 16 * RT + i * 16 + g4 * 4 + e;
       if (p >= g.P) continue;
       bool rowok = true;
       if (EPI == EPI_SUB && g.rowmask) rowok = g.rowmask[p] < 0;
@@ -253,23 +277,58 @@ hipError_t launch_nt(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// out = sum over splits of the partials (fixed order), one thread per 4
+// consecutive columns of a row; optional per-column float64 sums of squares
+// over each block of rows_per_block rows (deterministic: fixed order).
 __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ part,
                                                       int64_t part_stride, int nsplit,
                                                       float* out, int64_t ldo, int64_t P,
                                                       int64_t C, double* colsq_part, int rb) {
-  const int64_t c = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  const int64_t c4n = (C + 3) / 4;                 // float4 groups per row
+  const int lanes_per_row = (int)((c4n < 64) ? c4n : 64);
+  const int rows_per_pass = 256 / lanes_per_row;
+  const int tid = threadIdx.x;
+  const int rsub = tid / lanes_per_row, cl = tid % lanes_per_row;
   const int64_t pb = blockIdx.x;
-  if (c >= C) return;
   const int64_t pe = (pb * rb + rb < P) ? pb * rb + rb : P;
-  double cs = 0.0;
-  for (int64_t p = pb * rb; p < pe; ++p) {
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * part_stride + p * ldo + c];
-    if (out) out[p * ldo + c] = s;
-    const double d = s;
-    cs = fma(d, d, cs);
+  const bool active = rsub < rows_per_pass;
+  const int64_t cgi = (int64_t)blockIdx.y * 64 + cl;   // this thread's float4 column group
+  double cs[4] = {0.0, 0.0, 0.0, 0.0};
+  if (active && cgi < c4n) {
+    const int64_t c0 = cgi * 4;
+    for (int64_t p = pb * rb + rsub; p < pe; p += rows_per_pass) {
+      float s[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < nsplit; ++k) {
+        const float* src = part + (int64_t)k * part_stride + p * ldo + c0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (c0 + e < C) s[e] += src[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (c0 + e < C) {
+          if (out) out[p * ldo + c0 + e] = s[e];
+          const double d = s[e];
+          cs[e] = fma(d, d, cs[e]);
+        }
+      }
+    }
   }
-  if (colsq_part) colsq_part[pb * C + c] = cs;
+  if (!colsq_part) return;
+  // combine the rows_per_pass partial sums of each column group in a fixed order
+  __shared__ double acc[256][4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) acc[tid][e] = cs[e];
+  __syncthreads();
+  if (rsub == 0 && cgi < c4n) {
+    double tsum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < rows_per_pass; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tsum[e] += acc[r * lanes_per_row + cl][e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (cgi * 4 + e < C) colsq_part[pb * C + cgi * 4 + e] = tsum[e];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int64_t n, double* out) {
@@ -302,7 +361,10 @@ __global__ __launch_bounds__(256) void k_sumsq_matrix(const float* A, int64_t ld
 
 }  // namespace
 
-GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wgs) {
+GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int slots) {
+  // slots: workgroups the device runs at once.  The split of R is chosen so
+  // that the grid fills whole rounds of slots (the last round nearly full),
+  // with at least 256 of R per split.
   GemmPlan pl;
   pl.pblocks = (int)((P + BP - 1) / BP);
   const int64_t cb = (C + 127) / 128;
@@ -311,14 +373,24 @@ GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wg
   pl.nt = (int)((cpb + 15) / 16);
   if (pl.nt < 1) pl.nt = 1;
   const int64_t base = (int64_t)pl.pblocks * pl.cblocks;
-  int64_t ns = (target_wgs + base - 1) / base;
-  const int64_t max_by_depth = std::max<int64_t>(1, R / 512);   // keep >= 512 of R per split
-  ns = std::min<int64_t>(ns, max_by_depth);
-  ns = std::min<int64_t>(ns, max_split);
-  if (ns < 1) ns = 1;
-  int64_t rs = (R + ns - 1) / ns;
+  const int64_t max_by_depth = std::max<int64_t>(1, R / 256);
+  const int64_t hi = std::max<int64_t>(1, std::min<int64_t>(max_split, max_by_depth));
+  int64_t best_ns = 1;
+  double best_eff = -1.0;
+  for (int64_t ns = 1; ns <= hi; ++ns) {
+    const int64_t tot = base * ns;
+    const int64_t rounds = (tot + slots - 1) / slots;
+    // efficiency of the last-round fill, discounted when the grid is tiny
+    double eff = (double)tot / (double)(rounds * slots);
+    if (tot < slots) eff = (double)tot / (double)slots;
+    if (eff > best_eff + 0.02) {
+      best_eff = eff;
+      best_ns = ns;
+    }
+  }
+  int64_t rs = (R + best_ns - 1) / best_ns;
   rs = ((rs + BK - 1) / BK) * BK;
-  ns = (R + rs - 1) / rs;
+  int64_t ns = (R + rs - 1) / rs;
   if (ns < 1) ns = 1;
   pl.nsplit = (int)ns;
   pl.rsplit = rs > 0 ? rs : BK;
@@ -356,7 +428,8 @@ hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const Gem
 hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit, float* out,
                                 int64_t ldo, int64_t P, int64_t C, double* colsq_part,
                                 int rows_per_block, hipStream_t s) {
-  dim3 grid((unsigned)((P + rows_per_block - 1) / rows_per_block), (unsigned)((C + 255) / 256));
+  dim3 grid((unsigned)((P + rows_per_block - 1) / rows_per_block),
+            (unsigned)(((C + 3) / 4 + 63) / 64));
   hipLaunchKernelGGL(k_splitk_reduce, grid, dim3(256), 0, s, part, part_stride, nsplit, out, ldo,
                      P, C, colsq_part, rows_per_block);
   return hipGetLastError();

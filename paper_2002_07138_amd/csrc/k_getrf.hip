@@ -130,20 +130,81 @@ __device__ __forceinline__ Cand wave_reduce(Cand c) {
   return c;
 }
 
-template <int NB, int RPT>
-__global__ __launch_bounds__(256) void k_getrf_panel(PanelArgs a) {
+// Wave-wide maxima: rotations inside each row of 16 lanes (DPP), then the
+// two cross-row exchanges.
+template <int R>
+__device__ __forceinline__ uint32_t dpp_ror(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + R, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+
+template <int R>
+__device__ __forceinline__ unsigned long long dpp_ror64(unsigned long long v) {
+  const uint32_t lo = dpp_ror<R>((uint32_t)v), hi = dpp_ror<R>((uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  v = umax64(v, dpp_ror64<1>(v));
+  v = umax64(v, dpp_ror64<2>(v));
+  v = umax64(v, dpp_ror64<4>(v));
+  v = umax64(v, dpp_ror64<8>(v));
+  v = umax64(v, __shfl_xor(v, 16, 64));
+  v = umax64(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_max_f32(float v) {
+  v = fmaxf(v, __uint_as_float(dpp_ror<1>(__float_as_uint(v))));
+  v = fmaxf(v, __uint_as_float(dpp_ror<2>(__float_as_uint(v))));
+  v = fmaxf(v, __uint_as_float(dpp_ror<4>(__float_as_uint(v))));
+  v = fmaxf(v, __uint_as_float(dpp_ror<8>(__float_as_uint(v))));
+  v = fmaxf(v, __shfl_xor(v, 16, 64));
+  v = fmaxf(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
+// One cooperative grid factors a panel of up to NB columns.  A workgroup of
+// NWAVE waves owns NWAVE*64*RPT consecutive rows; each lane keeps a window of
+// NB panel columns of its RPT rows in VGPRs.  Steps are processed in groups
+// of S (unrolled, so the window is indexed at compile time); after each
+// group the window shifts left by S columns, which keeps the code small
+// enough for the instruction cache.  Multipliers and the pivot row's U
+// entries are stored to F as soon as they are final.
+//
+// Pivot step: (1) each wave finds its best candidate (DPP max of the 64-bit
+// key |value|, position), the workgroup combines them in LDS; (2) the owner
+// of the workgroup's candidate publishes one message: header (value, row,
+// position, runner-up) and the candidate's window entries to the right of
+// the pivot column; (3) the waves of every workgroup share the polling of all
+// messages into LDS; (4) every wave picks the same winner and updates.
+template <int NB, int RPT, int NWAVE, int S>
+__global__ __launch_bounds__(64 * NWAVE) void k_getrf_panel(PanelArgs a) {
+  constexpr int MAXG = 64;                 // message slots (workgroups) at most
   const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  const int G = gridDim.x;
+  const int wg = blockIdx.x;
   const uint64_t t0 = wall_clock64();
 
+  __shared__ unsigned long long wck[NWAVE];            // wave best keys
+  __shared__ float wcs[NWAVE];                         // wave runner-up |value|
+  __shared__ uint32_t hdr[MAXG][MSGH];                 // polled headers
+  __shared__ __attribute__((aligned(16))) float dat[MAXG][NB];   // polled windows
+  __shared__ __attribute__((aligned(16))) float rowbuf[NWAVE][NB];
+  __shared__ int flag_abort;
+
   float x[RPT][NB];
-  bool act[RPT], live0[RPT];
-  int rpos[RPT], pstep[RPT];
-  int rowid[RPT];
+  bool act[RPT];
+  int rpos[RPT], pstep[RPT], rowid[RPT];
+  const int64_t wave_base = ((int64_t)wg * NWAVE + wv) * RPT * 64;
 
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t r = ((int64_t)gw * RPT + q) * 64 + lane;
+    const int64_t r = wave_base + q * 64 + lane;
     rowid[q] = (int)r;
     act[q] = false;
     rpos[q] = INT_MAX;
@@ -169,171 +230,258 @@ __global__ __launch_bounds__(256) void k_getrf_panel(PanelArgs a) {
         }
       }
     }
-    live0[q] = act[q];
   }
-
-  auto slot = [&](int J, int w) __attribute__((always_inline)) -> unsigned long long* {
-    return a.msg + ((size_t)(J & 1) * a.nwaves + w) * a.msgw;
-  };
-
-  // Local best over this wave's rows for column j (compile-time j).
-  auto local_cand = [&](auto jc) __attribute__((always_inline)) -> Cand {
-    constexpr int j = decltype(jc)::value;
-    Cand c{0ull, -1, 0.f, -1, -1.f};
+  const bool live_any = act[0] || (RPT > 1 && act[RPT - 1]);
+  (void)live_any;
+  bool live0[RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      if (act[q]) {
-        Cand y{cand_key(fabsf(x[q][j]), rpos[q]), rowid[q], x[q][j], q, -1.f};
-        merge(c, y);
-      }
-    }
-    return c;
+  for (int q = 0; q < RPT; ++q) live0[q] = act[q];
+  if (threadIdx.x == 0) flag_abort = 0;
+  __syncthreads();
+
+  auto slot = [&](int J, int g) __attribute__((always_inline)) -> unsigned long long* {
+    return a.msg + ((size_t)(J & 1) * G + g) * a.msgw;
   };
 
   bool ok = true;
-  // Publishes the header of this wave's candidate for step J and returns the
-  // wave-level winner (for the later data publication).
-  auto publish_header = [&](const Cand& wb, int J) __attribute__((always_inline)) {
-    const uint32_t tag = a.tagbase + (uint32_t)J + 1u;
-    unsigned long long* s = slot(J, gw);
-    if (lane < MSGH) {
-      uint32_t payload = 0;
-      if (lane == 0) payload = __float_as_uint(wb.sv);
-      if (lane == 1) payload = (uint32_t)wb.row;
-      if (lane == 2) payload = 0xFFFFFFFFu - (uint32_t)wb.key;   // candidate's position
-      if (lane == 3) payload = __float_as_uint(wb.sec);
-      st_word(s + lane, payload, tag);
-    }
-  };
+  uint32_t lmask[RPT];      // window columns of the current group that hold multipliers
 
-  // Publishes the trailing entries (columns > j) of the wave's candidate row.
-  auto publish_data = [&](auto jc, const Cand& wb, int J) __attribute__((always_inline)) {
-    constexpr int j = decltype(jc)::value;
-    const uint32_t tag = a.tagbase + (uint32_t)J + 1u;
-    unsigned long long* s = slot(J, gw) + MSGH;
-    const int owner = wb.row >= 0 ? (int)(wb.row - (((int64_t)gw * RPT + wb.src) * 64)) : 0;
-    const int qsel = wb.row >= 0 ? wb.src : 0;
-    float mine = 0.f;
-#pragma unroll
-    for (int jj = j + 1; jj < NB; ++jj) {
-      float t = x[0][jj];
-#pragma unroll
-      for (int q = 1; q < RPT; ++q) t = (qsel == q) ? x[q][jj] : t;
-      const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), owner));
-      mine = (lane == jj) ? v : mine;
-    }
-    if (lane > j && lane < NB) st_word(s + lane, __float_as_uint(mine), tag);
-  };
-
-  // step 0 candidate
-  {
-    Cand wb = wave_reduce(local_cand(std::integral_constant<int, 0>{}));
-    publish_header(wb, a.jb);
-    publish_data(std::integral_constant<int, 0>{}, wb, a.jb);
-  }
-
-  auto step = [&](auto jc) __attribute__((always_inline)) {
-    constexpr int j = decltype(jc)::value;
-    if (!ok || j >= a.nbw) return;
+  // one pivot step on window column s (compile time); jcur = window origin
+  auto step = [&](auto sc, int jcur) __attribute__((always_inline)) {
+    constexpr int s = decltype(sc)::value;
+    const int j = jcur + s;
     const int J = a.jb + j;
     const uint32_t tag = a.tagbase + (uint32_t)J + 1u;
-    // ---- gather every wave's candidate header and agree on the winner
-    Cand best{0ull, -1, 0.f, -1, -1.f};
-    for (int w = lane; w < a.nwaves; w += 64) {
-      unsigned long long* s = slot(J, w);
-      uint32_t h0, h1, h2, h3;
-      if (!wait_word(s + 0, tag, h0, a.abortf, t0, a.timeout_ticks) ||
-          !wait_word(s + 1, tag, h1, a.abortf, t0, a.timeout_ticks) ||
-          !wait_word(s + 2, tag, h2, a.abortf, t0, a.timeout_ticks) ||
-          !wait_word(s + 3, tag, h3, a.abortf, t0, a.timeout_ticks)) {
-        ok = false;
-        break;
+    // ---- (1) candidates
+    unsigned long long mykey = 0ull;
+    int myq = 0;
+    float mysec = -1.f;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (act[q]) {
+        const float av = fabsf(x[q][s]);
+        const unsigned long long k = cand_key(av, rpos[q]);
+        if (k > mykey) {
+          mysec = fmaxf(mysec, key_abs(mykey));
+          mykey = k;
+          myq = q;
+        } else {
+          mysec = fmaxf(mysec, av);
+        }
       }
-      const int row = (int)h1;
+    }
+    const unsigned long long wk = wave_max_u64(mykey);
+    const unsigned long long bal = __ballot(wk != 0ull && mykey == wk);
+    const int wl = bal ? (int)__ffsll((long long)bal) - 1 : 0;
+    const float wsec = wave_max_f32((lane == wl) ? mysec : key_abs(mykey));
+    const int wq = __builtin_amdgcn_readlane(myq, wl);
+    if (lane == 0) {
+      wck[wv] = wk;
+      wcs[wv] = wsec;
+    }
+    __syncthreads();
+    unsigned long long bk = 0ull;
+    int bw = 0;
+#pragma unroll
+    for (int v = 0; v < NWAVE; ++v) {
+      const unsigned long long k = wck[v];
+      if (k > bk) {
+        bk = k;
+        bw = v;
+      }
+    }
+    float bsec = -1.f;
+#pragma unroll
+    for (int v = 0; v < NWAVE; ++v) bsec = fmaxf(bsec, (v == bw) ? wcs[v] : key_abs(wck[v]));
+    // ---- (2) publish the workgroup's candidate
+    if (bk != 0ull && wv == bw) {
+      if (lane == wl) {
+#pragma unroll
+        for (int jj = 0; jj < NB; jj += 4) {
+          f32x4 v4;
+          v4.x = x[0][jj]; v4.y = x[0][jj + 1]; v4.z = x[0][jj + 2]; v4.w = x[0][jj + 3];
+#pragma unroll
+          for (int q = 1; q < RPT; ++q) {
+            if (wq == q) {
+              v4.x = x[q][jj]; v4.y = x[q][jj + 1]; v4.z = x[q][jj + 2]; v4.w = x[q][jj + 3];
+            }
+          }
+          *reinterpret_cast<f32x4*>(&rowbuf[wv][jj]) = v4;
+        }
+      }
+      unsigned long long* sl = slot(J, wg);
+      const float mine = rowbuf[wv][lane < NB ? lane : 0];
+      if (lane > s && lane < NB) st_word(sl + MSGH + lane, __float_as_uint(mine), tag);
+      if (lane < MSGH) {
+        uint32_t pl = 0;
+        if (lane == 0) pl = __float_as_uint(rowbuf[wv][s]);
+        if (lane == 1) pl = (uint32_t)(wave_base + wq * 64 + wl);
+        if (lane == 2) pl = 0xFFFFFFFFu - (uint32_t)bk;
+        if (lane == 3) pl = __float_as_uint(bsec);
+        st_word(sl + lane, pl, tag);
+      }
+    } else if (bk == 0ull && wv == 0) {
+      unsigned long long* sl = slot(J, wg);          // no candidate in this workgroup
+      if (lane < MSGH) st_word(sl + lane, lane == 1 ? 0xFFFFFFFFu : 0u, tag);
+      if (lane > s && lane < NB) st_word(sl + MSGH + lane, 0u, tag);
+    }
+    // ---- (3) poll the messages of workgroups wv, wv+NWAVE, ... into LDS;
+    // all of a wave's slots are in flight together
+    {
+      constexpr int TS = MAXG / NWAVE;
+      uint32_t pend_h = 0, pend_d = 0;
+#pragma unroll
+      for (int t = 0; t < TS; ++t) {
+        if (wv + NWAVE * t < G) {
+          if (lane < MSGH) pend_h |= 1u << t;
+          if (lane > s && lane < NB) pend_d |= 1u << t;
+        }
+      }
+      int it = 0;
+      while (true) {
+        unsigned long long vh[TS], vd[TS];
+#pragma unroll
+        for (int t = 0; t < TS; ++t) {
+          unsigned long long* sl = slot(J, wv + NWAVE * t);
+          if (pend_h & (1u << t)) vh[t] = ld_word(sl + lane);
+          if (pend_d & (1u << t)) vd[t] = ld_word(sl + MSGH + lane);
+        }
+#pragma unroll
+        for (int t = 0; t < TS; ++t) {
+          const int g = wv + NWAVE * t;
+          if ((pend_h & (1u << t)) && (uint32_t)(vh[t] >> 32) == tag) {
+            hdr[g][lane] = (uint32_t)vh[t];
+            pend_h &= ~(1u << t);
+          }
+          if ((pend_d & (1u << t)) && (uint32_t)(vd[t] >> 32) == tag) {
+            dat[g][lane] = __uint_as_float((uint32_t)vd[t]);
+            pend_d &= ~(1u << t);
+          }
+        }
+        if (__all((pend_h | pend_d) == 0u)) break;
+        if ((++it & 63) == 0) {
+          bool stop = false;
+          if (wall_clock64() - t0 > a.timeout_ticks) {
+            __hip_atomic_store(a.abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            stop = true;
+          } else if (__hip_atomic_load(a.abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            stop = true;
+          }
+          if (__any(stop)) {
+            if (lane == 0) flag_abort = 1;
+            break;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (flag_abort) {
+      ok = false;
+      return;
+    }
+    // ---- (4) every wave agrees on the winner
+    unsigned long long gkey = 0ull;
+    float gabs = -1.f, gsec = -1.f;
+    if (lane < G) {
+      const int row = (int)hdr[lane][1];
       if (row >= 0) {
-        const float sv = __uint_as_float(h0);
-        Cand y{cand_key(fabsf(sv), (int)h2), row, sv, w, __uint_as_float(h3)};
-        merge(best, y);
+        gabs = fabsf(__uint_as_float(hdr[lane][0]));
+        gkey = cand_key(gabs, (int)hdr[lane][2]);
+        gsec = __uint_as_float(hdr[lane][3]);
       }
     }
-    ok = __all(ok);
-    if (!ok) return;
-    best = wave_reduce(best);
-    // ---- the winner's trailing entries: lane jj (j < jj < NB) holds u[jj]
-    float uv = 0.f;
-    bool dok = true;
-    if (lane > j && lane < NB && best.row >= 0) {
-      uint32_t w;
-      dok = wait_word(slot(J, best.src) + MSGH + lane, tag, w, a.abortf, t0, a.timeout_ticks);
-      uv = __uint_as_float(w);
-    }
-    ok = __all(dok);
-    if (!ok) return;
-    const float piv = best.sv;
-    const float aw = key_abs(best.key);
-    const int wpos = (int)(0xFFFFFFFFu - (uint32_t)best.key);
-    if (gw == 0 && lane == 0) {
-      a.piv_row[J] = best.row;
-      const float sec = best.sec > 0.f ? best.sec : 0.f;
+    const unsigned long long best = wave_max_u64(gkey);
+    const unsigned long long gb = __ballot(best != 0ull && gkey == best);
+    const int gs = gb ? (int)__ffsll((long long)gb) - 1 : 0;
+    const float runner = wave_max_f32((lane == gs) ? gsec : gabs);
+    const float piv = __uint_as_float(hdr[gs][0]);
+    const int prow = (best != 0ull) ? (int)hdr[gs][1] : -1;
+    const float aw = key_abs(best);
+    const int wpos = (int)(0xFFFFFFFFu - (uint32_t)best);
+    if (wg == 0 && wv == 0 && lane == 0) {
+      a.piv_row[J] = prow;
+      const float sec = runner > 0.f ? runner : 0.f;
       a.gaps[J] = aw > 0.f ? (aw - sec) / aw : 0.f;
       if (!(aw > 0.f)) atomicMin(a.zstep, J);
     }
+    // the pivot row's U entries (its window was staged in rowbuf by its wave)
+    if (prow >= wave_base && prow < wave_base + RPT * 64) {
+      if (lane >= s && lane < NB && jcur + lane < a.nbw)
+        a.F[(int64_t)prow * a.ldf + a.jb + jcur + lane] = rowbuf[wv][lane];
+    }
     const float rinv = (piv != 0.f) ? 1.0f / piv : 0.f;
-    // ---- bookkeeping and multipliers; update column j+1 first
-    float lmul[RPT];
+    float lm[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      lmul[q] = 0.f;
+      lm[q] = 0.f;
       if (act[q]) {
-        if (rowid[q] == best.row) {
+        if (rowid[q] == prow) {
           act[q] = false;
           pstep[q] = J;
           rpos[q] = J;
         } else {
           if (rpos[q] == J) rpos[q] = wpos;
-          const float l = (piv != 0.f) ? x[q][j] * rinv : x[q][j];
-          x[q][j] = l;
-          lmul[q] = l;
+          const float l = (piv != 0.f) ? x[q][s] * rinv : x[q][s];
+          x[q][s] = l;
+          lm[q] = l;
+          lmask[q] |= 1u << s;
         }
       }
     }
-    if constexpr (j + 1 < NB) {
-      const float u1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uv), j + 1));
+    const float* ug = &dat[gs][0];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (act[q]) x[q][j + 1] = fmaf(-lmul[q], u1, x[q][j + 1]);
-      // ---- next step's candidate header goes out before the rest of the update
-      Cand wb{0ull, -1, 0.f, -1, -1.f};
-      const bool more = (j + 1 < a.nbw);
-      if (more) {
-        wb = wave_reduce(local_cand(std::integral_constant<int, j + 1>{}));
-        publish_header(wb, J + 1);
+    for (int j4 = (s + 1) / 4; j4 < NB / 4; ++j4) {
+      const f32x4 u4 = *reinterpret_cast<const f32x4*>(ug + 4 * j4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int jj = 4 * j4 + e;
+        if (jj > s) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q)
+            if (act[q]) x[q][jj] = fmaf(-lm[q], u4[e], x[q][jj]);
+        }
       }
-#pragma unroll
-      for (int jj = j + 2; jj < NB; ++jj) {
-        const float u = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uv), jj));
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (act[q]) x[q][jj] = fmaf(-lmul[q], u, x[q][jj]);
-      }
-      if (more) publish_data(std::integral_constant<int, j + 1>{}, wb, J + 1);
     }
   };
 
-  [&]<int... Js>(std::integer_sequence<int, Js...>) __attribute__((always_inline)) {
-    (step(std::integral_constant<int, Js>{}), ...);
-  }(std::make_integer_sequence<int, NB>{});
+  for (int jcur = 0; jcur < a.nbw; jcur += S) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) lmask[q] = 0u;
+    [&]<int... Ss>(std::integer_sequence<int, Ss...>) __attribute__((always_inline)) {
+      ((ok && jcur + Ss < a.nbw ? step(std::integral_constant<int, Ss>{}, jcur) : void()), ...);
+    }(std::make_integer_sequence<int, S>{});
+    if (!ok) break;
+    // the group's multipliers, one store batch per row
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (lmask[q]) {
+        float* dst = a.F + (int64_t)rowid[q] * a.ldf + a.jb + jcur;
+        if (S == 4 && lmask[q] == 0xFu && (reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
+          f32x4 v4;
+          v4.x = x[q][0]; v4.y = x[q][1]; v4.z = x[q][2]; v4.w = x[q][3];
+          *reinterpret_cast<f32x4*>(dst) = v4;
+        } else {
+#pragma unroll
+          for (int e = 0; e < S; ++e)
+            if (lmask[q] & (1u << e)) dst[e] = x[q][e];
+        }
+      }
+    }
+    // shift the window left by S columns
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+#pragma unroll
+      for (int jj = 0; jj < NB - S; ++jj) x[q][jj] = x[q][jj + S];
+#pragma unroll
+      for (int jj = NB - S; jj < NB; ++jj) x[q][jj] = 0.f;
+    }
+  }
 
   if (!ok) return;
-  // ---- write back this panel's columns and the row bookkeeping
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int64_t r = rowid[q];
     if (r < a.M && live0[q]) {
-      float* dst = a.F + r * a.ldf + a.jb;
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
-        if (jj < a.nbw) dst[jj] = x[q][jj];
       a.pos[r] = rpos[q];
       if (pstep[q] >= 0) a.piv_step[r] = pstep[q];
     }
@@ -350,7 +498,8 @@ struct TrsmArgs {
 };
 
 // U12 = L11^{-1} F[pivot rows of the panel, right columns]; written back into
-// the pivot rows and into a compact nbw x (c - jb - nbw) buffer.
+// the pivot rows and into a compact nbw x (c - jb - nbw) buffer.  The block's
+// 64 right-hand columns are staged in LDS first, then solved in place.
 __global__ __launch_bounds__(64) void k_getrf_trsm(TrsmArgs a) {
   __shared__ float L11[64][65];
   __shared__ float us[64][65];
@@ -358,17 +507,23 @@ __global__ __launch_bounds__(64) void k_getrf_trsm(TrsmArgs a) {
   const int t = threadIdx.x;
   if (t < a.nbw) rows[t] = a.piv_row[a.jb + t];
   __syncthreads();
-  for (int s = 0; s < a.nbw; ++s) {
-    L11[s][t] = (t < s) ? a.F[(int64_t)rows[s] * a.ldf + a.jb + t] : 0.f;
-  }
-  __syncthreads();
   const int cs = a.jb + a.nbw;
   const int64_t cc = (int64_t)cs + (int64_t)blockIdx.x * 64 + t;
-  if (cc >= a.c) return;
+  const bool col_ok = cc < a.c;
   for (int s = 0; s < a.nbw; ++s) {
-    float v = a.F[(int64_t)rows[s] * a.ldf + cc];
+    const float* row = a.F + (int64_t)rows[s] * a.ldf;
+    L11[s][t] = (t < s) ? row[a.jb + t] : 0.f;
+    us[s][t] = col_ok ? row[cc] : 0.f;
+  }
+  __syncthreads();
+  if (!col_ok) return;
+  for (int s = 0; s < a.nbw; ++s) {
+    float v = us[s][t];
     for (int k = 0; k < s; ++k) v = fmaf(-L11[s][k], us[k][t], v);
     us[s][t] = v;
+  }
+  for (int s = 0; s < a.nbw; ++s) {
+    const float v = us[s][t];
     a.F[(int64_t)rows[s] * a.ldf + cc] = v;
     a.u12[(int64_t)s * a.ldu12 + (cc - cs)] = v;
   }
@@ -412,19 +567,20 @@ __global__ __launch_bounds__(256) void k_getrf_finalize(float* F, int64_t ldf, i
   if (t == 0 && perm) perm[pos[i]] = (int32_t)i;
 }
 
-template <int NB, int RPT>
+template <int NB, int RPT, int NWAVE, int S>
 hipError_t launch_panel(const PanelArgs& pa, int nblocks, hipStream_t s) {
   void* args[] = {const_cast<PanelArgs*>(&pa)};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_getrf_panel<NB, RPT>),
-                                    dim3(nblocks), dim3(256), args, 0, s);
+  return hipLaunchCooperativeKernel(
+      reinterpret_cast<const void*>(&k_getrf_panel<NB, RPT, NWAVE, S>), dim3(nblocks),
+      dim3(64 * NWAVE), args, 0, s);
 }
 
 }  // namespace
 
 size_t getrf_msg_words(int64_t M) {
-  // worst case: RPT = 1 rows per lane -> one wave per 64 rows, rounded to 4 waves
-  const int64_t waves = ((M + 255) / 256) * 4;
-  return (size_t)2 * waves * (MSGH + 64);
+  // one message slot per panel workgroup (at most 64), two parities
+  (void)M;
+  return (size_t)2 * 64 * (MSGH + 64);
 }
 
 hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w, int32_t* perm,
@@ -434,12 +590,13 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
   hipLaunchKernelGGL(k_getrf_init, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, w.piv_step,
                      w.pos, M, w.zstep);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  constexpr int NB = 64, RPT = 2;
-  const int64_t waves = (M + 64 * RPT - 1) / (64 * RPT);
-  const int nblocks = (int)((waves + 3) / 4);
-  if ((int64_t)nblocks * 4 > w.max_waves) return hipErrorInvalidValue;
-  const int nw = nblocks * 4;
-  if ((size_t)2 * nw * (MSGH + NB) > w.msg_words) return hipErrorInvalidValue;
+  constexpr int NB = 64, NWAVE = 8, S = 4;
+  // one row per lane while 64 workgroups of 512 rows suffice, else two
+  const int rpt = (M <= 64LL * NWAVE * 64) ? 1 : 2;
+  const int64_t rows_per_wg = (int64_t)NWAVE * 64 * rpt;
+  const int nblocks = (int)((M + rows_per_wg - 1) / rows_per_wg);
+  if (nblocks > 64 || (int64_t)nblocks * NWAVE > w.max_waves) return hipErrorInvalidValue;
+  if ((size_t)2 * nblocks * (MSGH + NB) > w.msg_words) return hipErrorInvalidValue;
   for (int jb = 0; jb < c; jb += NB) {
     PanelArgs pa;
     pa.F = F; pa.ldf = ldf; pa.M = M; pa.jb = jb; pa.nbw = (c - jb < NB) ? c - jb : NB;
@@ -452,10 +609,11 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
         return e;
     }
     pa.tagbase = (seq % 500000u) * 8192u;
-    pa.nwaves = nw;
+    pa.nwaves = nblocks;
     pa.msgw = MSGH + NB;
     pa.timeout_ticks = w.timeout_ticks;
-    e = launch_panel<NB, RPT>(pa, nblocks, s);
+    e = (rpt == 1) ? launch_panel<NB, 1, NWAVE, S>(pa, nblocks, s)
+                   : launch_panel<NB, 2, NWAVE, S>(pa, nblocks, s);
     if (e != hipSuccess) return e;
     const int cs = jb + pa.nbw;
     if (cs < c) {

@@ -75,92 +75,108 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int nch
   W[e] = s;
 }
 
-// Cholesky W = L L^T (float64, in LDS), L^{-1} in place, R^{-1} = (L^{-1})^T
-// written as float32 (upper triangular, bw x bw, leading dimension ldr).
+// Cholesky W = L L^T and X = L^{-1} in float64, both in one LDS tile: L in
+// the lower triangle (S[i][t], t <= i) and X transposed in the upper part
+// (X[i][c] at S[c][i+1], c <= i).  R^{-1} = X^T is written as float32
+// (upper triangular, bw x bw, leading dimension ldr) and, when Rinv64 is set,
+// as float64.  The column being eliminated is copied to its own array so the
+// trailing update reads and writes different LDS objects.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* W, int bw, float* Rinv, int64_t ldr,
                                                  double* Rinv64, int32_t* status) {
   __shared__ double S[QB][QB + 1];
-  __shared__ double tmp[QB];
+  __shared__ double cj[QB];
   const int t = threadIdx.x;
-  for (int e = t; e < bw * bw; e += 256) S[e / bw][e % bw] = W[e];
+  const int tx = t & 15, ty = t >> 4;
+  for (int r = ty; r < bw; r += 16)
+    for (int c = tx; c <= r; c += 16) S[r][c] = W[r * bw + c];
   __syncthreads();
+  // right-looking Cholesky, two barriers per column
   for (int j = 0; j < bw; ++j) {
-    if (t == 0) {
-      double d = S[j][j];
-      if (!(d > 0.0)) {
-        status[2] = 1;
-        d = DBL_MIN;
-      }
-      S[j][j] = sqrt(d);
+    double d = S[j][j];
+    if (!(d > 0.0)) {
+      if (t == 0) status[2] = 1;
+      d = DBL_MIN;
     }
-    __syncthreads();
-    const double piv = S[j][j];
-    for (int i = j + 1 + t; i < bw; i += 256) S[i][j] /= piv;
-    __syncthreads();
-    const int n = bw - j - 1;
-    for (int e = t; e < n * n; e += 256) {
-      const int i = j + 1 + e / n, c = j + 1 + e % n;
-      if (c <= i) S[i][c] -= S[i][j] * S[c][j];
-    }
-    __syncthreads();
-  }
-  // in-place inverse of the lower factor, last column first
-  for (int j = bw - 1; j >= 0; --j) {
-    const double ljj = S[j][j];
+    const double sd = sqrt(d);
+    const double rp = 1.0 / sd;
     for (int i = j + 1 + t; i < bw; i += 256) {
-      double acc = 0.0;
-      for (int c = j + 1; c <= i; ++c) acc = fma(S[i][c], S[c][j], acc);
-      tmp[i] = -acc / ljj;
+      const double v = S[i][j] * rp;
+      cj[i] = v;
+      S[i][j] = v;
     }
     __syncthreads();
-    for (int i = j + 1 + t; i < bw; i += 256) S[i][j] = tmp[i];
-    if (t == 0) S[j][j] = 1.0 / ljj;
+    if (t == 0) S[j][j] = sd;
+    for (int i = j + 1 + ty; i < bw; i += 16) {
+      const double lij = cj[i];
+      for (int c = j + 1 + tx; c <= i; c += 16) S[i][c] = fma(-lij, cj[c], S[i][c]);
+    }
     __syncthreads();
   }
-  for (int e = t; e < bw * bw; e += 256) {
-    const int r = e / bw, c = e % bw;   // Rinv[r][c] = Linv[c][r] for r <= c
-    const double v = (r <= c) ? S[c][r] : 0.0;
-    Rinv[(int64_t)r * ldr + c] = (float)v;
-    if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v;
+  // X = L^{-1} row by row: X[i][c] = (delta_ic - sum_{c<=q<i} L[i][q] X[q][c]) / L[i][i]
+  for (int i = 0; i < bw; ++i) {
+    const double rl = 1.0 / S[i][i];
+    for (int c = t; c <= i; c += 256) {
+      double acc = (c == i) ? 1.0 : 0.0;
+      for (int q = c; q < i; ++q) acc = fma(-S[i][q], S[c][q + 1], acc);
+      S[c][i + 1] = acc * rl;
+    }
+    __syncthreads();
+  }
+  for (int r = ty; r < bw; r += 16) {
+    for (int c = tx; c < bw; c += 16) {   // Rinv[r][c] = X[c][r] = S[r][c+1] for r <= c
+      const double v = (r <= c) ? S[r][c + 1] : 0.0;
+      Rinv[(int64_t)r * ldr + c] = (float)v;
+      if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v;
+    }
   }
 }
 
 // dst = src R^{-1} with float64 products and sums, rounded once to float32.
-// A wave owns 64 rows and one of four interleaved column groups; R^{-1}
-// (upper triangular, zeros below) is read with wave-uniform addresses.
-template <int CPT>
-__global__ __launch_bounds__(256) void k_apply_rinv64(const float* __restrict__ src, int64_t lds,
+// R^{-1} (upper triangular, bw x bw <= 128 x 128) is staged in LDS as float32
+// with its diagonal kept in float64 (in the last CholeskyQR round R is close
+// to I, so the off-diagonal entries are tiny and their float32 rounding is a
+// second-order effect); each thread owns one row and 16 interleaved columns
+// of a block of 64 rows.
+constexpr int APPLY_ROWS = 64;
+constexpr size_t APPLY_LDS = (size_t)QB * QB * sizeof(float) + QB * sizeof(double) +
+                             (size_t)APPLY_ROWS * (QB + 1) * sizeof(float);
+
+__global__ __launch_bounds__(512) void k_apply_rinv64(const float* __restrict__ src, int64_t lds,
                                                      int64_t M, int bw,
                                                      const double* __restrict__ rinv,
                                                      int64_t ldr, float* dst, int64_t ldd) {
-  __shared__ float Vs[64][QB + 1];
+  extern __shared__ double smem[];
+  double* Dg = smem;                                           // [QB] diagonal, float64
+  float* R = reinterpret_cast<float*>(smem + QB);              // [QB][QB]
+  float* Vs = R + QB * QB;                                     // [APPLY_ROWS][QB+1]
   const int t = threadIdx.x;
-  const int lane = t & 63, cg = t >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int e = t; e < 64 * bw; e += 256) {
-    const int rr = e / bw, cc = e % bw;
+  for (int r = t >> 5; r < bw; r += 16)
+    for (int c = t & 31; c < QB; c += 32)
+      R[r * QB + c] = (c < bw && c != r) ? (float)rinv[(int64_t)r * ldr + c] : 0.f;
+  if (t < bw) Dg[t] = rinv[(int64_t)t * ldr + t];
+  const int64_t r0 = (int64_t)blockIdx.x * APPLY_ROWS;
+  for (int rr = t >> 5; rr < APPLY_ROWS; rr += 16) {
     const int64_t row = r0 + rr;
-    Vs[rr][cc] = (row < M) ? src[row * lds + cc] : 0.f;
+    for (int c = t & 31; c < bw; c += 32) Vs[rr * (QB + 1) + c] = (row < M) ? src[row * lds + c] : 0.f;
   }
   __syncthreads();
-  double acc[CPT];
+  const int rr = t & 63;          // row within the block
+  const int cg = t >> 6;          // column group: columns cg, cg+8, ...
+  double acc[QB / 8];
 #pragma unroll
-  for (int jj = 0; jj < CPT; ++jj) acc[jj] = 0.0;
+  for (int jj = 0; jj < QB / 8; ++jj) acc[jj] = 0.0;
   for (int tt = 0; tt < bw; ++tt) {
-    const double v = Vs[lane][tt];
-    const double* rr = rinv + (int64_t)tt * ldr + cg;
+    const double v = Vs[rr * (QB + 1) + tt];
+    const float* Rr = R + tt * QB + cg;
 #pragma unroll
-    for (int jj = 0; jj < CPT; ++jj) {
-      const int j = cg + 4 * jj;
-      if (j < bw) acc[jj] = fma(v, rr[4 * jj], acc[jj]);
-    }
+    for (int jj = 0; jj < QB / 8; ++jj) acc[jj] = fma(v, (double)Rr[8 * jj], acc[jj]);
   }
-  const int64_t row = r0 + lane;
+  const int64_t row = r0 + rr;
   if (row < M) {
 #pragma unroll
-    for (int jj = 0; jj < CPT; ++jj) {
-      const int j = cg + 4 * jj;
-      if (j < bw) dst[row * ldd + j] = (float)acc[jj];
+    for (int jj = 0; jj < QB / 8; ++jj) {
+      const int j = cg + 8 * jj;
+      if (j < bw) dst[row * ldd + j] = (float)fma((double)Vs[rr * (QB + 1) + j], Dg[j], acc[jj]);
     }
   }
 }
@@ -185,7 +201,7 @@ hipError_t gemm_any(int mode, int epi, GemmArgs g, const QrWork& qw, hipStream_t
 
 hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float* dst, int64_t ldd,
                         const QrWork& qw, bool fp64_apply, hipStream_t s) {
-  int nchunk = (int)((M + 255) / 256);
+  int nchunk = (int)((M + 63) / 64);
   if (nchunk > qw.max_chunks) nchunk = qw.max_chunks;
   int64_t rpc = (M + nchunk - 1) / nchunk;
   rpc = ((rpc + 63) / 64) * 64;
@@ -200,8 +216,16 @@ hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float*
                      fp64_apply ? qw.rinv64 : nullptr, qw.status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (fp64_apply) {
-    hipLaunchKernelGGL(k_apply_rinv64<QB / 4>, dim3((unsigned)((M + 63) / 64)), dim3(256), 0, s,
-                       src, lds, M, bw, qw.rinv64, (int64_t)QB, dst, ldd);
+    static bool attr_set = false;
+    if (!attr_set) {
+      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_rinv64),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)APPLY_LDS)) !=
+          hipSuccess)
+        return e;
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_apply_rinv64, dim3((unsigned)((M + APPLY_ROWS - 1) / APPLY_ROWS)),
+                       dim3(512), APPLY_LDS, s, src, lds, M, bw, qw.rinv64, (int64_t)QB, dst, ldd);
     return hipGetLastError();
   }
   GemmArgs g;

@@ -40,7 +40,7 @@ struct GemmArgs {
   int avec = 0, xvec = 0;
 };
 
-constexpr int GEMM_BP = 256;
+constexpr int GEMM_BP = 128;   // rows of the kept dimension per pass workgroup (2 tiles per wave)
 constexpr int GEMM_BK = 32;
 
 // Plans the split of R and launches; part must hold nsplit*P*ldo floats when
