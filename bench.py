@@ -99,6 +99,38 @@ def cpu_baseline(A_host, k, p_over, v, seed):
     }
 
 
+def profile_pass(m, n):
+    """Dominant kernel only: 3 passes A X and 3 passes A^T X at the workload
+    shape (A is a seeded Gaussian matrix of the workload size: the kernels do
+    not depend on its values), then 3 copies of 1 GiB (the calibration
+    kernel for the HBM byte counters: 1 GiB read and 1 GiB written each)."""
+    import torch
+    import paper_2002_07138_amd as plu
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    A = torch.randn((m, n), device=dev, generator=g)
+    l = K_RANK + P_OVER
+    X_n = torch.randn((n, l), device=dev, generator=g)
+    X_m = torch.randn((m, l), device=dev, generator=g)
+    out_m = torch.empty((m, l), device=dev)
+    out_n = torch.empty((n, l), device=dev)
+    h = plu.Handle(0)
+    for _ in range(3):
+        h.pass_(A, X_n, trans=False, out=out_m)
+    for _ in range(3):
+        h.pass_(A, X_m, trans=True, out=out_n)
+    src = torch.empty(2 ** 28, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    h.close()
+    print(json.dumps({"profile_pass": True, "m": m, "n": n, "l": l,
+                      "pass_algorithmic_bytes": 4.0 * m * n,
+                      "copy_bytes_each_direction": 4 * 2 ** 28}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +138,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=20000, help="reduced sizes for quick checks")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="run only the pass kernels at the workload shape (3 launches per "
+                         "direction) and a plain 1 GiB copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU design is "
@@ -119,6 +154,9 @@ def main():
 
     w = WORKLOADS[WORKLOAD]
     m = n = args.size
+    if args.profile_pass:
+        profile_pass(m, n)
+        return
     t_gen = time.perf_counter()
     A_host = workload_matrix(w, m, n)
     t_gen = time.perf_counter() - t_gen

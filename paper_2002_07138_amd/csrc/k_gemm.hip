@@ -296,13 +296,35 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
   if (active && cgi < c4n) {
     const int64_t c0 = cgi * 4;
+    const bool v4ok = ((reinterpret_cast<uintptr_t>(part) & 15u) == 0) && ((ldo & 3) == 0) &&
+                      ((part_stride & 3) == 0) && (c0 + 3 < C);
     for (int64_t p = pb * rb + rsub; p < pe; p += rows_per_pass) {
       float s[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int k = 0; k < nsplit; ++k) {
-        const float* src = part + (int64_t)k * part_stride + p * ldo + c0;
+      const float* src0 = part + p * ldo + c0;
+      if (v4ok) {
+        // four splits in flight at a time, summed in split order
+        int k = 0;
+        for (; k + 4 <= nsplit; k += 4) {
+          f32x4 v[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (c0 + e < C) s[e] += src[e];
+          for (int u = 0; u < 4; ++u)
+            v[u] = *reinterpret_cast<const f32x4*>(src0 + (int64_t)(k + u) * part_stride);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            s[0] += v[u].x; s[1] += v[u].y; s[2] += v[u].z; s[3] += v[u].w;
+          }
+        }
+        for (; k < nsplit; ++k) {
+          const f32x4 v = *reinterpret_cast<const f32x4*>(src0 + (int64_t)k * part_stride);
+          s[0] += v.x; s[1] += v.y; s[2] += v.z; s[3] += v.w;
+        }
+      } else {
+        for (int k = 0; k < nsplit; ++k) {
+          const float* src = src0 + (int64_t)k * part_stride;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (c0 + e < C) s[e] += src[e];
+        }
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {

@@ -500,7 +500,7 @@ struct TrsmArgs {
 // U12 = L11^{-1} F[pivot rows of the panel, right columns]; written back into
 // the pivot rows and into a compact nbw x (c - jb - nbw) buffer.  The block's
 // 64 right-hand columns are staged in LDS first, then solved in place.
-__global__ __launch_bounds__(64) void k_getrf_trsm(TrsmArgs a) {
+__global__ __launch_bounds__(256) void k_getrf_trsm(TrsmArgs a) {
   __shared__ float L11[64][65];
   __shared__ float us[64][65];
   __shared__ int rows[64];
@@ -508,15 +508,18 @@ __global__ __launch_bounds__(64) void k_getrf_trsm(TrsmArgs a) {
   if (t < a.nbw) rows[t] = a.piv_row[a.jb + t];
   __syncthreads();
   const int cs = a.jb + a.nbw;
-  const int64_t cc = (int64_t)cs + (int64_t)blockIdx.x * 64 + t;
-  const bool col_ok = cc < a.c;
-  for (int s = 0; s < a.nbw; ++s) {
+  const int64_t cbase = (int64_t)cs + (int64_t)blockIdx.x * 64;
+  // stage L11 and the block's 64 right-hand columns with all 256 threads
+  for (int e = t; e < a.nbw * 64; e += 256) {
+    const int s = e >> 6, col = e & 63;
     const float* row = a.F + (int64_t)rows[s] * a.ldf;
-    L11[s][t] = (t < s) ? row[a.jb + t] : 0.f;
-    us[s][t] = col_ok ? row[cc] : 0.f;
+    L11[s][col] = (col < s) ? row[a.jb + col] : 0.f;
+    us[s][col] = (cbase + col < a.c) ? row[cbase + col] : 0.f;
   }
   __syncthreads();
-  if (!col_ok) return;
+  if (t >= 64) return;
+  const int64_t cc = cbase + t;
+  if (cc >= a.c) return;
   for (int s = 0; s < a.nbw; ++s) {
     float v = us[s][t];
     for (int k = 0; k < s; ++k) v = fmaf(-L11[s][k], us[k][t], v);
@@ -618,7 +621,7 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
     const int cs = jb + pa.nbw;
     if (cs < c) {
       TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12};
-      hipLaunchKernelGGL(k_getrf_trsm, dim3((unsigned)((c - cs + 63) / 64)), dim3(64), 0, s, ta);
+      hipLaunchKernelGGL(k_getrf_trsm, dim3((unsigned)((c - cs + 63) / 64)), dim3(256), 0, s, ta);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       GemmArgs g;
       g.A = F + jb; g.lda = ldf;

@@ -70,9 +70,16 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int nch
                                                     double* W) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= bw * bw) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * bw * bw + e];
-  W[e] = s;
+  // eight independent partial sums keep eight loads in flight; fixed order
+  double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t st = (int64_t)bw * bw;
+  int c = 0;
+  for (; c + 8 <= nchunk; c += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] += part[(int64_t)(c + u) * st + e];
+  }
+  for (int u = 0; c < nchunk; ++c, ++u) s8[u] += part[(int64_t)c * st + e];
+  W[e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
 // Cholesky W = L L^T and X = L^{-1} in float64, both in one LDS tile: L in
@@ -112,13 +119,18 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* W, int bw, float
     }
     __syncthreads();
   }
-  // X = L^{-1} row by row: X[i][c] = (delta_ic - sum_{c<=q<i} L[i][q] X[q][c]) / L[i][i]
-  for (int i = 0; i < bw; ++i) {
-    const double rl = 1.0 / S[i][i];
-    for (int c = t; c <= i; c += 256) {
-      double acc = (c == i) ? 1.0 : 0.0;
-      for (int q = c; q < i; ++q) acc = fma(-S[i][q], S[c][q + 1], acc);
-      S[c][i + 1] = acc * rl;
+  // X = L^{-1} by right-looking forward substitution on X = I: row k of X is
+  // final once divided by L[k][k]; it then updates rows k+1.. in parallel.
+  for (int i = ty; i < bw; i += 16)
+    for (int c = tx; c <= i; c += 16) S[c][i + 1] = (c == i) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = 0; k < bw; ++k) {
+    const double rk = 1.0 / S[k][k];
+    for (int c = t; c <= k; c += 256) S[c][k + 1] *= rk;
+    __syncthreads();
+    for (int i = k + 1 + ty; i < bw; i += 16) {
+      const double lik = S[i][k];
+      for (int c = tx; c <= k; c += 16) S[c][i + 1] = fma(-lik, S[c][k + 1], S[c][i + 1]);
     }
     __syncthreads();
   }
