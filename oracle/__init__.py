@@ -15,6 +15,8 @@ powerlu   GETRF with partial pivoting, the LU reorthogonalization, thin QR,
           the generalized power iteration (Alg. 7), PowerLU (Alg. 5),
           the error indicator and rank rules (Thm 4.3, Alg. 8, Alg. 11),
           PowerLU_FP (Alg. 9) and the relative residual (eq. "error", Sec. 6.2).
+lowp      bfloat16 and block-scaled FP8 E4M3 operand rounding for the
+          precision form of the passes.
 philox    Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
           Box-Muller transform, for the seeded Gaussian test matrix.
 

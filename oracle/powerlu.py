@@ -28,6 +28,10 @@ design notes of the repository):
   R8  When l columns are not enough, the rank-l result is returned with
       ``tol_reached = False`` (the Remark after Alg. 8 suggests a restart; that
       is not part of this oracle).
+  R13 Precision form (not in the paper, which computes in float64): the v - 1
+      passes of Alg. 7 take operands rounded to a narrower format (module
+      ``lowp``) and accumulate exactly; the final product with A, the LU and
+      QR steps and the indicator stay exact.
 
 Pins: see tests/test_oracle_pins.py (GETRF against LAPACK and the textbook
 definition, crafted ties, zero columns; thin QR against exact arithmetic;
@@ -131,7 +135,7 @@ class RangeRecord:
 
 
 def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
-                record: RangeRecord | None = None) -> np.ndarray:
+                record: RangeRecord | None = None, pass_round=None) -> np.ndarray:
     """Alg. 7.  Returns an orthonormal n x l basis V of (A^T A)^P A^T Omega
     (v even, Omega m x l) or (A^T A)^P Omega (v odd, Omega n x l), with
     P = floor((v - 1) / 2).  Makes v - 1 passes over A; the caller's final
@@ -140,6 +144,11 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
     v even: X = A^T Omega, then LU reorth if v > 2 else QR.
     v odd:  V = Omega.
     Loop i = 1..P: V = lur(A V); V = qr(A^T V) if i == P else lur(A^T V).
+
+    pass_round (precision form, reading R13): when given, every one of these
+    v - 1 products takes rounded operands, pass_round(A, axis) and
+    pass_round(X, 0), with axis the contraction axis of A (1 for A X, 0 for
+    A^T X), and is accumulated exactly.  Nothing else is rounded.
     """
     if v < 2:
         raise ValueError("v >= 2 (Alg. 7 REQUIRE)")
@@ -147,10 +156,21 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
     m, n = A.shape
     P = (v - 1) // 2
     rec = record if record is not None else RangeRecord()
+
+    def times(X):          # A X, the products of the loop
+        if pass_round is None:
+            return A @ X
+        return pass_round(A, 1) @ pass_round(X, 0)
+
+    def times_t(X):        # A^T X
+        if pass_round is None:
+            return A.T @ X
+        return pass_round(A, 0).T @ pass_round(X, 0)
+
     if v % 2 == 0:
         if Omega.shape[0] != m:
             raise ValueError("even v needs an m x l Gaussian matrix (reading R3)")
-        X = A.T @ Omega
+        X = times_t(Omega)
         rec.passes += 1
         if v > 2:
             V, f = lur(X)
@@ -162,11 +182,11 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
             raise ValueError("odd v needs an n x l Gaussian matrix")
         V = np.array(Omega, dtype=np.float64, copy=True)
     for i in range(1, P + 1):
-        Y = A @ V
+        Y = times(V)
         rec.passes += 1
         V, f = lur(Y)
         rec.lu_steps.append(f)
-        X = A.T @ V
+        X = times_t(V)
         rec.passes += 1
         if i == P:
             V = thin_qr(X)
@@ -216,16 +236,19 @@ def assemble(A: np.ndarray, Vk: np.ndarray, Y: np.ndarray | None = None) -> Fact
                          lu2=f2, V=Vk, Y=Y, Bt=Bt)
 
 
-def powerlu(A: np.ndarray, k: int, Omega: np.ndarray, v: int) -> Factorization:
+def powerlu(A: np.ndarray, k: int, Omega: np.ndarray, v: int,
+            pass_round=None) -> Factorization:
     """PowerLU (Alg. 5 with Alg. 7 in place of steps 1-2).  Omega is the
-    caller's Gaussian matrix: m x l for even v, n x l for odd v, l = k + q."""
+    caller's Gaussian matrix: m x l for even v, n x l for odd v, l = k + q.
+    pass_round: precision form of the v - 1 range passes (see range_basis);
+    the final product Y = A V_k is always exact."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     l = Omega.shape[1]
     if not (1 <= k <= l < min(m, n)):
         raise ValueError("need 1 <= k <= l < min(m, n)")
     rec = RangeRecord()
-    V = range_basis(A, Omega, v, rec)
+    V = range_basis(A, Omega, v, rec, pass_round)
     fac = assemble(A, V[:, :k])
     fac.passes = rec.passes + 1
     fac.normA2 = float(np.sum(A * A))
@@ -274,9 +297,10 @@ def rank_rule(normA2: float, colnorm2: np.ndarray, eps: float, b: int,
 
 
 def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
-               column_mode: bool = True) -> Factorization:
+               column_mode: bool = True, pass_round=None) -> Factorization:
     """PowerLU_FP (Alg. 9) on top of Alg. 8 (block rule) or Alg. 11 (column
-    rule).  l = Omega.shape[1] must be a multiple of b (Sec. 4.1, l = s b)."""
+    rule).  l = Omega.shape[1] must be a multiple of b (Sec. 4.1, l = s b).
+    pass_round: precision form of the v - 1 range passes; G = A V is exact."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     l = Omega.shape[1]
@@ -284,7 +308,7 @@ def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
         raise ValueError("need b | l and l < min(m, n)")
     normA2 = float(np.sum(A * A))
     rec = RangeRecord()
-    V = range_basis(A, Omega, v, rec)
+    V = range_basis(A, Omega, v, rec, pass_round)
     G = A @ V
     colnorm2 = np.sum(G * G, axis=0)
     E = indicator(normA2, colnorm2)
