@@ -47,6 +47,214 @@ def flops_fixed_rank(m: int, n: int, k: int, l: int, v: int) -> float:
     return f
 
 
+def flops_fixed_precision(m: int, n: int, l: int, k: int, v: int) -> float:
+    """Algorithmic flops of PowerLU_FP (Alg. 9 on Alg. 7): v passes with all
+    l columns (the last is G = A V), the reorthogonalizations on l columns,
+    the indicator (2 m l) and the assembly on the rank k."""
+    lu = lambda r, c: r * c * c - c ** 3 / 3.0
+    qr = lambda r, c: 2.0 * r * c * c - 2.0 * c ** 3 / 3.0
+    f = v * 2.0 * m * n * l + 2.0 * m * l
+    P = (v - 1) // 2
+    f += P * lu(m, l) + ((v - 2) - P) * lu(n, l) + qr(n, l)
+    if k > 0:
+        f += lu(m, k) + 2.0 * n * k * k + lu(n, k) + 2.0 * m * k * k
+    return f
+
+
+FORMS = {"bf16": 1, "fp8_e4m3": 2, "bf16+refine_last": 1 | 16, "fp8_e4m3+refine_last": 2 | 16}
+
+
+def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
+    """The precision form (rounded passes, fp32 refinement pass) on the same
+    workload and seeds as the fp32 step; residuals against the fp32 path's."""
+    import torch
+    l = k + p_over
+    flops_step = sum(flops_fixed_rank(m, n, k, l, v) for v in VS)
+    res = {}
+    for name, prec in FORMS.items():
+        def step(seed):
+            for v in VS:
+                h.fixed_rank(A, k, p_over, v, seed=seed * 16 + v, prec=prec, sync_info=False,
+                             out=outs[v])
+        step(999)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rr = {}
+        for v in VS:
+            f = h.fixed_rank(A, k, p_over, v, seed=5 + v, prec=prec, sync_info=True, out=outs[v])
+            rr[str(v)] = h.residual(A, f)
+        res[name] = {
+            "ms_per_step": round(dt * 1e3, 3),
+            "gflops": round(flops_step / dt / 1e9, 2),
+            "residual": rr,
+            "residual_ratio_vs_fp32": {v_: rr[v_] / resid_fp32[v_] for v_ in rr},
+        }
+    return res
+
+
+def serving_pool(pool_size, seed=5000):
+    """Host matrices of the serving workload: pool_size distinct rank-r
+    low-rank-plus-noise matrices with m, n ~ U[512, 8192], r ~ U[16, 256],
+    sigma_i = exp(-i/(r/4)), ||noise||_F = 1e-4 ||signal||_F, in pinned host
+    memory."""
+    import numpy as np
+    import torch
+    from synth import spectrum, lowrank_factors
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(pool_size):
+        m, n = (int(x) for x in rng.integers(512, 8193, 2))
+        r = int(rng.integers(16, 257))
+        sig = spectrum("exp", r, tau=r / 4.0)
+        X, sg, Y = lowrank_factors(m, n, sig, seed + 100 * i + 1, seed + 100 * i + 2)
+        S = (X * sg) @ Y.T
+        g = np.random.default_rng(seed + 100 * i + 3)
+        N = g.standard_normal((m, n), dtype=np.float32)
+        N *= np.float32(1e-4 * np.linalg.norm(sig) / max(np.linalg.norm(N), 1e-30))
+        A = torch.empty((m, n), dtype=torch.float32, pin_memory=True)
+        A.numpy()[...] = (S + N).astype(np.float32)
+        pool.append((A, r))
+    return pool
+
+
+def request_params(i, r, m, n, rng):
+    """Even requests fixed rank (k = r/2, p = 10, v ~ U{2..5}); odd ones
+    fixed precision (eps = 1e-3, b = 16, default l, v = 4)."""
+    if i % 2 == 0:
+        k = max(1, r // 2)
+        p_over = 10 if k + 10 < min(m, n) else 0
+        return dict(mode=0, k=k, p_over=p_over, v=int(rng.integers(2, 6)), seed=7000 + i)
+    return dict(mode=1, eps=1e-3, b=16, l=0, v=4, seed=7000 + i)
+
+
+def request_flops(prm, m, n, rank):
+    if prm["mode"] == 0:
+        return flops_fixed_rank(m, n, prm["k"], prm["k"] + prm["p_over"], prm["v"])
+    l = min(50 * 16, 16 * ((min(m, n) - 1) // 16))
+    return flops_fixed_precision(m, n, l, rank, prm["v"])
+
+
+def batched_vs_single(h, pool, count=32):
+    """The same problems solved one call at a time and as one batch (and its
+    graph replay for the fixed-rank ones) on the same GPU."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(11)
+    dev = torch.device("cuda:0")
+    dA = [A.to(dev, non_blocking=True) for (A, r) in pool]
+    probs = []
+    for i in range(count):
+        j = i % len(pool)
+        m, n = pool[j][0].shape
+        prm = request_params(i, pool[j][1], m, n, rng)
+        probs.append(dict(A=dA[j], **prm))
+    torch.cuda.synchronize()
+
+    def single():
+        outs = []
+        for pr in probs:
+            if pr["mode"] == 0:
+                outs.append(h.fixed_rank(pr["A"], pr["k"], pr["p_over"], pr["v"], seed=pr["seed"],
+                                         sync_info=False))
+            else:
+                outs.append(h.fixed_precision(pr["A"], pr["eps"], pr["b"], l=pr["l"], v=pr["v"],
+                                              seed=pr["seed"]))
+        torch.cuda.synchronize()
+        return outs
+
+    single()
+    t0 = time.perf_counter()
+    s_out = single()
+    t_single = time.perf_counter() - t0
+    h.batched(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b_out = h.batched(probs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(a.L.cpu().numpy(), b.L.cpu().numpy()) and
+               np.array_equal(a.p.cpu().numpy(), b.p.cpu().numpy()) for a, b in zip(s_out, b_out))
+    fr = [pr for pr in probs if pr["mode"] == 0]
+    h.batched(fr, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.batched(fr, graph=True)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    h.batched(fr)
+    torch.cuda.synchronize()
+    t_fr_batch = time.perf_counter() - t0
+    flops = sum(request_flops(pr, pr["A"].shape[0], pr["A"].shape[1], o.rank)
+                for pr, o in zip(probs, b_out))
+    return {
+        "problems": count, "distinct_matrices": len(pool),
+        "single_calls_ms": round(t_single * 1e3, 2), "batched_ms": round(t_batch * 1e3, 2),
+        "speedup": round(t_single / t_batch, 3), "batched_gflops": round(flops / t_batch / 1e9, 1),
+        "results_identical": bool(same),
+        "fixed_rank_subset": {"problems": len(fr), "batched_ms": round(t_fr_batch * 1e3, 2),
+                              "graph_replay_ms": round(t_graph * 1e3, 2)},
+    }
+
+
+def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
+    """Replay of a Poisson request stream through the serving loop: requests
+    cycle the pool's matrices (host, pinned); latency = completion minus
+    scheduled arrival."""
+    import threading
+    import numpy as np
+    import paper_2002_07138_amd as plu
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0 / rate, count)
+    sched = np.cumsum(gaps)
+    srv = plu.Server(0, hbm_budget_bytes=int(budget_gb) << 30, max_slots=slots)
+    tickets, late, meta = [], [], []
+    results = [None] * count
+
+    def waiter():
+        for i in range(count):
+            while len(tickets) <= i:
+                time.sleep(0.0005)
+            results[i] = srv.wait(tickets[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_start = time.perf_counter()
+    for i in range(count):
+        j = i % len(pool)
+        A, r = pool[j]
+        m, n = A.shape
+        prm = request_params(i, r, m, n, rng)
+        delay = t_start + sched[i] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        late.append(max(0.0, time.perf_counter() - (t_start + sched[i])))
+        kw = dict(prm)
+        tickets.append(srv.submit(A, **kw))
+        meta.append((prm, m, n))
+    th.join()
+    t_end = time.perf_counter()
+    srv.close()
+    lat = np.array([(res["t_done"] - res["t_submit"]) + lt for res, lt in zip(results, late)])
+    flops = sum(request_flops(prm, m, n, res["rank"]) for (prm, m, n), res in zip(meta, results))
+    ok = sum(1 for res in results if res["status"] in (0, 1, 2))
+    return {
+        "requests": count, "rate_per_s": rate, "distinct_matrices": len(pool),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "mean_ms": round(float(lat.mean()) * 1e3, 2),
+        "throughput_req_per_s": round(count / (t_end - t_start), 1),
+        "gflops": round(flops / (t_end - t_start) / 1e9, 1),
+        "completed_ok": ok,
+        "hbm_budget_gb": budget_gb, "slots": slots,
+        "latency_includes": "H2D copy of A, all steps, D2H copy of p, q, L, U",
+    }
+
+
 def kernel_source_hash() -> str:
     p = os.path.join(ROOT, "paper_2002_07138_amd", "csrc", "k_gemm.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -138,6 +346,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=20000, help="reduced sizes for quick checks")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision forms")
+    ap.add_argument("--serving-count", type=int, default=1024,
+                    help="requests of the serving replay (0 skips it and the batch comparison)")
+    ap.add_argument("--pool", type=int, default=16, help="distinct matrices of the serving replay")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run only the pass kernels at the workload shape (3 launches per "
                          "direction) and a plain 1 GiB copy, for hardware-counter runs")
@@ -228,6 +440,8 @@ def main():
         f = h.fixed_rank(A, k, p_over, v, seed=5 + v, sync_info=True, out=outs[v])
         resid[str(v)] = h.residual(A, f)
 
+    if not args.no_forms:
+        forms = precision_forms(h, A, outs, m, n, k, p_over, resid)
     traffic = load_traffic()
     roofline = {
         "bound": "mfma",
@@ -262,6 +476,8 @@ def main():
         "residual": resid,
         "input_generation_s": round(t_gen, 2),
     }
+    if not args.no_forms:
+        result["precision_forms"] = forms
 
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
@@ -282,6 +498,16 @@ def main():
         result["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
     else:
         result["cpu_baseline"] = None
+    if args.serving_count > 0:
+        del A
+        torch.cuda.empty_cache()
+        t_pool = time.perf_counter()
+        pool = serving_pool(args.pool)
+        t_pool = time.perf_counter() - t_pool
+        result["batched"] = batched_vs_single(h, pool)
+        torch.cuda.empty_cache()
+        result["serving"] = serving(pool, count=args.serving_count)
+        result["serving"]["pool_generation_s"] = round(t_pool, 2)
     h.close()
     print(json.dumps(result))
 

@@ -49,7 +49,19 @@ enum {
   PLU_PENDING = 8              /* server: request not finished yet */
 };
 
-typedef enum { PLU_PREC_FP32 = 0, PLU_PREC_BF16 = 1 } plu_prec;
+typedef enum {
+  PLU_PREC_FP32 = 0,       /* passes on the fp32 matrix cores */
+  PLU_PREC_BF16 = 1,       /* pass operands rounded to bfloat16 (round to nearest even) */
+  PLU_PREC_FP8_E4M3 = 2,   /* pass operands rounded to FP8 E4M3 (OCP e4m3fn) with one
+                              power-of-two (E8M0) scale per 32 consecutive entries along
+                              the contraction index: the smallest 2^e, e >= -127, with
+                              max|x| / 2^e <= 448 */
+  PLU_PREC_FORMAT_MASK = 15,
+  PLU_PREC_REFINE_LAST = 16 /* flag, OR-ed with BF16 or FP8_E4M3: the last of the v-1
+                              passes of Alg. 7 (the one whose result the final QR
+                              orthonormalizes) also runs on the fp32 A, re-projecting the
+                              rounded iterate; for v = 2 nothing is then rounded */
+} plu_prec;
 
 typedef struct plu_handle_s* plu_handle;
 
@@ -73,8 +85,10 @@ int plu_create(plu_handle* h, int device, void* hip_stream);
 int plu_destroy(plu_handle h);
 int plu_set_stream(plu_handle h, void* hip_stream);
 /* Bytes of device workspace the handle will hold for a fixed-rank or
- * fixed-precision call of this shape and sketch width l. */
-int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, size_t* bytes);
+ * fixed-precision call of this shape, sketch width l and pass precision
+ * (the bfloat16 form adds two rounded copies of A, 4 m n bytes). */
+int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, int32_t prec,
+                       size_t* bytes);
 const char* plu_status_string(int status);
 
 /* ---- Fixed-rank problem (Def. 1.1, Sec. 1) solved by PowerLU: Alg. 5 with
@@ -83,9 +97,14 @@ const char* plu_status_string(int status);
  *   k      target rank, 1 <= k;  p_over >= 0 oversampling (the paper's q);
  *          l = k + p_over must satisfy l < min(m, n) (Alg. 7 REQUIRE).
  *   v      passes over A, v >= 2.
- *   prec   arithmetic of the v-1 passes inside Alg. 7: FP32 (MFMA fp32) or
- *          BF16 (A and the iterate rounded to bf16, fp32 accumulation).  The
- *          final pass Y = A V(:,1:k) always runs in FP32.
+ *   prec   arithmetic of the v-1 passes inside Alg. 7: FP32 (MFMA fp32),
+ *          BF16 or FP8_E4M3 (A and the iterate rounded to that format, see
+ *          plu_prec; exact products on the matrix cores with fp32
+ *          accumulation), optionally | PLU_PREC_REFINE_LAST.  The final pass
+ *          Y = A V(:,1:k) always runs in FP32 on the fp32 A: it is the
+ *          refinement pass of the precision form.
+ *          The rounded copies of A cost 4 m n (BF16) or 2 m n (FP8) bytes
+ *          of workspace and are rebuilt on every call.
  *   Omega  device, nullable.  (v even ? m : n) x l Gaussian test matrix with
  *          leading dimension l.  NULL draws it on the device from `seed` with
  *          the Philox4x32-10 layout of plu_gaussian.
@@ -125,6 +144,89 @@ int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda
                  const float* L, int64_t ldl, const float* U, int64_t ldu,
                  double* rel_resid);
 
+/* ---- Batched problems: many fixed-rank and fixed-precision problems of
+ * uneven shapes solved together on the handle's stream.  Every problem runs
+ * exactly the steps of plu_fixed_rank / plu_fixed_precision; launches of the
+ * same kernel by different problems are merged into one grouped launch (the
+ * problems own consecutive ranges of its workgroups), so the passes of all
+ * problems share one persistent grouped GEMM launch and their LU panels one
+ * cooperative batched launch.  Each problem's result is bit-identical to the
+ * single-problem call with the same arguments.
+ *   A, Omega, p, q, L, U   device pointers as in the single calls.
+ *   prec                   PLU_PREC_FP32 only (the batched path has no
+ *                          rounded copies); others give status
+ *                          PLU_ERR_NOT_IMPLEMENTED.
+ * Outputs (host, in each request): rank, status and info; the call
+ * synchronizes once for the fixed-precision ranks and once at the end.
+ * flags: PLU_BATCH_GRAPH captures the merged launch sequence of a batch of
+ * fixed-rank problems into a HIP graph kept by the handle and replays it
+ * when the next call has the same requests (same shapes and pointers).
+ * Returns PLU_OK, or -3 when some request is invalid (its status then holds
+ * -i for its i-th field, counted from 1 in declaration order).             */
+typedef struct {
+  int32_t mode;            /* 0: fixed rank, 1: fixed precision */
+  int32_t column_exact;    /* fixed precision: Alg. 11 column rule */
+  int64_t m, n, lda;
+  const float* A;
+  int32_t k, p_over;       /* fixed rank */
+  int32_t v;               /* passes over A */
+  int32_t b, l;            /* fixed precision (l = 0: the default sketch width) */
+  double eps;              /* fixed precision */
+  int32_t prec;
+  const float* Omega;      /* nullable */
+  uint64_t seed;
+  int32_t* p;
+  int32_t* q;
+  float* L;
+  int64_t ldl;
+  float* U;
+  int64_t ldu;
+  int32_t rank;            /* out */
+  int32_t status;          /* out: PLU_* status of this problem */
+  plu_info info;           /* out */
+} plu_request;
+
+#define PLU_BATCH_GRAPH 1
+
+int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags);
+
+/* ---- Serving: a request loop on its own stream and worker thread.
+ * Requests are admitted in arrival order while the device memory they need
+ * (the copy of A, the outputs and the workspace) fits in the HBM budget and
+ * a slot is free; admitted requests are batched continuously: every loop
+ * iteration first admits what arrived, then advances all admitted problems
+ * through a bounded number of grouped launches (the merged launch sequence
+ * of plu_batched), so a request that arrives while others run joins them at
+ * the next iteration.  Results are bit-identical to the single calls.
+ *   plu_server_create   hbm_budget_bytes: device memory the server may use;
+ *                       max_slots: problems admitted at once (>= 1).
+ *   plu_server_submit   req: as for plu_batched, but A, p, q, L, U are HOST
+ *                       pointers (pinned memory recommended); they must stay
+ *                       valid until the request completes.  The server
+ *                       copies A in and the results out (p, q, the leading
+ *                       rank columns of L with leading dimension ldl and
+ *                       rows of U with ldu).  Never blocks.  Returns -i for
+ *                       an invalid field i, PLU_ERR_OOM when the request
+ *                       alone exceeds the budget.
+ *   plu_server_poll     PLU_PENDING, or PLU_OK with *res filled.
+ *   plu_server_wait     blocks until the ticket completes.
+ *   plu_server_destroy  finishes all submitted work, then frees.
+ * Times in plu_result are seconds since plu_server_create.                */
+typedef struct plu_server_s* plu_server;
+typedef struct {
+  uint64_t ticket;
+  int32_t status;          /* PLU_* status of the problem */
+  int32_t rank;
+  double t_submit, t_admit, t_done;
+  plu_info info;
+} plu_result;
+
+int plu_server_create(plu_server* s, int device, size_t hbm_budget_bytes, int32_t max_slots);
+int plu_server_submit(plu_server s, const plu_request* req, uint64_t* ticket);
+int plu_server_poll(plu_server s, uint64_t ticket, plu_result* res);
+int plu_server_wait(plu_server s, uint64_t ticket, plu_result* res);
+int plu_server_destroy(plu_server s);
+
 /* ================= Building blocks (one call per step of the path) ======= */
 
 /* Gaussian test matrix (Sec. 1; Alg. 7 lines 2 and 9): out (device,
@@ -144,6 +246,25 @@ int plu_gaussian(plu_handle h, int64_t rows, int64_t cols, uint64_t seed,
 int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, int64_t lda,
              int32_t l, const float* X, int64_t ldx, float* out, int64_t ldo,
              int32_t prec, double* normA2_out);
+
+/* Rounded copy of an operand of the precision form of the passes (the
+ * rounding the v-1 passes of Alg. 7 apply to A and to the iterate when prec
+ * is not FP32).  src: device fp32 rows x cols (lds).
+ *   fmt        PLU_PREC_BF16: uint16 bfloat16 codes (NaN kept quiet);
+ *              PLU_PREC_FP8_E4M3: uint8 E4M3 codes plus one E8M0 scale byte
+ *              (e + 127) per block of 32 consecutive entries of a dst row;
+ *              code = round(x / 2^e) to nearest even.
+ *   transpose  0: dst is rows x ldd, dst[i][j] = code(src[i][j]);
+ *              1: dst is cols x ldd, dst[j][i] = code(src[i][j]) (blocks of
+ *              32 then run along the columns of src).
+ *   dst        device codes; ldd a multiple of 64 (BF16) or 128 (FP8), at
+ *              least the row length; entries past the row length are set to
+ *              zero (the padded layout the passes read).
+ *   scales     device uint8, (transpose ? cols : rows) x ldd/32, FP8 only
+ *              (ignored for BF16, may be NULL); blocks wholly in the padding
+ *              get scale byte 0.                                           */
+int plu_quantize(plu_handle h, int32_t fmt, int64_t rows, int64_t cols, const float* src,
+                 int64_t lds, int32_t transpose, void* dst, int64_t ldd, void* scales);
 
 /* LU with partial pivoting of a tall M x c matrix (M >= c), the paper's
  * lu(.) (Sec. 2 notation): pivots are the first maximum |value| in LAPACK's

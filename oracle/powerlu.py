@@ -31,7 +31,9 @@ design notes of the repository):
   R13 Precision form (not in the paper, which computes in float64): the v - 1
       passes of Alg. 7 take operands rounded to a narrower format (module
       ``lowp``) and accumulate exactly; the final product with A, the LU and
-      QR steps and the indicator stay exact.
+      QR steps and the indicator stay exact.  With exact_last, the last of
+      the v - 1 passes (the one feeding the final QR) is exact too: a
+      refinement pass that re-projects the rounded iterate with the exact A.
 
 Pins: see tests/test_oracle_pins.py (GETRF against LAPACK and the textbook
 definition, crafted ties, zero columns; thin QR against exact arithmetic;
@@ -135,7 +137,8 @@ class RangeRecord:
 
 
 def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
-                record: RangeRecord | None = None, pass_round=None) -> np.ndarray:
+                record: RangeRecord | None = None, pass_round=None,
+                exact_last: bool = False) -> np.ndarray:
     """Alg. 7.  Returns an orthonormal n x l basis V of (A^T A)^P A^T Omega
     (v even, Omega m x l) or (A^T A)^P Omega (v odd, Omega n x l), with
     P = floor((v - 1) / 2).  Makes v - 1 passes over A; the caller's final
@@ -149,6 +152,8 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
     v - 1 products takes rounded operands, pass_round(A, axis) and
     pass_round(X, 0), with axis the contraction axis of A (1 for A X, 0 for
     A^T X), and is accumulated exactly.  Nothing else is rounded.
+    exact_last: the last of the v - 1 products (the one whose result the
+    final QR orthonormalizes) is exact even when pass_round is given.
     """
     if v < 2:
         raise ValueError("v >= 2 (Alg. 7 REQUIRE)")
@@ -157,15 +162,22 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
     P = (v - 1) // 2
     rec = record if record is not None else RangeRecord()
 
-    def times(X):          # A X, the products of the loop
+    def rounded():         # is the product about to be taken a rounded one?
         if pass_round is None:
+            return False
+        return not (exact_last and rec.passes - start == v - 2)
+
+    def times(X):          # A X, the products of the loop
+        if not rounded():
             return A @ X
         return pass_round(A, 1) @ pass_round(X, 0)
 
     def times_t(X):        # A^T X
-        if pass_round is None:
+        if not rounded():
             return A.T @ X
         return pass_round(A, 0).T @ pass_round(X, 0)
+
+    start = rec.passes
 
     if v % 2 == 0:
         if Omega.shape[0] != m:
@@ -237,18 +249,18 @@ def assemble(A: np.ndarray, Vk: np.ndarray, Y: np.ndarray | None = None) -> Fact
 
 
 def powerlu(A: np.ndarray, k: int, Omega: np.ndarray, v: int,
-            pass_round=None) -> Factorization:
+            pass_round=None, exact_last: bool = False) -> Factorization:
     """PowerLU (Alg. 5 with Alg. 7 in place of steps 1-2).  Omega is the
     caller's Gaussian matrix: m x l for even v, n x l for odd v, l = k + q.
-    pass_round: precision form of the v - 1 range passes (see range_basis);
-    the final product Y = A V_k is always exact."""
+    pass_round, exact_last: precision form of the v - 1 range passes (see
+    range_basis); the final product Y = A V_k is always exact."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     l = Omega.shape[1]
     if not (1 <= k <= l < min(m, n)):
         raise ValueError("need 1 <= k <= l < min(m, n)")
     rec = RangeRecord()
-    V = range_basis(A, Omega, v, rec, pass_round)
+    V = range_basis(A, Omega, v, rec, pass_round, exact_last)
     fac = assemble(A, V[:, :k])
     fac.passes = rec.passes + 1
     fac.normA2 = float(np.sum(A * A))
@@ -297,7 +309,8 @@ def rank_rule(normA2: float, colnorm2: np.ndarray, eps: float, b: int,
 
 
 def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
-               column_mode: bool = True, pass_round=None) -> Factorization:
+               column_mode: bool = True, pass_round=None,
+               exact_last: bool = False) -> Factorization:
     """PowerLU_FP (Alg. 9) on top of Alg. 8 (block rule) or Alg. 11 (column
     rule).  l = Omega.shape[1] must be a multiple of b (Sec. 4.1, l = s b).
     pass_round: precision form of the v - 1 range passes; G = A V is exact."""
@@ -308,7 +321,7 @@ def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
         raise ValueError("need b | l and l < min(m, n)")
     normA2 = float(np.sum(A * A))
     rec = RangeRecord()
-    V = range_basis(A, Omega, v, rec, pass_round)
+    V = range_basis(A, Omega, v, rec, pass_round, exact_last)
     G = A @ V
     colnorm2 = np.sum(G * G, axis=0)
     E = indicator(normA2, colnorm2)

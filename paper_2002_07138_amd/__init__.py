@@ -26,12 +26,17 @@ PLU_ERR_TIMEOUT = 7
 PLU_PENDING = 8
 PREC_FP32 = 0
 PREC_BF16 = 1
+PREC_FP8_E4M3 = 2
+PREC_REFINE_LAST = 16
 
 _ENTRY_POINTS = [
     "plu_create", "plu_destroy", "plu_set_stream", "plu_workspace_size", "plu_status_string",
     "plu_fixed_rank", "plu_fixed_precision", "plu_residual", "plu_gaussian", "plu_pass",
-    "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule",
+    "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule", "plu_quantize",
+    "plu_batched", "plu_server_create", "plu_server_submit", "plu_server_poll",
+    "plu_server_wait", "plu_server_destroy",
 ]
+BATCH_GRAPH = 1
 
 
 class PluInfo(ctypes.Structure):
@@ -44,6 +49,33 @@ class PluInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
+class PluRequest(ctypes.Structure):
+    """Mirror of plu_request (include/powerlu.h)."""
+    _fields_ = [
+        ("mode", ctypes.c_int32), ("column_exact", ctypes.c_int32),
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+        ("A", ctypes.c_void_p),
+        ("k", ctypes.c_int32), ("p_over", ctypes.c_int32), ("v", ctypes.c_int32),
+        ("b", ctypes.c_int32), ("l", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("prec", ctypes.c_int32),
+        ("Omega", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+        ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
+        ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
+        ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+        ("rank", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("info", PluInfo),
+    ]
+
+
+class PluResult(ctypes.Structure):
+    """Mirror of plu_result (include/powerlu.h)."""
+    _fields_ = [
+        ("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("rank", ctypes.c_int32),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+        ("info", PluInfo),
+    ]
 
 
 class PowerLUError(RuntimeError):
@@ -70,7 +102,7 @@ def _lib():
             "plu_create": [ctypes.POINTER(vp), ctypes.c_int, vp],
             "plu_destroy": [vp],
             "plu_set_stream": [vp, vp],
-            "plu_workspace_size": [vp, i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "plu_workspace_size": [vp, i64, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
             "plu_status_string": [ctypes.c_int],
             "plu_fixed_rank": [vp, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
                                vp, vp, vp, i64, vp, i64, pinfo],
@@ -85,6 +117,13 @@ def _lib():
             "plu_range_basis": [vp, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, i64],
             "plu_rank_rule": [vp, i64, i32, vp, i64, dbl, dbl, i32, i32, ctypes.POINTER(i32),
                               ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+            "plu_quantize": [vp, i32, i64, i64, vp, i64, i32, vp, i64, vp],
+            "plu_batched": [vp, i32, ctypes.POINTER(PluRequest), i32],
+            "plu_server_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, i32],
+            "plu_server_submit": [vp, ctypes.POINTER(PluRequest), ctypes.POINTER(u64)],
+            "plu_server_poll": [vp, u64, ctypes.POINTER(PluResult)],
+            "plu_server_wait": [vp, u64, ctypes.POINTER(PluResult)],
+            "plu_server_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -192,6 +231,28 @@ class Handle:
                                  _ld(X), _ptr(out), _ld(out), prec, _ptr(normA2)), "plu_pass")
         return out
 
+    def quantize(self, src, fmt=PREC_BF16, transpose=False):
+        """Rounded copy of src (the operand rounding of the precision form).
+        BF16: returns the codes as int16 (bfloat16 bit patterns), row length
+        padded to a multiple of 64 with zeros.  FP8_E4M3: returns (codes
+        uint8, scale bytes uint8), row length padded to a multiple of 128."""
+        t = self._torch
+        _check_mat(src, "src")
+        rows, cols = src.shape
+        out_rows, row_len = (cols, rows) if transpose else (rows, cols)
+        if fmt == PREC_FP8_E4M3:
+            ldd = (row_len + 127) // 128 * 128
+            dst = t.empty((out_rows, ldd), dtype=t.uint8, device=src.device)
+            sc = t.empty((out_rows, ldd // 32), dtype=t.uint8, device=src.device)
+        else:
+            ldd = (row_len + 63) // 64 * 64
+            dst = t.empty((out_rows, ldd), dtype=t.int16, device=src.device)
+            sc = None
+        self._rc(_lib().plu_quantize(self._h, fmt, rows, cols, _ptr(src), _ld(src),
+                                     1 if transpose else 0, _ptr(dst), ldd, _ptr(sc)),
+                 "plu_quantize")
+        return dst if sc is None else (dst, sc)
+
     def getrf(self, F, want_perm=True, want_u=True, sync_info=True):
         """In place: F -> V = P^T L.  Returns (perm, U, info)."""
         t = self._torch
@@ -274,6 +335,56 @@ class Handle:
         kk = k.value
         return Factors(p, q, L[:, :kk], U[:kk], kk, info.as_dict())
 
+    def batched(self, problems, graph=False):
+        """Solve many problems in one batched call (plu_batched).  Each
+        problem is a dict with A (device fp32 matrix) and either
+        mode=0, k, p_over, v or mode=1, eps, b, l (0: default), v,
+        column_exact; optional Omega, seed.  Returns a list of Factors (the
+        fixed-precision ones trimmed to their rank)."""
+        t = self._torch
+        reqs = (PluRequest * len(problems))()
+        keep = []
+        for r, pr in zip(reqs, problems):
+            A = pr["A"]
+            _check_mat(A, "A")
+            m, n = A.shape
+            mode = int(pr.get("mode", 0))
+            r.mode = mode
+            r.column_exact = 1 if pr.get("column_exact", True) else 0
+            r.m, r.n, r.lda = m, n, _ld(A)
+            r.A = A.data_ptr()
+            r.v = int(pr["v"])
+            r.prec = int(pr.get("prec", PREC_FP32))
+            if mode == 0:
+                r.k, r.p_over = int(pr["k"]), int(pr["p_over"])
+                cap = r.k
+            else:
+                r.b, r.l, r.eps = int(pr["b"]), int(pr.get("l", 0)), float(pr["eps"])
+                cap = r.l if r.l else min(50 * r.b, r.b * ((min(m, n) - 1) // r.b))
+            Om = pr.get("Omega")
+            if Om is not None:
+                _check_mat(Om, "Omega")
+            r.Omega = Om.data_ptr() if Om is not None else None
+            r.seed = int(pr.get("seed", 0))
+            p = t.empty(m, dtype=t.int32, device=A.device)
+            q = t.empty(n, dtype=t.int32, device=A.device)
+            L = t.empty((m, cap), dtype=t.float32, device=A.device)
+            U = t.empty((cap, n), dtype=t.float32, device=A.device)
+            r.p, r.q, r.L, r.ldl, r.U, r.ldu = p.data_ptr(), q.data_ptr(), L.data_ptr(), cap, \
+                U.data_ptr(), n
+            keep.append((p, q, L, U, A, Om))
+        rc = _lib().plu_batched(self._h, len(problems), reqs, BATCH_GRAPH if graph else 0)
+        if rc != PLU_OK:
+            bad = [(i, r.status) for i, r in enumerate(reqs) if r.status != 0]
+            raise PowerLUError(rc, f"plu_batched (request statuses {bad})")
+        out = []
+        for r, (p, q, L, U, A, Om) in zip(reqs, keep):
+            if r.status not in (PLU_OK, PLU_WARN_ZERO_PIVOT, PLU_TOL_NOT_REACHED):
+                raise PowerLUError(r.status, "plu_batched request")
+            k = r.rank
+            out.append(Factors(p, q, L[:, :k], U[:k], k, r.info.as_dict()))
+        return out
+
     def residual(self, A, f: Factors):
         _check_mat(A, "A")
         m, n = A.shape
@@ -283,3 +394,89 @@ class Handle:
                                      _ptr(L), _ld(L), _ptr(U), _ld(U), ctypes.byref(r)),
                  "plu_residual")
         return r.value
+
+
+class Server:
+    """The request loop of libpowerlu (plu_server_*).  Inputs and outputs are
+    host memory: pass torch CPU tensors (pinned recommended) or numpy arrays;
+    they are kept alive here until the request completes."""
+
+    def __init__(self, device=0, hbm_budget_bytes=8 << 30, max_slots=64):
+        lib = _lib()
+        s = ctypes.c_void_p()
+        rc = lib.plu_server_create(ctypes.byref(s), device, hbm_budget_bytes, max_slots)
+        if rc != 0:
+            raise PowerLUError(rc, "plu_server_create")
+        self._s = s
+        self._keep = {}
+
+    @staticmethod
+    def _hptr(x):
+        if hasattr(x, "data_ptr"):
+            if x.is_cuda:
+                raise TypeError("server inputs and outputs are host memory")
+            return x.data_ptr()
+        return x.ctypes.data
+
+    def submit(self, A, mode=0, k=0, p_over=0, v=4, eps=0.0, b=1, l=0, column_exact=True,
+               seed=0, out=None):
+        """A: host fp32 m x n (row-major, contiguous rows).  out: optional
+        (p, q, L, U) host arrays (int32 m, int32 n, fp32 m x cap, fp32 cap x n);
+        allocated (numpy) when omitted.  Returns the ticket."""
+        import numpy as np
+        m, n = A.shape
+        cap = k if mode == 0 else (l if l else min(50 * b, b * ((min(m, n) - 1) // b)))
+        if out is None:
+            out = (np.empty(m, np.int32), np.empty(n, np.int32), np.empty((m, max(cap, 1)), np.float32),
+                   np.empty((max(cap, 1), n), np.float32))
+        p, q, L, U = out
+        r = PluRequest()
+        r.mode, r.column_exact = mode, 1 if column_exact else 0
+        r.m, r.n = m, n
+        r.lda = A.stride(0) if hasattr(A, "stride") and callable(A.stride) else A.strides[0] // 4
+        r.A = self._hptr(A)
+        r.k, r.p_over, r.v, r.b, r.l, r.eps = k, p_over, v, b, l, float(eps)
+        r.prec, r.Omega, r.seed = PREC_FP32, None, seed
+        r.p, r.q, r.L, r.U = self._hptr(p), self._hptr(q), self._hptr(L), self._hptr(U)
+        r.ldl = max(cap, 1)
+        r.ldu = n
+        t = ctypes.c_uint64()
+        rc = _lib().plu_server_submit(self._s, ctypes.byref(r), ctypes.byref(t))
+        if rc != 0:
+            raise PowerLUError(rc, "plu_server_submit")
+        self._keep[t.value] = (A, out)
+        return t.value
+
+    def poll(self, ticket):
+        res = PluResult()
+        rc = _lib().plu_server_poll(self._s, ticket, ctypes.byref(res))
+        if rc == PLU_PENDING:
+            return None
+        if rc != 0:
+            raise PowerLUError(rc, "plu_server_poll")
+        return self._finish(ticket, res)
+
+    def wait(self, ticket):
+        res = PluResult()
+        rc = _lib().plu_server_wait(self._s, ticket, ctypes.byref(res))
+        if rc != 0:
+            raise PowerLUError(rc, "plu_server_wait")
+        return self._finish(ticket, res)
+
+    def _finish(self, ticket, res):
+        A, (p, q, L, U) = self._keep.pop(ticket)
+        k = res.rank
+        return dict(p=p, q=q, L=L[:, :k], U=U[:k], rank=k, status=res.status,
+                    t_submit=res.t_submit, t_admit=res.t_admit, t_done=res.t_done,
+                    info=res.info.as_dict())
+
+    def close(self):
+        if getattr(self, "_s", None):
+            _lib().plu_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

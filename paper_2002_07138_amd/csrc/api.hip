@@ -9,6 +9,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
+#include <condition_variable>
+#include <cstddef>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/powerlu.h"
@@ -25,6 +33,15 @@ struct plu_handle_s {
   size_t arena_bytes = 0;
   uint32_t tag_counter = 0;
   size_t msg_off = 0, msg_words = 0;
+  // batched path: one workspace region per problem, merged-launch tables,
+  // and the graph of the last captured batch with the requests it was built for
+  char* batch_arena = nullptr;
+  size_t batch_bytes = 0;
+  plu::MergeBuffers mbuf;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gsig;
+  plu::MergeBuffers gbuf;
 };
 
 namespace {
@@ -33,8 +50,15 @@ constexpr int kQB = 128;
 constexpr int kMaxGramChunks = 256;
 constexpr int kTargetWgs = 1024;  // concurrent pass workgroups: 4 per CU on 256 CUs
 constexpr int kMaxSplit = 16;
+constexpr int kLowpWgs = 512;     // concurrent bfloat16 pass workgroups: 2 per CU
 
 inline int64_t ru4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+inline bool valid_prec(int prec) {
+  const int fmt = prec & PLU_PREC_FORMAT_MASK;
+  return fmt >= PLU_PREC_FP32 && fmt <= PLU_PREC_FP8_E4M3 &&
+         (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST)) == 0;
+}
 inline int64_t ru(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 #define PLU_TRY_HIP(expr)                \
@@ -70,6 +94,15 @@ struct Ws {
   double *gram_part, *gram, *rinv64, *sumsq_part, *colsq_part, *vsq_part, *colnorm, *scal;
   int32_t* iscal;
   int64_t sumsq_cap, colsq_cap;
+  // precision form: bfloat16 copies of A (row-major and transposed) and of the
+  // sketch (transposed), padded to multiples of 64 along the contraction index
+  uint16_t *ab, *abt, *xt;
+  int64_t ldab, ldabt, ldxt, xt_rows;
+  double* cvt_part;
+  int64_t cvt_cap;
+  // FP8 form: codes and E8M0 scales of A (both layouts) and of the sketch
+  uint8_t *a8, *a8s, *a8t, *a8ts, *x8, *x8s;
+  int64_t lda8, lda8t, ldx8, x8_rows;
 };
 
 int64_t part_need(int64_t m, int64_t n, int64_t l) {
@@ -93,7 +126,29 @@ int64_t part_need(int64_t m, int64_t n, int64_t l) {
   return need;
 }
 
-Ws layout(Layout& L, int64_t m, int64_t n, int64_t l) {
+// Contraction padding of the reduced-precision copies (the depth of one
+// stage of the pass kernel).
+inline int64_t lowp_kalign(int prec) { return prec == PLU_PREC_FP8_E4M3 ? 128 : 64; }
+
+// Rows of the transposed sketch a reduced-precision pass over C columns reads.
+int64_t lowp_xt_rows(int64_t P, int64_t K, int64_t C, int prec) {
+  const GemmPlan pl = plan_gemm(P, K, C, kMaxSplit, kLowpWgs, (int)lowp_kalign(prec));
+  return ru((int64_t)pl.cblocks * pl.nt * 16, 64);
+}
+
+int64_t lowp_part_need(int64_t m, int64_t n, int64_t l, int prec) {
+  int64_t need = 0;
+  const int64_t lp = ru4(l), ka = lowp_kalign(prec);
+  for (int tr = 0; tr < 2; ++tr) {
+    const int64_t P = tr ? n : m, K = ru(tr ? m : n, ka);
+    const GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, (int)ka);
+    if (pl.nsplit > 1) need = std::max(need, (int64_t)pl.nsplit * P * lp);
+  }
+  return need;
+}
+
+Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32) {
+  prec &= PLU_PREC_FORMAT_MASK;
   Ws w{};
   const int64_t Mx = std::max(m, n);
   const int64_t lp = ru4(std::max<int64_t>(l, 4));
@@ -105,6 +160,7 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l) {
   w.tmp = L.take<float>(Mx * kQB);
   w.bt = L.take<float>(n * lp);
   w.part_cap = std::max<int64_t>(part_need(m, n, l), 1);
+  if (prec != PLU_PREC_FP32) w.part_cap = std::max(w.part_cap, lowp_part_need(m, n, l, prec));
   w.part = L.take<float>(w.part_cap);
   w.u12 = L.take<float>(64 * lp);
   w.rinv = L.take<float>(kQB * kQB);
@@ -133,12 +189,36 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l) {
   w.colnorm = L.take<double>(lp);
   w.scal = L.take<double>(16);
   w.iscal = L.take<int32_t>(16);
+  if (prec == PLU_PREC_BF16) {
+    w.ldab = ru(n, 64);
+    w.ldabt = ru(m, 64);
+    w.ldxt = ru(Mx, 64);
+    w.xt_rows = std::max(lowp_xt_rows(m, ru(n, 64), l, prec), lowp_xt_rows(n, ru(m, 64), l, prec));
+    w.ab = L.take<uint16_t>((size_t)m * w.ldab);
+    w.abt = L.take<uint16_t>((size_t)n * w.ldabt);
+    w.xt = L.take<uint16_t>((size_t)w.xt_rows * w.ldxt);
+    w.cvt_cap = ((std::max(m, w.ldabt) + 63) / 64) * 8;
+    w.cvt_part = L.take<double>(w.cvt_cap);
+  } else if (prec == PLU_PREC_FP8_E4M3) {
+    w.lda8 = ru(n, 128);
+    w.lda8t = ru(m, 128);
+    w.ldx8 = ru(Mx, 128);
+    w.x8_rows = std::max(lowp_xt_rows(m, w.lda8, l, prec), lowp_xt_rows(n, w.lda8t, l, prec));
+    w.a8 = L.take<uint8_t>((size_t)m * w.lda8);
+    w.a8s = L.take<uint8_t>((size_t)m * (w.lda8 / 32));
+    w.a8t = L.take<uint8_t>((size_t)n * w.lda8t);
+    w.a8ts = L.take<uint8_t>((size_t)n * (w.lda8t / 32));
+    w.x8 = L.take<uint8_t>((size_t)w.x8_rows * w.ldx8);
+    w.x8s = L.take<uint8_t>((size_t)w.x8_rows * (w.ldx8 / 32));
+    w.sumsq_cap = std::max<int64_t>(w.sumsq_cap, 1);
+  }
   return w;
 }
 
-int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out) {
+int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
+              int prec = PLU_PREC_FP32) {
   Layout dry;
-  layout(dry, m, n, l);
+  layout(dry, m, n, l, prec);
   const size_t need = dry.off + 256;
   if (need > h->arena_bytes) {
     if (h->arena) {
@@ -157,7 +237,7 @@ int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out) {
   }
   Layout L;
   L.base = h->arena;
-  *out = layout(L, m, n, l);
+  *out = layout(L, m, n, l, prec);
   if (h->tag_counter == 0) {
     if (launch_fill_u32(reinterpret_cast<uint32_t*>(out->msg), out->msg_words * 2, 0u, h->stream) !=
         hipSuccess)
@@ -249,11 +329,97 @@ hipError_t run_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, 
   return hipSuccess;
 }
 
+// bfloat16 copies of A for the precision form (both layouts), with ||A||_F^2
+// accumulated in float64 from the fp32 values.
+hipError_t convert_a_bf16(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A,
+                          int64_t lda, double* normA2_dev) {
+  hipError_t e;
+  int64_t np = 0;
+  if ((e = launch_cvt_bf16(A, lda, m, n, w.ab, w.ldab, w.abt, w.ldabt, n, w.cvt_part, &np,
+                           h->stream)) != hipSuccess)
+    return e;
+  if (np > w.cvt_cap) return hipErrorInvalidValue;
+  if (normA2_dev) return launch_sum_doubles(w.cvt_part, np, normA2_dev, h->stream);
+  return hipSuccess;
+}
+
+// One pass of the precision form: out = A X (trans 0) or A^T X (trans 1) with
+// both operands rounded to bfloat16 (A from the copies made by
+// convert_a_bf16), fp32 accumulation.
+hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n,
+                         const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo) {
+  const int64_t P = trans ? n : m, Kl = trans ? m : n, K = ru(Kl, 64);
+  const uint16_t* M = trans ? w.abt : w.ab;
+  const int64_t ldm = trans ? w.ldabt : w.ldab;
+  GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, 64);
+  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * ldo > w.part_cap)
+    pl = plan_gemm(P, K, l, 1, 1, 64);
+  const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
+  if (ct > w.xt_rows || K > w.ldxt) return hipErrorInvalidValue;
+  hipError_t e;
+  if ((e = launch_cvt_bf16(X, ldx, Kl, l, nullptr, 0, w.xt, K, ct, nullptr, nullptr,
+                           h->stream)) != hipSuccess)
+    return e;
+  if (pl.nsplit > 1) {
+    if ((e = launch_pass_bf16(EPI_PART, M, ldm, w.xt, K, w.part, ldo, P * ldo, P, K, l, pl,
+                              h->stream)) != hipSuccess)
+      return e;
+    return launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, l, nullptr, 64,
+                                h->stream);
+  }
+  return launch_pass_bf16(EPI_STORE, M, ldm, w.xt, K, out, ldo, 0, P, K, l, pl, h->stream);
+}
+
+// Block-scaled FP8 copies of A for the precision form (both layouts) and
+// ||A||_F^2 (float64, from the fp32 values: one extra read of A).
+hipError_t convert_a_fp8(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A,
+                         int64_t lda, double* normA2_dev) {
+  hipError_t e;
+  if ((e = launch_cvt_fp8(A, lda, m, n, w.a8, w.a8s, w.lda8, w.a8t, w.a8ts, w.lda8t, n,
+                          h->stream)) != hipSuccess)
+    return e;
+  if (normA2_dev) {
+    const int nb = 1024;
+    if (nb > w.sumsq_cap) return hipErrorInvalidValue;
+    if ((e = launch_sumsq_matrix(A, lda, m, n, w.sumsq_part, nb, h->stream)) != hipSuccess)
+      return e;
+    return launch_sum_doubles(w.sumsq_part, nb, normA2_dev, h->stream);
+  }
+  return hipSuccess;
+}
+
+// One pass of the FP8 form: both operands block-scaled E4M3, fp32 accumulation.
+hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n,
+                        const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo) {
+  const int64_t P = trans ? n : m, Kl = trans ? m : n, K = ru(Kl, 128);
+  const uint8_t* M = trans ? w.a8t : w.a8;
+  const uint8_t* Ms = trans ? w.a8ts : w.a8s;
+  const int64_t ldm = trans ? w.lda8t : w.lda8;
+  GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, 128);
+  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * ldo > w.part_cap)
+    pl = plan_gemm(P, K, l, 1, 1, 128);
+  const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
+  if (ct > w.x8_rows || K > w.ldx8) return hipErrorInvalidValue;
+  hipError_t e;
+  if ((e = launch_cvt_fp8(X, ldx, Kl, l, nullptr, nullptr, 0, w.x8, w.x8s, K, ct, h->stream)) !=
+      hipSuccess)
+    return e;
+  if (pl.nsplit > 1) {
+    if ((e = launch_pass_fp8(EPI_PART, M, Ms, ldm, w.x8, w.x8s, K, w.part, ldo, P * ldo, P, K, l,
+                             pl, h->stream)) != hipSuccess)
+      return e;
+    return launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, l, nullptr, 64,
+                                h->stream);
+  }
+  return launch_pass_fp8(EPI_STORE, M, Ms, ldm, w.x8, w.x8s, K, out, ldo, 0, P, K, l, pl,
+                         h->stream);
+}
+
 // Alg. 7.  Leaves the orthonormal n x l basis in *Vout (one of the workspace
 // buffers, leading dimension w.lp); passes counted in *passes.
 hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A, int64_t lda,
                        int l, int v, const float* Omega, uint64_t seed, float** Vout,
-                       int* passes) {
+                       int* passes, int prec = PLU_PREC_FP32) {
   const int64_t lp = w.lp;
   const int64_t rows = (v % 2 == 0) ? m : n;
   hipError_t e;
@@ -269,11 +435,33 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
   const int P = (v - 1) / 2;
   const GetrfWork gw = getrf_work(h, w, 0);
   const QrWork qw = qr_work(w, w.qb, lp);
-  if (v % 2 == 0) {
-    if ((e = run_pass(h, w, 1, m, n, A, lda, w.om, lp, l, w.zn, lp, first ? normA2 : nullptr,
-                      nullptr, nullptr)) != hipSuccess)
-      return e;
+  const int fmt = prec & PLU_PREC_FORMAT_MASK;
+  const bool refine = (prec & PLU_PREC_REFINE_LAST) != 0;
+  // the rounded copies are needed only if some pass is rounded
+  const bool any_rounded = fmt != PLU_PREC_FP32 && !(refine && v == 2);
+  if (any_rounded && fmt == PLU_PREC_BF16) {
+    if ((e = convert_a_bf16(h, w, m, n, A, lda, normA2)) != hipSuccess) return e;
     first = false;
+  } else if (any_rounded && fmt == PLU_PREC_FP8_E4M3) {
+    if ((e = convert_a_fp8(h, w, m, n, A, lda, normA2)) != hipSuccess) return e;
+    first = false;
+  }
+  // one of the v - 1 passes of Alg. 7 (the first one also yields ||A||_F^2);
+  // with refine, the last of them (it feeds the final QR) runs on the fp32 A
+  int pidx = 0;
+  auto pass = [&](int trans, const float* X, float* out) -> hipError_t {
+    const bool rounded = any_rounded && !(refine && pidx == v - 2);
+    ++pidx;
+    if (rounded && fmt == PLU_PREC_BF16) return run_pass_bf16(h, w, trans, m, n, X, lp, l, out, lp);
+    if (rounded && fmt == PLU_PREC_FP8_E4M3)
+      return run_pass_fp8(h, w, trans, m, n, X, lp, l, out, lp);
+    hipError_t r = run_pass(h, w, trans, m, n, A, lda, X, lp, l, out, lp,
+                            first ? normA2 : nullptr, nullptr, nullptr);
+    first = false;
+    return r;
+  };
+  if (v % 2 == 0) {
+    if ((e = pass(1, w.om, w.zn)) != hipSuccess) return e;
     ++np;
     if (v > 2) {
       if ((e = getrf_run(w.zn, lp, n, l, gw, nullptr, nullptr, 0, 0, h->stream)) != hipSuccess)
@@ -287,16 +475,11 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
     V = w.om;
   }
   for (int i = 1; i <= P; ++i) {
-    if ((e = run_pass(h, w, 0, m, n, A, lda, V, lp, l, w.ym, lp, first ? normA2 : nullptr, nullptr,
-                      nullptr)) != hipSuccess)
-      return e;
-    first = false;
+    if ((e = pass(0, V, w.ym)) != hipSuccess) return e;
     ++np;
     if ((e = getrf_run(w.ym, lp, m, l, gw, nullptr, nullptr, 0, 0, h->stream)) != hipSuccess)
       return e;
-    if ((e = run_pass(h, w, 1, m, n, A, lda, w.ym, lp, l, w.zn, lp, nullptr, nullptr, nullptr)) !=
-        hipSuccess)
-      return e;
+    if ((e = pass(1, w.ym, w.zn)) != hipSuccess) return e;
     ++np;
     if (i == P) {
       if ((e = thin_qr_run(w.zn, lp, n, l, gw, qw, h->stream)) != hipSuccess) return e;
@@ -378,6 +561,387 @@ int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int
   return status;
 }
 
+void drop_graph(plu_handle h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->gsig.clear();
+  h->gbuf.destroy();
+}
+
+// Checks one batched request; returns 0 or -(field index, from 1, in the
+// declaration order of plu_request) and the sketch width in *l_out.
+int check_request(const plu_request& r, int64_t* l_out) {
+  if (r.mode != 0 && r.mode != 1) return -1;
+  if (r.m <= 0) return -3;
+  if (r.n <= 0) return -4;
+  if (r.lda < r.n) return -5;
+  if (!r.A || (reinterpret_cast<uintptr_t>(r.A) & 3u)) return -6;
+  const int64_t mn = std::min(r.m, r.n);
+  int64_t l = 0;
+  if (r.mode == 0) {
+    if (r.k < 1) return -7;
+    if (r.p_over < 0) return -8;
+    l = (int64_t)r.k + r.p_over;
+    if (l >= mn) return -8;
+  } else {
+    if (r.b < 1) return -10;
+    l = r.l ? r.l : std::min<int64_t>(50LL * r.b, r.b * ((mn - 1) / r.b));
+    if (l <= 0 || l % r.b != 0 || l >= mn) return -11;
+    if (!(r.eps > 0.0)) return -12;
+  }
+  if (r.v < 2) return -9;
+  if (!valid_prec(r.prec)) return -13;
+  if (!r.p) return -16;
+  if (!r.q) return -17;
+  if (!r.L) return -18;
+  if (r.ldl < (r.mode == 0 ? r.k : l)) return -19;
+  if (!r.U) return -20;
+  if (r.ldu < r.n) return -21;
+  *l_out = l;
+  return 0;
+}
+
+// One problem of a batch: its own workspace region and launch record.
+struct BatchProblem {
+  plu_request* r = nullptr;
+  int64_t l = 0;
+  size_t off = 0, bytes = 0;
+  plu_handle_s hs;
+  Ws w{};
+  Recorder rec;
+  float* V = nullptr;
+  int np = 0, nblk = 0, k = 0;
+  bool ok = true;
+};
+
+// Steps of plu_fixed_rank (all) or of plu_fixed_precision up to the rank
+// rule (mode 1), recorded on the calling thread's recorder.
+hipError_t batch_phase_a(BatchProblem& b) {
+  plu_request& r = *b.r;
+  plu_handle hs = &b.hs;
+  hipError_t e;
+  int st = ensure_ws(hs, r.m, r.n, b.l, &b.w);
+  if (st) return hipErrorOutOfMemory;
+  if ((e = range_basis(hs, b.w, r.m, r.n, r.A, r.lda, (int)b.l, r.v, r.Omega, r.seed, &b.V,
+                       &b.np)) != hipSuccess)
+    return e;
+  if (r.mode == 0) {
+    if ((e = run_pass(hs, b.w, 0, r.m, r.n, r.A, r.lda, b.V, b.w.lp, r.k, b.w.ym, b.w.lp, nullptr,
+                      nullptr, nullptr)) != hipSuccess)
+      return e;
+    ++b.np;
+    return assemble(hs, b.w, r.m, r.n, r.k, b.V, r.p, r.q, r.L, r.ldl, r.U, r.ldu);
+  }
+  if ((e = run_pass(hs, b.w, 0, r.m, r.n, r.A, r.lda, b.V, b.w.lp, b.l, b.w.ym, b.w.lp, nullptr,
+                    b.w.colsq_part, &b.nblk)) != hipSuccess)
+    return e;
+  ++b.np;
+  if ((e = launch_splitk_reduce(b.V, 0, 1, nullptr, b.w.lp, r.n, b.l, b.w.vsq_part, 64,
+                                hs->stream)) != hipSuccess)
+    return e;
+  return launch_rank_rule(b.w.colsq_part, b.nblk, (int)b.l, b.w.vsq_part, (int)((r.n + 63) / 64),
+                          b.w.scal + 0, r.eps, r.b, r.column_exact ? 1 : 0, b.w.iscal + 0,
+                          b.w.scal + 1, b.w.iscal + 1, b.w.colnorm, hs->stream);
+}
+
+// The assembly of a fixed-precision problem once its rank is known.
+hipError_t batch_phase_b(BatchProblem& b) {
+  plu_request& r = *b.r;
+  plu_handle hs = &b.hs;
+  hipError_t e;
+  if (b.k == 0) {
+    if ((e = launch_iota(r.p, r.m, hs->stream)) != hipSuccess) return e;
+    return launch_iota(r.q, r.n, hs->stream);
+  }
+  return assemble(hs, b.w, r.m, r.n, b.k, b.V, r.p, r.q, r.L, r.ldl, r.U, r.ldu);
+}
+
+// Records fn(b) for every problem (each on its own recorder) and runs the
+// merged sequence.
+template <class F>
+hipError_t record_and_run(plu_handle h, std::vector<BatchProblem*>& ps, F fn, MergeBuffers& buf,
+                          bool dry_size_only, size_t* table_bytes) {
+  std::vector<const Recorder*> lists;
+  for (BatchProblem* b : ps) {
+    b->rec.ops.clear();
+    thread_recorder() = &b->rec;
+    hipError_t e = fn(*b);
+    thread_recorder() = nullptr;
+    if (e != hipSuccess) return e;
+    lists.push_back(&b->rec);
+  }
+  (void)dry_size_only;
+  (void)table_bytes;
+  return run_merged(lists, h->stream, h->cu_count, buf, nullptr);
+}
+
+// Inputs of a batch that decide its launch sequence (for graph reuse).
+std::vector<unsigned char> batch_signature(const plu_request* reqs, int count) {
+  std::vector<unsigned char> sig;
+  const size_t in_bytes = offsetof(plu_request, rank);
+  sig.resize((size_t)count * in_bytes);
+  for (int i = 0; i < count; ++i)
+    std::memcpy(sig.data() + (size_t)i * in_bytes, &reqs[i], in_bytes);
+  return sig;
+}
+
+// ---------------------------------------------------------------------------
+// Serving loop.
+// ---------------------------------------------------------------------------
+double now_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// First-fit sub-allocator over one device block (the HBM budget).
+struct Pool {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  bool init(size_t bytes) {
+    if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      base = nullptr;
+      return false;
+    }
+    size = bytes;
+    free_[0] = bytes;
+    return true;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, o = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[o] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct ServerJob {
+  uint64_t ticket = 0;
+  plu_request host{};          // the client's request (host pointers)
+  plu_request dev{};           // the same problem on device copies
+  int64_t cap = 0;             // columns of L / rows of U
+  size_t pool_off = 0, pool_bytes = 0, ws_off = 0, ws_bytes = 0;
+  BatchProblem bp;
+  int phase = 0;               // 1: main steps, 2: fixed-precision assembly
+  size_t head = 0;
+  plu_result res{};
+};
+
+size_t server_footprint(const plu_request& r, int64_t l, int64_t cap, size_t* ws_bytes) {
+  Layout dry;
+  layout(dry, r.m, r.n, l);
+  *ws_bytes = (size_t)ru((int64_t)(dry.off + 256), 256);
+  auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return a((size_t)r.m * r.n * 4) + a((size_t)r.m * 4) + a((size_t)r.n * 4) +
+         a((size_t)r.m * cap * 4) + a((size_t)cap * r.n * 4) + *ws_bytes;
+}
+
+}  // namespace
+
+struct plu_server_s {
+  plu_handle h = nullptr;
+  hipStream_t stream = nullptr;
+  Pool pool;
+  int max_slots = 1;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::unique_ptr<ServerJob>> pending;
+  std::vector<std::unique_ptr<ServerJob>> active;
+  std::map<uint64_t, plu_result> done;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  int device = 0;
+  int fatal = 0;
+};
+
+namespace {
+
+// Admits, records and runs; returns when stopped and drained.
+void server_loop(plu_server S) {
+  (void)hipSetDevice(S->device);
+  plu_handle h = S->h;
+  constexpr size_t kGroupsPerIter = 24;
+  for (;;) {
+    std::vector<ServerJob*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->active.empty())
+        S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+      if (S->stop && S->pending.empty() && S->active.empty()) return;
+      while (!S->pending.empty() && (int)S->active.size() < S->max_slots) {
+        ServerJob* j = S->pending.front().get();
+        size_t off = 0;
+        if (!S->pool.alloc(j->pool_bytes, &off)) break;
+        j->pool_off = off;
+        j->res.t_admit = now_s(S->t0);
+        S->active.push_back(std::move(S->pending.front()));
+        S->pending.pop_front();
+        admitted.push_back(j);
+      }
+    }
+    // device copies of the admitted problems, their workspaces, their steps
+    for (ServerJob* j : admitted) {
+      char* b = S->pool.base + j->pool_off;
+      auto take = [&](size_t bytes) {
+        char* p = b;
+        b += (bytes + 255) & ~size_t(255);
+        return p;
+      };
+      plu_request& r = j->host;
+      plu_request& d = j->dev;
+      d = r;
+      d.A = reinterpret_cast<float*>(take((size_t)r.m * r.n * 4));
+      d.lda = r.n;
+      d.p = reinterpret_cast<int32_t*>(take((size_t)r.m * 4));
+      d.q = reinterpret_cast<int32_t*>(take((size_t)r.n * 4));
+      d.L = reinterpret_cast<float*>(take((size_t)r.m * j->cap * 4));
+      d.ldl = j->cap;
+      d.U = reinterpret_cast<float*>(take((size_t)j->cap * r.n * 4));
+      d.ldu = r.n;
+      d.Omega = nullptr;
+      char* ws = take(j->ws_bytes);
+      (void)hipMemcpy2DAsync(const_cast<float*>(d.A), (size_t)r.n * 4, r.A, (size_t)r.lda * 4,
+                             (size_t)r.n * 4, (size_t)r.m, hipMemcpyHostToDevice, S->stream);
+      BatchProblem& bp = j->bp;
+      bp.r = &d;
+      bp.hs = *h;
+      bp.hs.stream = S->stream;
+      bp.hs.arena = ws;
+      bp.hs.arena_bytes = j->ws_bytes;
+      bp.hs.tag_counter = 0;
+      bp.hs.batch_arena = nullptr;
+      bp.hs.graph = nullptr;
+      bp.hs.gexec = nullptr;
+      bp.hs.mbuf = MergeBuffers();
+      bp.hs.gbuf = MergeBuffers();
+      int64_t l = 0;
+      (void)check_request(d, &l);
+      bp.l = l;
+      bp.rec.ops.clear();
+      thread_recorder() = &bp.rec;
+      hipError_t e = batch_phase_a(bp);
+      thread_recorder() = nullptr;
+      j->phase = 1;
+      j->head = 0;
+      if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
+    }
+    // advance every admitted problem through a bounded number of launches
+    std::vector<const Recorder*> lists;
+    std::vector<size_t> heads;
+    std::vector<ServerJob*> js;
+    for (auto& up : S->active) {
+      lists.push_back(&up->bp.rec);
+      heads.push_back(up->head);
+      js.push_back(up.get());
+    }
+    hipError_t e = run_merged_steps(lists, heads, S->stream, h->cu_count, kGroupsPerIter, h->mbuf,
+                                    nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) {
+      std::fprintf(stderr, "libpowerlu server: %s\n", hipGetErrorString(e));
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->fatal = PLU_ERR_HIP;
+    }
+    for (size_t i = 0; i < js.size(); ++i) js[i]->head = heads[i];
+    // completions
+    std::vector<ServerJob*> finished;
+    for (ServerJob* j : js) {
+      if (S->fatal) {
+        j->res.status = S->fatal;
+        finished.push_back(j);
+        continue;
+      }
+      if (j->head < j->bp.rec.ops.size()) continue;
+      BatchProblem& bp = j->bp;
+      if (j->dev.mode == 1 && j->phase == 1) {
+        int32_t ks[2];
+        double sc;
+        (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
+        (void)hipMemcpy(&sc, bp.w.scal, sizeof(sc), hipMemcpyDeviceToHost);
+        bp.k = std::isfinite(sc) ? ks[0] : 0;
+        bp.rec.ops.clear();
+        thread_recorder() = &bp.rec;
+        (void)batch_phase_b(bp);
+        thread_recorder() = nullptr;
+        j->phase = 2;
+        j->head = 0;
+        continue;
+      }
+      finished.push_back(j);
+    }
+    for (ServerJob* j : finished) {
+      const plu_request& d = j->dev;
+      const plu_request& r = j->host;
+      BatchProblem& bp = j->bp;
+      int k = d.mode == 0 ? d.k : bp.k;
+      if (!S->fatal) {
+        int st = PLU_OK;
+        if (d.mode == 1) {
+          int32_t ks[2];
+          double sc;
+          (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
+          (void)hipMemcpy(&sc, bp.w.scal, sizeof(sc), hipMemcpyDeviceToHost);
+          st = !std::isfinite(sc) ? PLU_ERR_NONFINITE : ks[1] ? PLU_OK : PLU_TOL_NOT_REACHED;
+          if (!std::isfinite(sc)) k = 0;
+        }
+        plu_handle_s hs = bp.hs;
+        j->res.status = finish_info(&hs, bp.w, st, k, d.v, (int)bp.l, d.mode == 1, &j->res.info);
+        if (d.mode == 1) j->res.info.tol_reached = st == PLU_OK ? 1 : 0;
+        j->res.rank = k;
+        (void)hipMemcpy(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost);
+        if (k > 0) {
+          (void)hipMemcpy2D(r.L, (size_t)r.ldl * 4, d.L, (size_t)d.ldl * 4, (size_t)k * 4,
+                            (size_t)r.m, hipMemcpyDeviceToHost);
+          (void)hipMemcpy2D(r.U, (size_t)r.ldu * 4, d.U, (size_t)d.ldu * 4, (size_t)r.n * 4,
+                            (size_t)k, hipMemcpyDeviceToHost);
+        }
+      }
+      j->res.t_done = now_s(S->t0);
+    }
+    if (!finished.empty()) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (ServerJob* j : finished) {
+        S->done[j->ticket] = j->res;
+        S->pool.release(j->pool_off, j->pool_bytes);
+        for (auto it = S->active.begin(); it != S->active.end(); ++it)
+          if (it->get() == j) {
+            S->active.erase(it);
+            break;
+          }
+      }
+      S->cv_done.notify_all();
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -422,10 +986,11 @@ int plu_create(plu_handle* out, int device, void* hip_stream) {
 
 int plu_destroy(plu_handle h) {
   if (!h) return -1;
-  if (h->arena) {
-    hipStreamSynchronize(h->stream);
-    hipFree(h->arena);
-  }
+  (void)hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  h->mbuf.destroy();
+  if (h->arena) (void)hipFree(h->arena);
+  if (h->batch_arena) (void)hipFree(h->batch_arena);
   delete h;
   return PLU_OK;
 }
@@ -436,14 +1001,16 @@ int plu_set_stream(plu_handle h, void* hip_stream) {
   return PLU_OK;
 }
 
-int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, size_t* bytes) {
+int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, int32_t prec,
+                       size_t* bytes) {
   if (!h) return -1;
   if (m <= 0) return -2;
   if (n <= 0) return -3;
   if (l <= 0) return -4;
-  if (!bytes) return -5;
+  if (!valid_prec(prec)) return -5;
+  if (!bytes) return -6;
   Layout dry;
-  layout(dry, m, n, l);
+  layout(dry, m, n, l, prec);
   *bytes = dry.off + 256;
   return PLU_OK;
 }
@@ -475,18 +1042,58 @@ int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, 
   if (ldx < l) return -9;
   if (!out) return -10;
   if (ldo < l) return -11;
-  if (prec != PLU_PREC_FP32) return prec == PLU_PREC_BF16 ? PLU_ERR_NOT_IMPLEMENTED : -12;
+  if (prec != PLU_PREC_FP32 && prec != PLU_PREC_BF16 && prec != PLU_PREC_FP8_E4M3) return -12;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
-  int st = ensure_ws(h, m, n, l, &w);
+  int st = ensure_ws(h, m, n, std::max<int64_t>(l, ru4(ldo)), &w, prec);
   if (st) return st;
-  const int64_t P = trans ? n : m;
-  // the split-K scratch uses the output's leading dimension
-  if (ru4(ldo) != ldo && plan_gemm(P, trans ? m : n, l, kMaxSplit, kTargetWgs).nsplit > 1) {
-    // fall through: run_pass keeps the partials at ldo, fine for any ldo
+  if (prec == PLU_PREC_BF16) {
+    PLU_TRY_HIP(convert_a_bf16(h, w, m, n, A, lda, normA2_out));
+    PLU_TRY_HIP(run_pass_bf16(h, w, trans, m, n, X, ldx, l, out, ldo));
+    return PLU_OK;
+  }
+  if (prec == PLU_PREC_FP8_E4M3) {
+    PLU_TRY_HIP(convert_a_fp8(h, w, m, n, A, lda, normA2_out));
+    PLU_TRY_HIP(run_pass_fp8(h, w, trans, m, n, X, ldx, l, out, ldo));
+    return PLU_OK;
   }
   PLU_TRY_HIP(run_pass(h, w, trans, m, n, A, lda, X, ldx, l, out, ldo, normA2_out, nullptr,
                        nullptr));
+  return PLU_OK;
+}
+
+int plu_quantize(plu_handle h, int32_t fmt, int64_t rows, int64_t cols, const float* src,
+                 int64_t lds, int32_t transpose, void* dst, int64_t ldd, void* scales) {
+  if (!h) return -1;
+  if (fmt != PLU_PREC_BF16 && fmt != PLU_PREC_FP8_E4M3) return -2;
+  if (rows <= 0) return -3;
+  if (cols <= 0) return -4;
+  if (!src || (reinterpret_cast<uintptr_t>(src) & 3u)) return -5;
+  if (lds < cols) return -6;
+  if (transpose != 0 && transpose != 1) return -7;
+  if (!dst || (reinterpret_cast<uintptr_t>(dst) & 15u)) return -8;
+  const int64_t align = fmt == PLU_PREC_BF16 ? 64 : 128;
+  if (ldd % align != 0 || ldd < (transpose ? rows : cols)) return -9;
+  if (fmt == PLU_PREC_FP8_E4M3 && !scales) return -10;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  if (fmt == PLU_PREC_FP8_E4M3) {
+    uint8_t* d = reinterpret_cast<uint8_t*>(dst);
+    uint8_t* sc = reinterpret_cast<uint8_t*>(scales);
+    if (transpose)
+      PLU_TRY_HIP(launch_cvt_fp8(src, lds, rows, cols, nullptr, nullptr, 0, d, sc, ldd, cols,
+                                 h->stream));
+    else
+      PLU_TRY_HIP(launch_cvt_fp8(src, lds, rows, cols, d, sc, ldd, nullptr, nullptr, 0, 0,
+                                 h->stream));
+    return PLU_OK;
+  }
+  uint16_t* d = reinterpret_cast<uint16_t*>(dst);
+  if (transpose)
+    PLU_TRY_HIP(launch_cvt_bf16(src, lds, rows, cols, nullptr, 0, d, ldd, cols, nullptr, nullptr,
+                                h->stream));
+  else
+    PLU_TRY_HIP(launch_cvt_bf16(src, lds, rows, cols, d, ldd, nullptr, 0, 0, nullptr, nullptr,
+                                h->stream));
   return PLU_OK;
 }
 
@@ -554,16 +1161,16 @@ int plu_range_basis(plu_handle h, int64_t m, int64_t n, const float* A, int64_t 
   if (lda < n) return -5;
   if (l <= 0 || l >= std::min(m, n)) return -6;
   if (v < 2) return -7;
-  if (prec != PLU_PREC_FP32) return prec == PLU_PREC_BF16 ? PLU_ERR_NOT_IMPLEMENTED : -8;
+  if (!valid_prec(prec)) return -8;
   if (!V) return -11;
   if (ldv < l) return -12;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
-  int st = ensure_ws(h, m, n, l, &w);
+  int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
   float* Vw = nullptr;
   int np = 0;
-  PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, Omega, seed, &Vw, &np));
+  PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, Omega, seed, &Vw, &np, prec));
   PLU_TRY_HIP(hipMemcpy2DAsync(V, ldv * sizeof(float), Vw, w.lp * sizeof(float),
                                l * sizeof(float), n, hipMemcpyDeviceToDevice, h->stream));
   return PLU_OK;
@@ -583,7 +1190,7 @@ int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t l
   const int64_t l = (int64_t)k + p_over;
   if (l >= std::min(m, n)) return -7;
   if (v < 2) return -8;
-  if (prec != PLU_PREC_FP32) return prec == PLU_PREC_BF16 ? PLU_ERR_NOT_IMPLEMENTED : -9;
+  if (!valid_prec(prec)) return -9;
   if (!p) return -12;
   if (!q) return -13;
   if (!L) return -14;
@@ -592,11 +1199,11 @@ int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t l
   if (ldu < n) return -17;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
-  int st = ensure_ws(h, m, n, l, &w);
+  int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
   float* V = nullptr;
   int np = 0;
-  PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, (int)l, v, Omega, seed, &V, &np));
+  PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, (int)l, v, Omega, seed, &V, &np, prec));
   // final pass: Y = A V(:, 1:k)
   PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, V, w.lp, k, w.ym, w.lp, nullptr, nullptr, nullptr));
   ++np;
@@ -620,7 +1227,7 @@ int plu_fixed_precision(plu_handle h, int64_t m, int64_t n, const float* A, int6
   if (l == 0) l = (int32_t)std::min<int64_t>(50LL * b, b * ((mn - 1) / b));
   if (l <= 0 || l % b != 0 || l >= mn) return -8;
   if (v < 2) return -9;
-  if (prec != PLU_PREC_FP32) return prec == PLU_PREC_BF16 ? PLU_ERR_NOT_IMPLEMENTED : -11;
+  if (!valid_prec(prec)) return -11;
   if (!p) return -14;
   if (!q) return -15;
   if (!L) return -16;
@@ -629,11 +1236,11 @@ int plu_fixed_precision(plu_handle h, int64_t m, int64_t n, const float* A, int6
   if (ldu < n) return -19;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
-  int st = ensure_ws(h, m, n, l, &w);
+  int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
   float* V = nullptr;
   int np = 0;
-  PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, Omega, seed, &V, &np));
+  PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, Omega, seed, &V, &np, prec));
   // G = A V with column norms^2 (float64) fused into the reduction
   int nblk = 0;
   PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, V, w.lp, l, w.ym, w.lp, nullptr, w.colsq_part,
@@ -760,6 +1367,241 @@ int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda
   hipStreamSynchronize(h->stream);
   hipFree(extra);
   return rc;
+}
+
+int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
+  if (!h) return -1;
+  if (count < 0) return -2;
+  if (count == 0) return PLU_OK;
+  if (!reqs) return -3;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  bool bad = false, all_fixed_rank = true;
+  std::vector<BatchProblem> probs((size_t)count);
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    plu_request& r = reqs[i];
+    std::memset(&r.info, 0, sizeof(r.info));
+    r.rank = 0;
+    int64_t l = 0;
+    const int c = check_request(r, &l);
+    r.status = c;
+    if (c) {
+      bad = true;
+      continue;
+    }
+    if ((r.prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32) {
+      r.status = PLU_ERR_NOT_IMPLEMENTED;
+      bad = true;
+      continue;
+    }
+    if (r.mode != 0) all_fixed_rank = false;
+    BatchProblem& b = probs[(size_t)i];
+    b.r = &r;
+    b.l = l;
+    Layout dry;
+    layout(dry, r.m, r.n, l);
+    b.bytes = ru((int64_t)(dry.off + 256), 256);
+    b.off = total;
+    total += b.bytes;
+  }
+  if (bad) return -3;
+  // graph replay of an identical batch of fixed-rank problems
+  const bool use_graph = (flags & PLU_BATCH_GRAPH) && all_fixed_rank;
+  std::vector<unsigned char> sig;
+  if (use_graph) {
+    sig = batch_signature(reqs, count);
+    if (h->gexec && sig == h->gsig && total <= h->batch_bytes) {
+      PLU_TRY_HIP(hipGraphLaunch(h->gexec, h->stream));
+      goto finish;
+    }
+  }
+  if (total > h->batch_bytes) {
+    PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+    drop_graph(h);   // its pointers refer to the old region
+    if (h->batch_arena) (void)hipFree(h->batch_arena);
+    h->batch_arena = nullptr;
+    h->batch_bytes = 0;
+    const size_t alloc = total + total / 8;
+    if (hipMalloc(reinterpret_cast<void**>(&h->batch_arena), alloc) != hipSuccess) {
+      (void)hipGetLastError();
+      return PLU_ERR_OOM;
+    }
+    h->batch_bytes = alloc;
+  }
+  {
+    std::vector<BatchProblem*> all, fp;
+    for (BatchProblem& b : probs) {
+      b.hs = *h;
+      b.hs.arena = h->batch_arena + b.off;
+      b.hs.arena_bytes = b.bytes;
+      b.hs.tag_counter = 0;   // first panel clears this problem's message slots
+      b.hs.batch_arena = nullptr;
+      b.hs.gexec = nullptr;
+      b.hs.graph = nullptr;
+      b.hs.mbuf = MergeBuffers();
+      b.hs.gbuf = MergeBuffers();
+      all.push_back(&b);
+      if (b.r->mode == 1) fp.push_back(&b);
+    }
+    if (use_graph) {
+      drop_graph(h);
+      // record, size the tables outside the capture, then capture the launches
+      std::vector<const Recorder*> lists;
+      for (BatchProblem* b : all) {
+        thread_recorder() = &b->rec;
+        hipError_t e = batch_phase_a(*b);
+        thread_recorder() = nullptr;
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? PLU_ERR_OOM : PLU_ERR_HIP;
+        lists.push_back(&b->rec);
+      }
+      PLU_TRY_HIP(h->gbuf.reserve(merged_table_bytes(lists, h->cu_count)));
+      h->gbuf.capturing = true;
+      PLU_TRY_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = run_merged(lists, h->stream, h->cu_count, h->gbuf, nullptr);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(h->stream, &g);
+      h->gbuf.capturing = false;
+      if (ce != hipSuccess || ee != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        std::fprintf(stderr, "libpowerlu: batch graph capture failed: %s / %s\n",
+                     hipGetErrorString(ce), hipGetErrorString(ee));
+        return PLU_ERR_HIP;
+      }
+      h->graph = g;
+      PLU_TRY_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+      h->gsig = sig;
+      PLU_TRY_HIP(hipGraphLaunch(h->gexec, h->stream));
+    } else {
+      hipError_t e = record_and_run(h, all, batch_phase_a, h->mbuf, false, nullptr);
+      if (e != hipSuccess) return e == hipErrorOutOfMemory ? PLU_ERR_OOM : PLU_ERR_HIP;
+      if (!fp.empty()) {
+        PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+        for (BatchProblem* b : fp) {
+          int32_t ks[2];
+          double sc;
+          PLU_TRY_HIP(hipMemcpy(ks, b->w.iscal, sizeof(ks), hipMemcpyDeviceToHost));
+          PLU_TRY_HIP(hipMemcpy(&sc, b->w.scal, sizeof(sc), hipMemcpyDeviceToHost));
+          b->k = std::isfinite(sc) ? ks[0] : 0;
+          b->r->info.tol_reached = ks[1];
+        }
+        if ((e = record_and_run(h, fp, batch_phase_b, h->mbuf, false, nullptr)) != hipSuccess)
+          return PLU_ERR_HIP;
+      }
+    }
+  }
+finish:
+  PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < count; ++i) {
+    plu_request& r = reqs[i];
+    // the workspace of problem i (same layout as when it was recorded)
+    Layout L;
+    L.base = h->batch_arena + probs[(size_t)i].off;
+    int64_t l = probs[(size_t)i].l;
+    const Ws w = layout(L, r.m, r.n, l);
+    if (r.mode == 0) {
+      r.rank = r.k;
+      r.status = finish_info(h, w, PLU_OK, r.k, r.v, (int)l, false, &r.info);
+    } else {
+      int32_t ks[2];
+      double sc[2];
+      PLU_TRY_HIP(hipMemcpy(ks, w.iscal, sizeof(ks), hipMemcpyDeviceToHost));
+      PLU_TRY_HIP(hipMemcpy(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost));
+      const int k = std::isfinite(sc[0]) ? ks[0] : 0;
+      r.rank = k;
+      int st = ks[1] ? PLU_OK : PLU_TOL_NOT_REACHED;
+      if (!std::isfinite(sc[0])) st = PLU_ERR_NONFINITE;
+      r.status = finish_info(h, w, st, k, r.v, (int)l, true, &r.info);
+      r.info.tol_reached = ks[1] ? 1 : 0;
+    }
+  }
+  return PLU_OK;
+}
+
+int plu_server_create(plu_server* out, int device, size_t hbm_budget_bytes, int32_t max_slots) {
+  if (!out) return -1;
+  if (max_slots < 1) return -4;
+  plu_handle h = nullptr;
+  int rc = plu_create(&h, device, nullptr);
+  if (rc) return rc;
+  plu_server S = new plu_server_s();
+  S->h = h;
+  S->device = device;
+  S->max_slots = max_slots;
+  S->t0 = std::chrono::steady_clock::now();
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    plu_destroy(h);
+    delete S;
+    return PLU_ERR_HIP;
+  }
+  h->stream = S->stream;
+  if (!S->pool.init(hbm_budget_bytes)) {
+    (void)hipStreamDestroy(S->stream);
+    plu_destroy(h);
+    delete S;
+    return PLU_ERR_OOM;
+  }
+  S->worker = std::thread(server_loop, S);
+  *out = S;
+  return PLU_OK;
+}
+
+int plu_server_submit(plu_server S, const plu_request* req, uint64_t* ticket) {
+  if (!S) return -1;
+  if (!req) return -2;
+  if (!ticket) return -3;
+  int64_t l = 0;
+  const int c = check_request(*req, &l);
+  if (c) return c;
+  if ((req->prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32) return PLU_ERR_NOT_IMPLEMENTED;
+  auto j = std::make_unique<ServerJob>();
+  j->host = *req;
+  j->cap = req->mode == 0 ? req->k : l;
+  j->pool_bytes = server_footprint(*req, l, j->cap, &j->ws_bytes);
+  if (j->pool_bytes > S->pool.size) return PLU_ERR_OOM;
+  std::lock_guard<std::mutex> lk(S->mu);
+  j->ticket = S->next_ticket++;
+  j->res.ticket = j->ticket;
+  j->res.t_submit = now_s(S->t0);
+  *ticket = j->ticket;
+  S->pending.push_back(std::move(j));
+  S->cv_work.notify_one();
+  return PLU_OK;
+}
+
+int plu_server_poll(plu_server S, uint64_t ticket, plu_result* res) {
+  if (!S) return -1;
+  if (!res) return -3;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->done.find(ticket);
+  if (it == S->done.end()) return ticket < S->next_ticket ? PLU_PENDING : -2;
+  *res = it->second;
+  return PLU_OK;
+}
+
+int plu_server_wait(plu_server S, uint64_t ticket, plu_result* res) {
+  if (!S) return -1;
+  if (!res) return -3;
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (ticket == 0 || ticket >= S->next_ticket) return -2;
+  S->cv_done.wait(lk, [&] { return S->done.count(ticket) > 0; });
+  *res = S->done[ticket];
+  return PLU_OK;
+}
+
+int plu_server_destroy(plu_server S) {
+  if (!S) return -1;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  (void)hipStreamSynchronize(S->stream);
+  if (S->pool.base) (void)hipFree(S->pool.base);
+  plu_destroy(S->h);
+  (void)hipStreamDestroy(S->stream);
+  delete S;
+  return PLU_OK;
 }
 
 }  // extern "C"

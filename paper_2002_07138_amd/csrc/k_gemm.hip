@@ -52,9 +52,12 @@ __device__ __forceinline__ f32x4 load4(const float* src, int64_t idx, int64_t li
 }
 
 // RT: 16-row MFMA tiles per wave (the workgroup covers BP = 64 RT rows);
-// BKT: reduction depth per LDS stage.
-template <int MODE, int NT, int EPI, int RT = GEMM_BP / 64, int BKT = GEMM_BK>
-__global__ __launch_bounds__(256, (NT * RT >= 32) ? 1 : 2) void k_pass(GemmArgs g) {
+// BKT: reduction depth per LDS stage.  DYN: the grouped form, where the
+// column-tile count (g.nt <= NT) is read at run time; all NT tiles are
+// multiplied (columns past C load as zeros, columns of the next block are
+// computed and dropped) and only g.nt are stored.
+template <int MODE, int NT, int EPI, int RT = GEMM_BP / 64, int BKT = GEMM_BK, bool DYN = false>
+__device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
   constexpr int BP = 64 * RT;
   constexpr int BK = BKT;
   constexpr int AST_N = BK + 4;   // mode N A tile: [BP][BK+4]  (row p, reduction r)
@@ -76,17 +79,19 @@ __global__ __launch_bounds__(256, (NT * RT >= 32) ? 1 : 2) void k_pass(GemmArgs 
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of logical ids, ordered split-major, so the workgroups
   // sharing an L2 also share the rows of X they stream.
-  const int nwg = gridDim.x;
-  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int nwg = gr.gx;
+  const int xcd = gr.bx & 7, idx = gr.bx >> 3;
   const int per = nwg >> 3, rem = nwg & 7;
   const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
   const int npb = nwg / g.nsplit;
   const int split = lid / npb;
   const int64_t p0 = (int64_t)(lid % npb) * BP;
-  const int64_t c0 = (int64_t)blockIdx.y * XC;
+  const int ntr = DYN ? g.nt : NT;                 // column tiles of this problem
+  const int64_t c0 = (int64_t)gr.by * (DYN ? ntr * 16 : XC);
   const int64_t rb = (int64_t)split * g.rsplit;
   const int64_t re = (rb + g.rsplit < g.R) ? rb + g.rsplit : g.R;
-  const bool do_ss = (g.sumsq_part != nullptr) && blockIdx.y == 0;
+  const bool do_ss = (g.sumsq_part != nullptr) && gr.by == 0;
+  constexpr int epi = EPI;
   double ss = 0.0;
 
   f32x4 ra[AIT];
@@ -233,18 +238,19 @@ __global__ __launch_bounds__(256, (NT * RT >= 32) ? 1 : 2) void k_pass(GemmArgs 
       const int64_t p = p0 + wave * 16 * RT + i * 16 + g4 * 4 + e;
       if (p >= g.P) continue;
       bool rowok = true;
-      if (EPI == EPI_SUB && g.rowmask) rowok = g.rowmask[p] < 0;
+      if (epi == EPI_SUB && g.rowmask) rowok = g.rowmask[p] < 0;
       if (!rowok) continue;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
+        if (DYN && j >= ntr) continue;
         const int64_t c = c0 + j * 16 + pr;
         if (c >= g.C) continue;
         const float v = acc[i][j][e];
-        if (EPI == EPI_STORE) {
+        if (epi == EPI_STORE) {
           g.out[p * g.ldo + c] = v;
-        } else if (EPI == EPI_PART) {
+        } else if (epi == EPI_PART) {
           g.out[(int64_t)split * g.part_stride + p * g.ldo + c] = v;
-        } else if (EPI == EPI_SUB) {
+        } else if (epi == EPI_SUB) {
           g.out[p * g.ldo + c] -= v;
         } else {
           const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + g.qidx[c]] - (double)v;
@@ -253,46 +259,76 @@ __global__ __launch_bounds__(256, (NT * RT >= 32) ? 1 : 2) void k_pass(GemmArgs 
       }
     }
   }
-  const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  if (g.sumsq_part != nullptr && blockIdx.y == 0) {
+  const int64_t wg = (int64_t)gr.by * gr.gx + gr.bx;
+  if (g.sumsq_part != nullptr && gr.by == 0) {
     const double t = block_sum_double(ss, red);
-    if (tid == 0) g.sumsq_part[blockIdx.x] = t;
+    if (tid == 0) g.sumsq_part[gr.bx] = t;
   }
-  if (EPI == EPI_RESID) {
+  if (epi == EPI_RESID) {
     const double t = block_sum_double(rs, red);
     if (tid == 0) g.resid_part[wg] = t;
   }
 }
 
+template <int MODE, int NT, int EPI>
+__device__ void b_pass(const GemmArgs& g, const Grid& gr) {
+  pass_body<MODE, NT, EPI>(g, gr);
+}
+
+// The grouped pass: either direction and up to 8 column tiles, read from the
+// problem's arguments, so one launch serves every pass of a batch that has
+// the same epilogue.
+template <int EPI>
+__device__ void b_pass_any(const GemmArgs& g, const Grid& gr) {
+  if (g.mode == 0) pass_body<0, 8, EPI, GEMM_BP / 64, GEMM_BK, true>(g, gr);
+  else pass_body<1, 8, EPI, GEMM_BP / 64, GEMM_BK, true>(g, gr);
+}
+
 template <int MODE, int EPI>
 hipError_t launch_nt(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
+  if (thread_recorder()) {
+    // recorded launches use the grouped form so that every pass of a batch
+    // can share one launch
+    GemmArgs b = a;
+    b.mode = MODE;
+    b.nt = nt;
+    return dispatch<GemmArgs, b_pass_any<EPI>, 256, 1>(b, grid, 0, s);
+  }
   switch (nt) {
 #define PLU_NT_CASE(N) \
-  case N: hipLaunchKernelGGL((k_pass<MODE, N, EPI>), grid, dim3(256), 0, s, a); break;
+  case N: return dispatch<GemmArgs, b_pass<MODE, N, EPI>, 256, (N * 2 >= 32) ? 1 : 2>(a, grid, 0, s);
     PLU_NT_CASE(1) PLU_NT_CASE(2) PLU_NT_CASE(3) PLU_NT_CASE(4)
     PLU_NT_CASE(5) PLU_NT_CASE(6) PLU_NT_CASE(7) PLU_NT_CASE(8)
 #undef PLU_NT_CASE
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 // out = sum over splits of the partials (fixed order), one thread per 4
 // consecutive columns of a row; optional per-column float64 sums of squares
 // over each block of rows_per_block rows (deterministic: fixed order).
-__global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ part,
-                                                      int64_t part_stride, int nsplit,
-                                                      float* out, int64_t ldo, int64_t P,
-                                                      int64_t C, double* colsq_part, int rb) {
+struct ReduceArgs {
+  const float* part; int64_t part_stride; int nsplit; float* out; int64_t ldo, P, C;
+  double* colsq_part; int rb;
+};
+
+__device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
+  const float* __restrict__ part = ra.part;
+  const int64_t part_stride = ra.part_stride;
+  const int nsplit = ra.nsplit;
+  float* out = ra.out;
+  const int64_t ldo = ra.ldo, P = ra.P, C = ra.C;
+  double* colsq_part = ra.colsq_part;
+  const int rb = ra.rb;
   const int64_t c4n = (C + 3) / 4;                 // float4 groups per row
   const int lanes_per_row = (int)((c4n < 64) ? c4n : 64);
   const int rows_per_pass = 256 / lanes_per_row;
   const int tid = threadIdx.x;
   const int rsub = tid / lanes_per_row, cl = tid % lanes_per_row;
-  const int64_t pb = blockIdx.x;
+  const int64_t pb = gr.bx;
   const int64_t pe = (pb * rb + rb < P) ? pb * rb + rb : P;
   const bool active = rsub < rows_per_pass;
-  const int64_t cgi = (int64_t)blockIdx.y * 64 + cl;   // this thread's float4 column group
+  const int64_t cgi = (int64_t)gr.by * 64 + cl;   // this thread's float4 column group
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
   if (active && cgi < c4n) {
     const int64_t c0 = cgi * 4;
@@ -353,7 +389,15 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int64_t n, double* out) {
+struct SumArgs {
+  const double* in; int64_t n; double* out;
+};
+
+__device__ void b_sum_doubles(const SumArgs& a, const Grid& gr) {
+  (void)gr;
+  const double* in = a.in;
+  const int64_t n = a.n;
+  double* out = a.out;
   __shared__ double red[256];
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) s += in[i];
@@ -366,11 +410,17 @@ __global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int64_t n
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_sumsq_matrix(const float* A, int64_t lda, int64_t m,
-                                                     int64_t n, double* part) {
+struct SumsqArgs {
+  const float* A; int64_t lda, m, n; double* part;
+};
+
+__device__ void b_sumsq_matrix(const SumsqArgs& a, const Grid& gr) {
+  const float* A = a.A;
+  const int64_t lda = a.lda, m = a.m, n = a.n;
+  double* part = a.part;
   __shared__ double red[4];
   double s = 0.0;
-  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+  for (int64_t i = gr.bx; i < m; i += gr.gx) {
     const float* row = A + i * lda;
     for (int64_t j = threadIdx.x; j < n; j += 256) {
       const double d = row[j];
@@ -378,12 +428,12 @@ __global__ __launch_bounds__(256) void k_sumsq_matrix(const float* A, int64_t ld
     }
   }
   const double t = block_sum_double(s, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) part[gr.bx] = t;
 }
 
 }  // namespace
 
-GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int slots) {
+GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int slots, int kalign) {
   // slots: workgroups the device runs at once.  The split of R is chosen so
   // that the grid fills whole rounds of slots (the last round nearly full),
   // with at least 256 of R per split.
@@ -411,11 +461,11 @@ GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int slots) {
     }
   }
   int64_t rs = (R + best_ns - 1) / best_ns;
-  rs = ((rs + BK - 1) / BK) * BK;
+  rs = ((rs + kalign - 1) / kalign) * kalign;
   int64_t ns = (R + rs - 1) / rs;
   if (ns < 1) ns = 1;
   pl.nsplit = (int)ns;
-  pl.rsplit = rs > 0 ? rs : BK;
+  pl.rsplit = rs > 0 ? rs : kalign;
   return pl;
 }
 
@@ -452,20 +502,19 @@ hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nspl
                                 int rows_per_block, hipStream_t s) {
   dim3 grid((unsigned)((P + rows_per_block - 1) / rows_per_block),
             (unsigned)(((C + 3) / 4 + 63) / 64));
-  hipLaunchKernelGGL(k_splitk_reduce, grid, dim3(256), 0, s, part, part_stride, nsplit, out, ldo,
-                     P, C, colsq_part, rows_per_block);
-  return hipGetLastError();
+  return dispatch<ReduceArgs, b_splitk_reduce, 256>(
+      ReduceArgs{part, part_stride, nsplit, out, ldo, P, C, colsq_part, rows_per_block}, grid, 0,
+      s);
 }
 
 hipError_t launch_sum_doubles(const double* in, int64_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_doubles, dim3(1), dim3(256), 0, s, in, n, out);
-  return hipGetLastError();
+  return dispatch<SumArgs, b_sum_doubles, 256>(SumArgs{in, n, out}, dim3(1), 0, s);
 }
 
 hipError_t launch_sumsq_matrix(const float* A, int64_t lda, int64_t m, int64_t n, double* part,
                                int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_sumsq_matrix, dim3(nblocks), dim3(256), 0, s, A, lda, m, n, part);
-  return hipGetLastError();
+  return dispatch<SumsqArgs, b_sumsq_matrix, 256>(SumsqArgs{A, lda, m, n, part}, dim3(nblocks),
+                                                  0, s);
 }
 
 }  // namespace plu

@@ -182,12 +182,12 @@ __device__ __forceinline__ float wave_max_f32(float v) {
 // the pivot column; (3) the waves of every workgroup share the polling of all
 // messages into LDS; (4) every wave picks the same winner and updates.
 template <int NB, int RPT, int NWAVE, int S>
-__global__ __launch_bounds__(64 * NWAVE) void k_getrf_panel(PanelArgs a) {
+__device__ void b_panel(const PanelArgs& a, const Grid& gr) {
   constexpr int MAXG = 64;                 // message slots (workgroups) at most
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int G = gridDim.x;
-  const int wg = blockIdx.x;
+  const int G = gr.gx;
+  const int wg = gr.bx;
   const uint64_t t0 = wall_clock64();
 
   __shared__ unsigned long long wck[NWAVE];            // wave best keys
@@ -500,7 +500,7 @@ struct TrsmArgs {
 // U12 = L11^{-1} F[pivot rows of the panel, right columns]; written back into
 // the pivot rows and into a compact nbw x (c - jb - nbw) buffer.  The block's
 // 64 right-hand columns are staged in LDS first, then solved in place.
-__global__ __launch_bounds__(256) void k_getrf_trsm(TrsmArgs a) {
+__device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
   __shared__ float L11[64][65];
   __shared__ float us[64][65];
   __shared__ int rows[64];
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256) void k_getrf_trsm(TrsmArgs a) {
   if (t < a.nbw) rows[t] = a.piv_row[a.jb + t];
   __syncthreads();
   const int cs = a.jb + a.nbw;
-  const int64_t cbase = (int64_t)cs + (int64_t)blockIdx.x * 64;
+  const int64_t cbase = (int64_t)cs + (int64_t)gr.bx * 64;
   // stage L11 and the block's 64 right-hand columns with all 256 threads
   for (int e = t; e < a.nbw * 64; e += 256) {
     const int s = e >> 6, col = e & 63;
@@ -532,23 +532,37 @@ __global__ __launch_bounds__(256) void k_getrf_trsm(TrsmArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_getrf_init(int32_t* piv_step, int32_t* pos, int64_t M,
-                                                   int32_t* zstep) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < M) {
-    piv_step[i] = -1;
-    pos[i] = (int32_t)i;
+struct InitArgs {
+  int32_t* piv_step; int32_t* pos; int64_t M; int32_t* zstep;
+};
+
+__device__ void b_getrf_init(const InitArgs& a, const Grid& gr) {
+  const int64_t i = (int64_t)gr.bx * 256 + threadIdx.x;
+  if (i < a.M) {
+    a.piv_step[i] = -1;
+    a.pos[i] = (int32_t)i;
   }
-  if (i == 0) *zstep = INT_MAX;
+  if (i == 0) *a.zstep = INT_MAX;
 }
 
 // Turns the in-place factor into V = P^T L (unit diagonal on each pivot row,
 // zeros to its right), extracts U (or U^T) and the row order perm.
-__global__ __launch_bounds__(256) void k_getrf_finalize(float* F, int64_t ldf, int64_t M, int c,
-                                                       const int32_t* piv_step, const int32_t* pos,
-                                                       int32_t* perm, float* Uout, int64_t ldu,
-                                                       int utrans) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+struct FinalizeArgs {
+  float* F; int64_t ldf, M; int c; const int32_t* piv_step; const int32_t* pos; int32_t* perm;
+  float* Uout; int64_t ldu; int utrans;
+};
+
+__device__ void b_getrf_finalize(const FinalizeArgs& fa, const Grid& gr) {
+  float* F = fa.F;
+  const int64_t ldf = fa.ldf, M = fa.M;
+  const int c = fa.c;
+  const int32_t* piv_step = fa.piv_step;
+  const int32_t* pos = fa.pos;
+  int32_t* perm = fa.perm;
+  float* Uout = fa.Uout;
+  const int64_t ldu = fa.ldu;
+  const int utrans = fa.utrans;
+  const int64_t e = (int64_t)gr.bx * 256 + threadIdx.x;
   if (e >= M * (int64_t)c) return;
   const int64_t i = e / c;
   const int t = (int)(e - i * c);
@@ -572,10 +586,8 @@ __global__ __launch_bounds__(256) void k_getrf_finalize(float* F, int64_t ldf, i
 
 template <int NB, int RPT, int NWAVE, int S>
 hipError_t launch_panel(const PanelArgs& pa, int nblocks, hipStream_t s) {
-  void* args[] = {const_cast<PanelArgs*>(&pa)};
-  return hipLaunchCooperativeKernel(
-      reinterpret_cast<const void*>(&k_getrf_panel<NB, RPT, NWAVE, S>), dim3(nblocks),
-      dim3(64 * NWAVE), args, 0, s);
+  return dispatch<PanelArgs, b_panel<NB, RPT, NWAVE, S>, 64 * NWAVE>(pa, dim3(nblocks), 0, s,
+                                                                      true);
 }
 
 }  // namespace
@@ -590,9 +602,10 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
                      float* Uout, int64_t ldu, int utrans, hipStream_t s) {
   if (c <= 0 || M < c) return hipErrorInvalidValue;
   hipError_t e;
-  hipLaunchKernelGGL(k_getrf_init, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, w.piv_step,
-                     w.pos, M, w.zstep);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = dispatch<InitArgs, b_getrf_init, 256>(InitArgs{w.piv_step, w.pos, M, w.zstep},
+                                                 dim3((unsigned)((M + 255) / 256)), 0, s)) !=
+      hipSuccess)
+    return e;
   constexpr int NB = 64, NWAVE = 8, S = 4;
   // one row per lane while 64 workgroups of 512 rows suffice, else two
   const int rpt = (M <= 64LL * NWAVE * 64) ? 1 : 2;
@@ -621,8 +634,9 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
     const int cs = jb + pa.nbw;
     if (cs < c) {
       TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12};
-      hipLaunchKernelGGL(k_getrf_trsm, dim3((unsigned)((c - cs + 63) / 64)), dim3(256), 0, s, ta);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = dispatch<TrsmArgs, b_trsm, 256>(ta, dim3((unsigned)((c - cs + 63) / 64)), 0, s)) !=
+          hipSuccess)
+        return e;
       GemmArgs g;
       g.A = F + jb; g.lda = ldf;
       g.X = w.u12; g.ldx = w.ldu12;
@@ -634,9 +648,9 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
     }
   }
   const int64_t tot = M * (int64_t)c;
-  hipLaunchKernelGGL(k_getrf_finalize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, F,
-                     ldf, M, c, w.piv_step, w.pos, perm, Uout, ldu, utrans);
-  return hipGetLastError();
+  return dispatch<FinalizeArgs, b_getrf_finalize, 256>(
+      FinalizeArgs{F, ldf, M, c, w.piv_step, w.pos, perm, Uout, ldu, utrans},
+      dim3((unsigned)((tot + 255) / 256)), 0, s);
 }
 
 }  // namespace plu

@@ -1,0 +1,644 @@
+// Precision form of the passes over A: reduced-precision copies of A and of
+// the sketch, and the pass kernel on the bfloat16 matrix cores.
+//
+// The v - 1 passes of Alg. 7 (Sec. 3.4) run on rounded operands with fp32
+// accumulation; the final product with A (Alg. 5 step 3, Alg. 9 step 2) stays
+// on the fp32 path and is the refinement pass.
+//
+// Both operands of a pass are read with the contraction index contiguous:
+// A is kept twice, row-major (for A X) and transposed (for A^T Y), and the
+// sketch X (K x l) is stored transposed (l x K).  Every copy is zero-padded to
+// a multiple of 64 along the contraction index, and the sketch to whole
+// column tiles, so the pass kernel has no bounds checks along K.
+#include "plu_internal.h"
+
+#include <algorithm>
+
+namespace plu {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// bfloat16 of an fp32 value: round to nearest, ties to even, on the 16
+// discarded bits; NaN is kept quiet.
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return ((u >> 16) | 0x40u) & 0xFFFFu;
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ __forceinline__ double wg_sum_double(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// src: R x C fp32 (ld lds).  Writes, for the tiles of 64 x 64 this workgroup
+// owns,
+//   rm (nullable): R x ldr bf16, rm[i][j] = bf16(src[i][j]) for j < C, 0 for C <= j < ldr;
+//   tr (nullable): Ct x ldt bf16, tr[j][i] = bf16(src[i][j]) for i < R, j < C, 0 elsewhere.
+// blockIdx.y: band of 64 rows of the tile grid (covering max(R, ldt) rows);
+// blockIdx.x: first column tile, then strided by gridDim.x (covering
+// max(ldr, Ct) columns).  Optional float64 sum of squares of src, one
+// partial per workgroup.
+__global__ __launch_bounds__(256) void k_cvt_bf16(const float* __restrict__ src, int64_t lds,
+                                                  int64_t R, int64_t C, uint16_t* rm, int64_t ldr,
+                                                  uint16_t* tr, int64_t ldt, int64_t Ct,
+                                                  int64_t ncol_tiles, double* sumsq_part) {
+  __shared__ uint16_t T[64][64 + 4];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * 64;
+  const int tr_row = tid >> 4, tc4 = (tid & 15) * 4;   // 16 threads x 4 columns per row
+  const bool svec = ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) && ((lds & 3) == 0);
+  double ss = 0.0;
+  for (int64_t tj = blockIdx.x; tj < ncol_tiles; tj += gridDim.x) {
+    const int64_t j0 = tj * 64;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int rr = it * 16 + tr_row;
+      const int64_t i = i0 + rr, j = j0 + tc4;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (i < R) {
+        const float* s = src + i * lds + j;
+        if (svec && j + 3 < C) {
+          const f32x4 q = *reinterpret_cast<const f32x4*>(s);
+          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (j + e < C) v[e] = s[e];
+        }
+      }
+      uint32_t b[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (sumsq_part) {
+          const double d = v[e];
+          ss = fma(d, d, ss);
+        }
+        b[e] = bf16_bits(v[e]);
+        T[tc4 + e][rr] = (uint16_t)b[e];
+      }
+      if (rm && i < R && j < ldr) {
+        uint2 w;
+        w.x = b[0] | (b[1] << 16);
+        w.y = b[2] | (b[3] << 16);
+        *reinterpret_cast<uint2*>(rm + i * ldr + j) = w;
+      }
+    }
+    __syncthreads();
+    if (tr) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int cc = it * 16 + tr_row;
+        const int64_t j = j0 + cc, i = i0 + tc4;
+        if (j < Ct && i < ldt) {
+          uint2 w;
+          w.x = (uint32_t)T[cc][tc4 + 0] | ((uint32_t)T[cc][tc4 + 1] << 16);
+          w.y = (uint32_t)T[cc][tc4 + 2] | ((uint32_t)T[cc][tc4 + 3] << 16);
+          *reinterpret_cast<uint2*>(tr + j * ldt + i) = w;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (sumsq_part) {
+    const double t = wg_sum_double(ss, red);
+    if (tid == 0) sumsq_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// One pass on the bfloat16 matrix cores: out[p][c] = sum_k M[p][k] Xt[c][k].
+//   M: P x K bf16 (ld ldm, 16-byte aligned rows, zero beyond the logical K),
+//   Xt: Ct x K bf16 (ld ldx), K a multiple of 64, Ct >= gridDim.y * NT * 16.
+// Workgroup: 256 threads, 128 rows of P (32 per wave, two 16-row MFMA tiles)
+// x NT*16 columns, a contiguous range of K walked 64 at a time.  The lane
+// (r, g) of v_mfma_f32_16x16x32_bf16 step h takes the entries
+// k0 + 16 g + 8 h + [0, 8) of its row of M and of its column of X, so each
+// lane reads 32 contiguous bytes of a row per stage; both operands use the
+// same assignment, so the contraction is unchanged.  A goes from HBM straight
+// to registers (prefetched one stage ahead); the sketch stage is shared by
+// the four waves through a double-buffered LDS tile.
+template <int NT, int EPI>
+__global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_bf16(const uint16_t* __restrict__ M, int64_t ldm,
+                                                      const uint16_t* __restrict__ Xt, int64_t ldx,
+                                                      float* out, int64_t ldo, int64_t part_stride,
+                                                      int64_t P, int64_t K, int64_t C,
+                                                      int64_t ksplit, int nsplit) {
+  constexpr int KS = 64;
+  constexpr int XR = NT * 16;
+  constexpr int XP = KS + 8;                 // LDS row pitch (elements): 144 bytes
+  constexpr int XCH = XR * (KS / 8);         // 16-byte chunks per sketch stage
+  constexpr int XIT = (XCH + 255) / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][XR * XP];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int npb = nwg / nsplit;
+  const int split = lid / npb;
+  const int64_t p0 = (int64_t)(lid % npb) * 128;
+  const int64_t c0 = (int64_t)blockIdx.y * XR;
+  const int64_t kb = (int64_t)split * ksplit;
+  const int64_t ke = (kb + ksplit < K) ? kb + ksplit : K;
+
+  const int64_t pa0 = p0 + wave * 32 + r, pa1 = pa0 + 16;
+  const bool ok0 = pa0 < P, ok1 = pa1 < P;
+  const uint16_t* a0 = M + (ok0 ? pa0 : 0) * ldm + g4 * 16;
+  const uint16_t* a1 = M + (ok1 ? pa1 : 0) * ldm + g4 * 16;
+
+  uint4 ra[2][2], rn[2][2];
+  static_assert(XIT <= 4, "sketch stage larger than 4 chunks per thread");
+  uint4 rx0 = {0u, 0u, 0u, 0u}, rx1 = rx0, rx2 = rx0, rx3 = rx0;   // named: kept in VGPRs
+  f32x4 acc[2][NT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // every thread loads (chunks past the tile re-read its last chunk, which
+  // keeps rx in registers: no load sits under a branch); only real chunks
+  // are stored to LDS
+  auto xsrc = [&](int it, int64_t k) __attribute__((always_inline)) {
+    const int q0 = it * 256 + tid;
+    const int q = q0 < XCH ? q0 : XCH - 1;
+    return reinterpret_cast<const uint4*>(Xt + (c0 + (q >> 3)) * ldx + k + (q & 7) * 8);
+  };
+  auto load_x = [&](int64_t k) __attribute__((always_inline)) {
+    rx0 = *xsrc(0, k);
+    if (XIT > 1) rx1 = *xsrc(1, k);
+    if (XIT > 2) rx2 = *xsrc(2, k);
+    if (XIT > 3) rx3 = *xsrc(3, k);
+  };
+  auto xdst = [&](int it, int buf) __attribute__((always_inline)) {
+    const int q = it * 256 + tid;
+    return reinterpret_cast<uint4*>(&Xs[buf][(q >> 3) * XP + (q & 7) * 8]);
+  };
+  auto store_x = [&](int buf) __attribute__((always_inline)) {
+    if (0 * 256 + tid < XCH) *xdst(0, buf) = rx0;
+    if (XIT > 1 && 1 * 256 + tid < XCH) *xdst(1, buf) = rx1;
+    if (XIT > 2 && 2 * 256 + tid < XCH) *xdst(2, buf) = rx2;
+    if (XIT > 3 && 3 * 256 + tid < XCH) *xdst(3, buf) = rx3;
+  };
+  auto load_a = [&](int64_t k, uint4 (&d)[2][2]) __attribute__((always_inline)) {
+    const uint4 z = {0u, 0u, 0u, 0u};
+    d[0][0] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k) : z;
+    d[0][1] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k + 8) : z;
+    d[1][0] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k) : z;
+    d[1][1] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k + 8) : z;
+  };
+  auto compute = [&](int buf, const uint4 (&a)[2][2]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bf16x8 f0 = __builtin_bit_cast(bf16x8, a[0][h]);
+      const bf16x8 f1 = __builtin_bit_cast(bf16x8, a[1][h]);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const bf16x8 b =
+            *reinterpret_cast<const bf16x8*>(&Xs[buf][(j * 16 + r) * XP + g4 * 16 + h * 8]);
+        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, b, acc[0][j], 0, 0, 0);
+        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1, b, acc[1][j], 0, 0, 0);
+      }
+    }
+  };
+
+  // one stage: prefetch stage k + KS, multiply stage k, publish the prefetched
+  // sketch tile.  The two register sets alternate roles (static indexing).
+  auto stage = [&](int64_t k, const uint4 (&cur)[2][2], uint4 (&nxt)[2][2], int buf)
+      __attribute__((always_inline)) {
+    const bool more = k + KS < ke;
+    if (more) {
+      load_x(k + KS);         // issued first: its wait leaves the A loads in flight
+      load_a(k + KS, nxt);
+    }
+    compute(buf, cur);
+    if (more) store_x(buf ^ 1);
+    __syncthreads();
+  };
+  if (kb < ke) {
+    load_x(kb);
+    load_a(kb, ra);
+    store_x(0);
+    __syncthreads();
+    for (int64_t k = kb;;) {
+      stage(k, ra, rn, 0);
+      k += KS;
+      if (k >= ke) break;
+      stage(k, rn, ra, 1);
+      k += KS;
+      if (k >= ke) break;
+    }
+  }
+
+  // acc[t][j][e] is out[p][c], p = p0 + 32 wave + 16 t + 4 g4 + e, c = c0 + 16 j + r
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = p0 + wave * 32 + t * 16 + g4 * 4 + e;
+      if (p >= P) continue;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int64_t c = c0 + j * 16 + r;
+        if (c >= C) continue;
+        if (EPI == EPI_PART)
+          out[(int64_t)split * part_stride + p * ldo + c] = acc[t][j][e];
+        else
+          out[p * ldo + c] = acc[t][j][e];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-scaled FP8 E4M3 (OCP "e4m3fn": bias 7, 3 mantissa bits, largest
+// finite 448, subnormal spacing 2^-9).  Each block of 32 consecutive entries
+// along the contraction index shares a power-of-two scale 2^e (an E8M0 byte
+// e + 127), e the smallest integer with max|x| / 2^e <= 448, at least -127.
+// ---------------------------------------------------------------------------
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// e for a block whose largest magnitude is amax (>= 0, finite): with
+// amax = f 2^E, f in [1, 2), 448 = 1.75 2^8, e = E - 8 when f <= 1.75 and
+// E - 7 otherwise.
+__device__ __forceinline__ int mx_exponent(float amax) {
+  const uint32_t u = __float_as_uint(amax);
+  const int eb = (int)(u >> 23);
+  if (eb == 0) return -127;
+  const int e = eb - 127 - 8 + (((u & 0x7FFFFFu) > 0x600000u) ? 1 : 0);
+  return e < -127 ? -127 : e;
+}
+
+// E4M3 code of y, |y| <= 448, round to nearest even.
+__device__ __forceinline__ uint32_t e4m3_code(float y) {
+  const uint32_t s = (__float_as_uint(y) >> 24) & 0x80u;
+  const float a = fabsf(y);
+  uint32_t c;
+  if (a < 0.015625f) {
+    // below 2^-6: multiples of 2^-9 (8 * 2^-9 = 2^-6 is the code of the
+    // smallest normal, so rounding up into it needs no special case)
+    c = (uint32_t)rintf(a * 512.0f);
+  } else {
+    const uint32_t ua = __float_as_uint(a);
+    const uint32_t E = (ua >> 23) - 120u;                    // biased exponent: 127 - 7
+    const uint32_t m = ua & 0x7FFFFFu;
+    const uint32_t m3 = (m + 0x7FFFFu + ((m >> 20) & 1u)) >> 20;   // 0..8, carry into E
+    c = (E << 3) + m3;
+  }
+  return s | c;
+}
+
+// Largest magnitude over the 8 lanes l with equal l >> 3 (a 32-entry block
+// held as 4 entries per lane).
+__device__ __forceinline__ float max8(float v) {
+  v = fmaxf(v, __shfl_xor(v, 1, 64));
+  v = fmaxf(v, __shfl_xor(v, 2, 64));
+  v = fmaxf(v, __shfl_xor(v, 4, 64));
+  return v;
+}
+
+// 4 codes of v[0..3] under the block exponent e, packed little-endian.
+__device__ __forceinline__ uint32_t pack4_e4m3(const float* v, int e) {
+  uint32_t w = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w |= e4m3_code(ldexpf(v[q], -e)) << (8 * q);
+  return w;
+}
+
+// src: R x C fp32 (ld lds).  Writes, for the 64 x 64 tiles this workgroup
+// owns (same tiling as k_cvt_bf16),
+//   rm/rsc (nullable): R x ldr codes and R x ldr/32 scales, blocks of 32
+//     along each row (j), zero codes and scale byte 0 past C;
+//   tr/tsc (nullable): Ct x ldt codes and Ct x ldt/32 scales of src^T,
+//     blocks of 32 along i, zero past R and for rows j >= C.
+__global__ __launch_bounds__(256) void k_cvt_fp8(const float* __restrict__ src, int64_t lds,
+                                                 int64_t R, int64_t C, uint8_t* rm, uint8_t* rsc,
+                                                 int64_t ldr, uint8_t* tr, uint8_t* tsc,
+                                                 int64_t ldt, int64_t Ct, int64_t ncol_tiles) {
+  __shared__ float T[64][64 + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * 64;
+  const int tr_row = tid >> 4, tc4 = (tid & 15) * 4;
+  const bool svec = ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) && ((lds & 3) == 0);
+  for (int64_t tj = blockIdx.x; tj < ncol_tiles; tj += gridDim.x) {
+    const int64_t j0 = tj * 64;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int rr = it * 16 + tr_row;
+      const int64_t i = i0 + rr, j = j0 + tc4;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (i < R) {
+        const float* sp = src + i * lds + j;
+        if (svec && j + 3 < C) {
+          const f32x4 q = *reinterpret_cast<const f32x4*>(sp);
+          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (j + e < C) v[e] = sp[e];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) T[tc4 + e][rr] = v[e];
+      if (rm) {
+        float am = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+        am = max8(am);
+        const int e = mx_exponent(am);
+        if (i < R && j < ldr) {
+          *reinterpret_cast<uint32_t*>(rm + i * ldr + j) = pack4_e4m3(v, e);
+          if ((tid & 7) == 0) rsc[i * (ldr / 32) + j / 32] = (uint8_t)(e + 127);
+        }
+      }
+    }
+    __syncthreads();
+    if (tr) {
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int cc = it * 16 + tr_row;
+        const int64_t j = j0 + cc, i = i0 + tc4;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = T[cc][tc4 + e];
+        float am = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+        am = max8(am);
+        const int e = mx_exponent(am);
+        if (j < Ct && i < ldt) {
+          *reinterpret_cast<uint32_t*>(tr + j * ldt + i) = pack4_e4m3(v, e);
+          if ((tid & 7) == 0) tsc[j * (ldt / 32) + i / 32] = (uint8_t)(e + 127);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One pass on the FP8 matrix cores with per-block scales:
+// out[p][c] = sum_k (M[p][k] 2^sM[p][k/32]) (Xt[c][k] 2^sX[c][k/32]).
+//   M: P x K codes (ld ldm, K a multiple of 128), Ms: P x K/32 scale bytes;
+//   Xt: Ct x K codes (ld ldx), Xs: Ct x K/32.
+// v_mfma_scale_f32_16x16x128_f8f6f4: lane (r, g) supplies row r's 32 codes
+// k0 + 32 g + [0, 32) (one scale block) with that block's scale, for both
+// operands.  Same decomposition as k_pass_bf16 with 128 of K per stage.
+template <int NT, int EPI>
+__global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8_t* __restrict__ M,
+                                                     const uint8_t* __restrict__ Ms, int64_t ldm,
+                                                     const uint8_t* __restrict__ Xt,
+                                                     const uint8_t* __restrict__ Xsc, int64_t ldx,
+                                                     float* out, int64_t ldo, int64_t part_stride,
+                                                     int64_t P, int64_t K, int64_t C,
+                                                     int64_t ksplit, int nsplit) {
+  constexpr int KS = 128;
+  constexpr int XR = NT * 16;
+  constexpr int XP = KS + 16;                // LDS row pitch (bytes)
+  constexpr int XCH = XR * (KS / 16);        // 16-byte chunks per sketch stage
+  constexpr int XIT = (XCH + 255) / 256;
+  static_assert(XIT <= 4, "sketch stage larger than 4 chunks per thread");
+  __shared__ __attribute__((aligned(16))) uint8_t Xs[2][XR * XP];
+  __shared__ uint32_t Xss[2][XR];           // the 4 scale bytes of a sketch row per stage
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int npb = nwg / nsplit;
+  const int split = lid / npb;
+  const int64_t p0 = (int64_t)(lid % npb) * 128;
+  const int64_t c0 = (int64_t)blockIdx.y * XR;
+  const int64_t kb = (int64_t)split * ksplit;
+  const int64_t ke = (kb + ksplit < K) ? kb + ksplit : K;
+  const int64_t lds_ = ldm / 32, ldxs = ldx / 32;
+
+  const int64_t pa0 = p0 + wave * 32 + r, pa1 = pa0 + 16;
+  const bool ok0 = pa0 < P, ok1 = pa1 < P;
+  const uint8_t* a0 = M + (ok0 ? pa0 : 0) * ldm + g4 * 32;
+  const uint8_t* a1 = M + (ok1 ? pa1 : 0) * ldm + g4 * 32;
+  const uint8_t* s0 = Ms + (ok0 ? pa0 : 0) * lds_ + g4;
+  const uint8_t* s1 = Ms + (ok1 ? pa1 : 0) * lds_ + g4;
+
+  uint4 ra[2][2], rn[2][2];
+  uint32_t sa[2], sn[2];
+  uint4 rx0 = {0u, 0u, 0u, 0u}, rx1 = rx0, rx2 = rx0, rx3 = rx0;
+  uint32_t rxs = 0;
+  f32x4 acc[2][NT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto xsrc = [&](int it, int64_t k) __attribute__((always_inline)) {
+    const int q0 = it * 256 + tid;
+    const int q = q0 < XCH ? q0 : XCH - 1;
+    return reinterpret_cast<const uint4*>(Xt + (c0 + (q >> 3)) * ldx + k + (q & 7) * 16);
+  };
+  auto load_x = [&](int64_t k) __attribute__((always_inline)) {
+    rx0 = *xsrc(0, k);
+    if (XIT > 1) rx1 = *xsrc(1, k);
+    if (XIT > 2) rx2 = *xsrc(2, k);
+    if (XIT > 3) rx3 = *xsrc(3, k);
+    const int row = tid < XR ? tid : XR - 1;
+    rxs = *reinterpret_cast<const uint32_t*>(Xsc + (c0 + row) * ldxs + k / 32);
+  };
+  auto xdst = [&](int it, int buf) __attribute__((always_inline)) {
+    const int q = it * 256 + tid;
+    return reinterpret_cast<uint4*>(&Xs[buf][(q >> 3) * XP + (q & 7) * 16]);
+  };
+  auto store_x = [&](int buf) __attribute__((always_inline)) {
+    if (0 * 256 + tid < XCH) *xdst(0, buf) = rx0;
+    if (XIT > 1 && 1 * 256 + tid < XCH) *xdst(1, buf) = rx1;
+    if (XIT > 2 && 2 * 256 + tid < XCH) *xdst(2, buf) = rx2;
+    if (XIT > 3 && 3 * 256 + tid < XCH) *xdst(3, buf) = rx3;
+    if (tid < XR) Xss[buf][tid] = rxs;
+  };
+  auto load_a = [&](int64_t k, uint4 (&d)[2][2], uint32_t (&sc)[2]) __attribute__((always_inline)) {
+    const uint4 z = {0u, 0u, 0u, 0u};
+    d[0][0] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k) : z;
+    d[0][1] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k + 16) : z;
+    d[1][0] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k) : z;
+    d[1][1] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k + 16) : z;
+    sc[0] = ok0 ? (uint32_t)s0[k / 32] : 0u;
+    sc[1] = ok1 ? (uint32_t)s1[k / 32] : 0u;
+  };
+  auto compute = [&](int buf, const uint4 (&a)[2][2], const uint32_t (&sc)[2])
+      __attribute__((always_inline)) {
+    i32x8 fa[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      fa[t][0] = (int)a[t][0].x; fa[t][1] = (int)a[t][0].y; fa[t][2] = (int)a[t][0].z;
+      fa[t][3] = (int)a[t][0].w; fa[t][4] = (int)a[t][1].x; fa[t][5] = (int)a[t][1].y;
+      fa[t][6] = (int)a[t][1].z; fa[t][7] = (int)a[t][1].w;
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const uint8_t* bp = &Xs[buf][(j * 16 + r) * XP + g4 * 32];
+      const uint4 b0 = *reinterpret_cast<const uint4*>(bp);
+      const uint4 b1 = *reinterpret_cast<const uint4*>(bp + 16);
+      i32x8 fb;
+      fb[0] = (int)b0.x; fb[1] = (int)b0.y; fb[2] = (int)b0.z; fb[3] = (int)b0.w;
+      fb[4] = (int)b1.x; fb[5] = (int)b1.y; fb[6] = (int)b1.z; fb[7] = (int)b1.w;
+      const int bs = (int)((Xss[buf][j * 16 + r] >> (8 * g4)) & 0xFFu);
+      acc[0][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[0], fb, acc[0][j], 0, 0, 0,
+                                                                   (int)sc[0], 0, bs);
+      acc[1][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[1], fb, acc[1][j], 0, 0, 0,
+                                                                   (int)sc[1], 0, bs);
+    }
+  };
+  auto stage = [&](int64_t k, const uint4 (&cur)[2][2], const uint32_t (&cs)[2],
+                   uint4 (&nxt)[2][2], uint32_t (&ns)[2], int buf) __attribute__((always_inline)) {
+    const bool more = k + KS < ke;
+    if (more) {
+      load_x(k + KS);
+      load_a(k + KS, nxt, ns);
+    }
+    compute(buf, cur, cs);
+    if (more) store_x(buf ^ 1);
+    __syncthreads();
+  };
+  if (kb < ke) {
+    load_x(kb);
+    load_a(kb, ra, sa);
+    store_x(0);
+    __syncthreads();
+    for (int64_t k = kb;;) {
+      stage(k, ra, sa, rn, sn, 0);
+      k += KS;
+      if (k >= ke) break;
+      stage(k, rn, sn, ra, sa, 1);
+      k += KS;
+      if (k >= ke) break;
+    }
+  }
+
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = p0 + wave * 32 + t * 16 + g4 * 4 + e;
+      if (p >= P) continue;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int64_t c = c0 + j * 16 + r;
+        if (c >= C) continue;
+        if (EPI == EPI_PART)
+          out[(int64_t)split * part_stride + p * ldo + c] = acc[t][j][e];
+        else
+          out[p * ldo + c] = acc[t][j][e];
+      }
+    }
+  }
+}
+
+template <int EPI>
+hipError_t launch_fp8_nt(int nt, dim3 grid, const uint8_t* M, const uint8_t* Ms, int64_t ldm,
+                         const uint8_t* Xt, const uint8_t* Xsc, int64_t ldx, float* out,
+                         int64_t ldo, int64_t ps, int64_t P, int64_t K, int64_t C, int64_t ks,
+                         int ns, hipStream_t s) {
+  switch (nt) {
+#define PLU_F8_CASE(N)                                                                     \
+  case N:                                                                                  \
+    hipLaunchKernelGGL((k_pass_fp8<N, EPI>), grid, dim3(256), 0, s, M, Ms, ldm, Xt, Xsc, \
+                       ldx, out, ldo, ps, P, K, C, ks, ns);                                \
+    break;
+    PLU_F8_CASE(1) PLU_F8_CASE(2) PLU_F8_CASE(3) PLU_F8_CASE(4)
+    PLU_F8_CASE(5) PLU_F8_CASE(6) PLU_F8_CASE(7) PLU_F8_CASE(8)
+#undef PLU_F8_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int EPI>
+hipError_t launch_bf16_nt(int nt, dim3 grid, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
+                          int64_t ldx, float* out, int64_t ldo, int64_t ps, int64_t P, int64_t K,
+                          int64_t C, int64_t ks, int ns, hipStream_t s) {
+  switch (nt) {
+#define PLU_BF_CASE(N)                                                                      \
+  case N:                                                                                   \
+    hipLaunchKernelGGL((k_pass_bf16<N, EPI>), grid, dim3(256), 0, s, M, ldm, Xt, ldx, out, \
+                       ldo, ps, P, K, C, ks, ns);                                           \
+    break;
+    PLU_BF_CASE(1) PLU_BF_CASE(2) PLU_BF_CASE(3) PLU_BF_CASE(4)
+    PLU_BF_CASE(5) PLU_BF_CASE(6) PLU_BF_CASE(7) PLU_BF_CASE(8)
+#undef PLU_BF_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cvt_bf16(const float* src, int64_t lds, int64_t R, int64_t C, uint16_t* rm,
+                           int64_t ldr, uint16_t* tr, int64_t ldt, int64_t Ct, double* sumsq_part,
+                           int64_t* nparts, hipStream_t s) {
+  if ((rm && (ldr % 64 != 0 || ldr < C)) || (tr && (ldt % 64 != 0 || ldt < R || Ct < C)))
+    return hipErrorInvalidValue;
+  const int64_t rows = std::max<int64_t>(R, tr ? ldt : 0);
+  const int64_t cols = std::max<int64_t>(rm ? ldr : 0, tr ? Ct : 0);
+  const int64_t bands = (rows + 63) / 64, ctiles = (cols + 63) / 64;
+  const int groups = (int)std::min<int64_t>(ctiles, 8);
+  if (nparts) *nparts = bands * groups;
+  hipLaunchKernelGGL(k_cvt_bf16, dim3((unsigned)groups, (unsigned)bands), dim3(256), 0, s, src,
+                     lds, R, C, rm, ldr, tr, ldt, Ct, ctiles, sumsq_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_bf16(int epi, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
+                            int64_t ldx, float* out, int64_t ldo, int64_t part_stride, int64_t P,
+                            int64_t K, int64_t C, const GemmPlan& pl, hipStream_t s) {
+  if (K % 64 != 0 || pl.rsplit % 64 != 0 || (ldm & 7) || (ldx & 7) ||
+      (reinterpret_cast<uintptr_t>(M) & 15u) || (reinterpret_cast<uintptr_t>(Xt) & 15u))
+    return hipErrorInvalidValue;
+  dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
+  if (epi == EPI_PART)
+    return launch_bf16_nt<EPI_PART>(pl.nt, grid, M, ldm, Xt, ldx, out, ldo, part_stride, P, K, C,
+                                    pl.rsplit, pl.nsplit, s);
+  if (epi == EPI_STORE)
+    return launch_bf16_nt<EPI_STORE>(pl.nt, grid, M, ldm, Xt, ldx, out, ldo, 0, P, K, C,
+                                     pl.rsplit, pl.nsplit, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cvt_fp8(const float* src, int64_t lds, int64_t R, int64_t C, uint8_t* rm,
+                          uint8_t* rsc, int64_t ldr, uint8_t* tr, uint8_t* tsc, int64_t ldt,
+                          int64_t Ct, hipStream_t s) {
+  if ((rm && (ldr % 128 != 0 || ldr < C || !rsc)) ||
+      (tr && (ldt % 128 != 0 || ldt < R || Ct < C || !tsc)))
+    return hipErrorInvalidValue;
+  const int64_t rows = std::max<int64_t>(R, tr ? ldt : 0);
+  const int64_t cols = std::max<int64_t>(rm ? ldr : 0, tr ? Ct : 0);
+  const int64_t bands = (rows + 63) / 64, ctiles = (cols + 63) / 64;
+  const int groups = (int)std::min<int64_t>(ctiles, 8);
+  hipLaunchKernelGGL(k_cvt_fp8, dim3((unsigned)groups, (unsigned)bands), dim3(256), 0, s, src,
+                     lds, R, C, rm, rsc, ldr, tr, tsc, ldt, Ct, ctiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_fp8(int epi, const uint8_t* M, const uint8_t* Ms, int64_t ldm,
+                           const uint8_t* Xt, const uint8_t* Xsc, int64_t ldx, float* out,
+                           int64_t ldo, int64_t part_stride, int64_t P, int64_t K, int64_t C,
+                           const GemmPlan& pl, hipStream_t s) {
+  if (K % 128 != 0 || pl.rsplit % 128 != 0 || (ldm % 128) || (ldx % 128) ||
+      (reinterpret_cast<uintptr_t>(M) & 15u) || (reinterpret_cast<uintptr_t>(Xt) & 15u) ||
+      (reinterpret_cast<uintptr_t>(Xsc) & 3u))
+    return hipErrorInvalidValue;
+  dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
+  if (epi == EPI_PART)
+    return launch_fp8_nt<EPI_PART>(pl.nt, grid, M, Ms, ldm, Xt, Xsc, ldx, out, ldo, part_stride,
+                                   P, K, C, pl.rsplit, pl.nsplit, s);
+  if (epi == EPI_STORE)
+    return launch_fp8_nt<EPI_STORE>(pl.nt, grid, M, Ms, ldm, Xt, Xsc, ldx, out, ldo, 0, P, K, C,
+                                    pl.rsplit, pl.nsplit, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace plu

@@ -28,14 +28,17 @@ __device__ __forceinline__ float unit_open0(uint32_t x) {
   return (float)((x >> 8) + 1u) * 5.9604644775390625e-8f;
 }
 
-__global__ __launch_bounds__(256) void k_gaussian(float* out, int64_t ldo, int64_t rows,
-                                                 int64_t cols, uint64_t seed) {
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = rows * cols;
+struct GaussArgs {
+  float* out; int64_t ldo, rows, cols; uint64_t seed;
+};
+
+__device__ void b_gaussian(const GaussArgs& a, const Grid& gr) {
+  const int64_t g = (int64_t)gr.bx * 256 + threadIdx.x;
+  const int64_t total = a.rows * a.cols;
   const int64_t e0 = g * 4;
   if (e0 >= total) return;
   uint32_t c[4] = {(uint32_t)g, (uint32_t)((uint64_t)g >> 32), 0u, 0u};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
   float z[4];
   const float two_pi = 6.2831853071795864769f;
   {
@@ -54,41 +57,46 @@ __global__ __launch_bounds__(256) void k_gaussian(float* out, int64_t ldo, int64
   for (int t = 0; t < 4; ++t) {
     const int64_t e = e0 + t;
     if (e < total) {
-      const int64_t i = e / cols, j = e - i * cols;
-      out[i * ldo + j] = z[t];
+      const int64_t i = e / a.cols, j = e - i * a.cols;
+      a.out[i * a.ldo + j] = z[t];
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_copy_pad(const float* src, int64_t lds, float* dst,
-                                                 int64_t ldd, int64_t rows, int64_t cols,
-                                                 int64_t cols_pad) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= rows * cols_pad) return;
-  const int64_t i = e / cols_pad, j = e - i * cols_pad;
-  dst[i * ldd + j] = (j < cols) ? src[i * lds + j] : 0.f;
+struct CopyPadArgs {
+  const float* src; int64_t lds; float* dst; int64_t ldd, rows, cols, cols_pad;
+};
+
+__device__ void b_copy_pad(const CopyPadArgs& a, const Grid& gr) {
+  const int64_t e = (int64_t)gr.bx * 256 + threadIdx.x;
+  if (e >= a.rows * a.cols_pad) return;
+  const int64_t i = e / a.cols_pad, j = e - i * a.cols_pad;
+  a.dst[i * a.ldd + j] = (j < a.cols) ? a.src[i * a.lds + j] : 0.f;
 }
 
 // U[t][r] = V[rowidx[r]][t] for t < k, r < nrows (32 x 32 LDS tiles).
-__global__ __launch_bounds__(256) void k_transpose_gather(const float* V, int64_t ldv,
-                                                         const int32_t* rowidx, int64_t nrows,
-                                                         int k, float* U, int64_t ldu) {
+struct TGatherArgs {
+  const float* V; int64_t ldv; const int32_t* rowidx; int64_t nrows; int k; float* U;
+  int64_t ldu;
+};
+
+__device__ void b_transpose_gather(const TGatherArgs& a, const Grid& gr) {
   __shared__ float tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  const int t0 = blockIdx.y * 32;
+  const int64_t r0 = (int64_t)gr.bx * 32;
+  const int t0 = gr.by * 32;
 #pragma unroll
   for (int yy = 0; yy < 4; ++yy) {
     const int64_t r = r0 + ty + 8 * yy;
     const int t = t0 + tx;
-    if (r < nrows && t < k) tile[ty + 8 * yy][tx] = V[(int64_t)rowidx[r] * ldv + t];
+    if (r < a.nrows && t < a.k) tile[ty + 8 * yy][tx] = a.V[(int64_t)a.rowidx[r] * a.ldv + t];
   }
   __syncthreads();
 #pragma unroll
   for (int yy = 0; yy < 4; ++yy) {
     const int t = t0 + ty + 8 * yy;
     const int64_t r = r0 + tx;
-    if (t < k && r < nrows) U[(int64_t)t * ldu + r] = tile[tx][ty + 8 * yy];
+    if (t < a.k && r < a.nrows) a.U[(int64_t)t * a.ldu + r] = tile[tx][ty + 8 * yy];
   }
 }
 
@@ -99,36 +107,40 @@ __global__ __launch_bounds__(256) void k_transpose_gather(const float* V, int64_
 // norm of the corresponding basis column (G(:,j) = A v_j): the indicator of
 // Thm 4.3 for the column-normalized basis, which removes the first-order
 // effect of storing an orthonormal V in float32.
-__global__ __launch_bounds__(256) void k_rank_rule(const double* colsq_part, int nblk, int l,
-                                                  const double* vsq_part, int nvblk,
-                                                  const double* normA2p, double eps, int b,
-                                                  int col_mode, int32_t* kout, double* Eout,
-                                                  int32_t* tol, double* colnorm) {
+struct RankArgs {
+  const double* colsq_part; int nblk, l; const double* vsq_part; int nvblk;
+  const double* normA2p; double eps; int b, col_mode; int32_t* kout; double* Eout;
+  int32_t* tol; double* colnorm;
+};
+
+__device__ void b_rank_rule(const RankArgs& a, const Grid& gr) {
+  (void)gr;
   extern __shared__ double cn[];
+  const int l = a.l;
   for (int j = threadIdx.x; j < l; j += 256) {
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += colsq_part[(int64_t)k * l + j];
-    if (vsq_part) {
+    for (int k = 0; k < a.nblk; ++k) s += a.colsq_part[(int64_t)k * l + j];
+    if (a.vsq_part) {
       double v = 0.0;
-      for (int k = 0; k < nvblk; ++k) v += vsq_part[(int64_t)k * l + j];
+      for (int k = 0; k < a.nvblk; ++k) v += a.vsq_part[(int64_t)k * l + j];
       if (v > 0.0) s /= v;
     }
     cn[j] = s;
-    if (colnorm) colnorm[j] = s;
+    if (a.colnorm) a.colnorm[j] = s;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double nA2 = *normA2p;
+  const double nA2 = *a.normA2p;
   int k = l, ok = 0;
   double E = nA2;
   if (nA2 == 0.0) {
     k = 0;
     ok = 1;
   } else {
-    const double acc = eps * eps * nA2;
-    for (int t1 = 0; t1 < l && !ok; t1 += b) {
-      const int t2 = (t1 + b < l) ? t1 + b : l;
-      if (col_mode) {
+    const double acc = a.eps * a.eps * nA2;
+    for (int t1 = 0; t1 < l && !ok; t1 += a.b) {
+      const int t2 = (t1 + a.b < l) ? t1 + a.b : l;
+      if (a.col_mode) {
         for (int j = t1; j < t2; ++j) {
           E -= cn[j];
           if (E <= acc) {
@@ -148,19 +160,27 @@ __global__ __launch_bounds__(256) void k_rank_rule(const double* colsq_part, int
       }
     }
   }
-  *kout = k;
-  *Eout = E;
-  *tol = ok;
+  *a.kout = k;
+  *a.Eout = E;
+  *a.tol = ok;
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = v;
+struct FillArgs {
+  uint32_t* p; size_t n; uint32_t v;
+};
+
+__device__ void b_fill_u32(const FillArgs& a, const Grid& gr) {
+  const size_t i = (size_t)gr.bx * 256 + threadIdx.x;
+  if (i < a.n) a.p[i] = a.v;
 }
 
-__global__ __launch_bounds__(256) void k_iota(int32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = (int32_t)i;
+struct IotaArgs {
+  int32_t* p; int64_t n;
+};
+
+__device__ void b_iota(const IotaArgs& a, const Grid& gr) {
+  const int64_t i = (int64_t)gr.bx * 256 + threadIdx.x;
+  if (i < a.n) a.p[i] = (int32_t)i;
 }
 
 }  // namespace
@@ -168,24 +188,23 @@ __global__ __launch_bounds__(256) void k_iota(int32_t* p, int64_t n) {
 hipError_t launch_gaussian(float* out, int64_t ldo, int64_t rows, int64_t cols, uint64_t seed,
                            hipStream_t s) {
   const int64_t nblk4 = (rows * cols + 3) / 4;
-  hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((nblk4 + 255) / 256)), dim3(256), 0, s, out, ldo,
-                     rows, cols, seed);
-  return hipGetLastError();
+  return dispatch<GaussArgs, b_gaussian, 256>(GaussArgs{out, ldo, rows, cols, seed},
+                                             dim3((unsigned)((nblk4 + 255) / 256)), 0, s);
 }
 
 hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows,
                            int64_t cols, int64_t cols_pad, hipStream_t s) {
   const int64_t tot = rows * cols_pad;
-  hipLaunchKernelGGL(k_copy_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, lds,
-                     dst, ldd, rows, cols, cols_pad);
-  return hipGetLastError();
+  return dispatch<CopyPadArgs, b_copy_pad, 256>(
+      CopyPadArgs{src, lds, dst, ldd, rows, cols, cols_pad}, dim3((unsigned)((tot + 255) / 256)),
+      0, s);
 }
 
 hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,
                                    int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s) {
   dim3 grid((unsigned)((nrows + 31) / 32), (unsigned)((k + 31) / 32));
-  hipLaunchKernelGGL(k_transpose_gather, grid, dim3(256), 0, s, V, ldv, rowidx, nrows, k, U, ldu);
-  return hipGetLastError();
+  return dispatch<TGatherArgs, b_transpose_gather, 256>(
+      TGatherArgs{V, ldv, rowidx, nrows, k, U, ldu}, grid, 0, s);
 }
 
 hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,
@@ -193,19 +212,20 @@ hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const dou
                             int32_t* kout, double* Eout, int32_t* tol, double* colnorm,
                             hipStream_t s) {
   if (l > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rank_rule, dim3(1), dim3(256), (size_t)l * sizeof(double), s, colsq_part,
-                     nblk, l, vsq_part, nvblk, normA2, eps, b, col_mode, kout, Eout, tol, colnorm);
-  return hipGetLastError();
+  return dispatch<RankArgs, b_rank_rule, 256>(
+      RankArgs{colsq_part, nblk, l, vsq_part, nvblk, normA2, eps, b, col_mode, kout, Eout, tol,
+               colnorm},
+      dim3(1), (size_t)l * sizeof(double), s);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
+  return dispatch<FillArgs, b_fill_u32, 256>(FillArgs{p, n, v},
+                                            dim3((unsigned)((n + 255) / 256)), 0, s);
 }
 
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
-  return hipGetLastError();
+  return dispatch<IotaArgs, b_iota, 256>(IotaArgs{p, n}, dim3((unsigned)((n + 255) / 256)), 0,
+                                         s);
 }
 
 }  // namespace plu

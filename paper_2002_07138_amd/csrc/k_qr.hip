@@ -21,8 +21,16 @@ namespace {
 constexpr int QB = 128;   // column block of the Gram-Schmidt sweep
 
 // part[chunk][a][b] = sum over the chunk's rows of V[i][a] V[i][b] (float64).
-__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ V, int64_t ldv, int64_t M,
-                                             int bw, int64_t rows_per_chunk, double* part) {
+struct GramArgs {
+  const float* V; int64_t ldv, M; int bw; int64_t rows_per_chunk; double* part;
+};
+
+__device__ void b_gram(const GramArgs& ga, const Grid& gr) {
+  const float* __restrict__ V = ga.V;
+  const int64_t ldv = ga.ldv, M = ga.M;
+  const int bw = ga.bw;
+  const int64_t rows_per_chunk = ga.rows_per_chunk;
+  double* part = ga.part;
   __shared__ float S[64][QB + 1];
   const int t = threadIdx.x;
   const int ta = t >> 4, tb = t & 15;
@@ -31,7 +39,7 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ V, int64
   for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r0 = (int64_t)gr.bx * rows_per_chunk;
   const int64_t r1 = (r0 + rows_per_chunk < M) ? r0 + rows_per_chunk : M;
   for (int64_t rb = r0; rb < r1; rb += 64) {
     __syncthreads();
@@ -53,7 +61,7 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ V, int64
         for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
     }
   }
-  double* out = part + (int64_t)blockIdx.x * bw * bw;
+  double* out = part + (int64_t)gr.bx * bw * bw;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int a = ta + 16 * i;
@@ -66,9 +74,15 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ V, int64
   }
 }
 
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int nchunk, int bw,
-                                                    double* W) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+struct GramReduceArgs {
+  const double* part; int nchunk, bw; double* W;
+};
+
+__device__ void b_gram_reduce(const GramReduceArgs& ga, const Grid& gr) {
+  const double* part = ga.part;
+  const int nchunk = ga.nchunk, bw = ga.bw;
+  double* W = ga.W;
+  const int e = gr.bx * 256 + threadIdx.x;
   if (e >= bw * bw) return;
   // eight independent partial sums keep eight loads in flight; fixed order
   double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -88,8 +102,18 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int nch
 // (upper triangular, bw x bw, leading dimension ldr) and, when Rinv64 is set,
 // as float64.  The column being eliminated is copied to its own array so the
 // trailing update reads and writes different LDS objects.
-__global__ __launch_bounds__(256) void k_chol_inv(const double* W, int bw, float* Rinv, int64_t ldr,
-                                                 double* Rinv64, int32_t* status) {
+struct CholArgs {
+  const double* W; int bw; float* Rinv; int64_t ldr; double* Rinv64; int32_t* status;
+};
+
+__device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
+  (void)gr;
+  const double* W = ca.W;
+  const int bw = ca.bw;
+  float* Rinv = ca.Rinv;
+  const int64_t ldr = ca.ldr;
+  double* Rinv64 = ca.Rinv64;
+  int32_t* status = ca.status;
   __shared__ double S[QB][QB + 1];
   __shared__ double cj[QB];
   const int t = threadIdx.x;
@@ -153,10 +177,19 @@ constexpr int APPLY_ROWS = 64;
 constexpr size_t APPLY_LDS = (size_t)QB * QB * sizeof(float) + QB * sizeof(double) +
                              (size_t)APPLY_ROWS * (QB + 1) * sizeof(float);
 
-__global__ __launch_bounds__(512) void k_apply_rinv64(const float* __restrict__ src, int64_t lds,
-                                                     int64_t M, int bw,
-                                                     const double* __restrict__ rinv,
-                                                     int64_t ldr, float* dst, int64_t ldd) {
+struct ApplyArgs {
+  const float* src; int64_t lds, M; int bw; const double* rinv; int64_t ldr; float* dst;
+  int64_t ldd;
+};
+
+__device__ void b_apply_rinv64(const ApplyArgs& aa, const Grid& gr) {
+  const float* __restrict__ src = aa.src;
+  const int64_t lds = aa.lds, M = aa.M;
+  const int bw = aa.bw;
+  const double* __restrict__ rinv = aa.rinv;
+  const int64_t ldr = aa.ldr;
+  float* dst = aa.dst;
+  const int64_t ldd = aa.ldd;
   extern __shared__ double smem[];
   double* Dg = smem;                                           // [QB] diagonal, float64
   float* R = reinterpret_cast<float*>(smem + QB);              // [QB][QB]
@@ -166,7 +199,7 @@ __global__ __launch_bounds__(512) void k_apply_rinv64(const float* __restrict__ 
     for (int c = t & 31; c < QB; c += 32)
       R[r * QB + c] = (c < bw && c != r) ? (float)rinv[(int64_t)r * ldr + c] : 0.f;
   if (t < bw) Dg[t] = rinv[(int64_t)t * ldr + t];
-  const int64_t r0 = (int64_t)blockIdx.x * APPLY_ROWS;
+  const int64_t r0 = (int64_t)gr.bx * APPLY_ROWS;
   for (int rr = t >> 5; rr < APPLY_ROWS; rr += 16) {
     const int64_t row = r0 + rr;
     for (int c = t & 31; c < bw; c += 32) Vs[rr * (QB + 1) + c] = (row < M) ? src[row * lds + c] : 0.f;
@@ -218,27 +251,23 @@ hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float*
   int64_t rpc = (M + nchunk - 1) / nchunk;
   rpc = ((rpc + 63) / 64) * 64;
   nchunk = (int)((M + rpc - 1) / rpc);
-  hipLaunchKernelGGL(k_gram, dim3(nchunk), dim3(256), 0, s, src, lds, M, bw, rpc, qw.gram_part);
   hipError_t e;
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((bw * bw + 255) / 256), dim3(256), 0, s, qw.gram_part,
-                     nchunk, bw, qw.gram);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, qw.gram, bw, qw.rinv, (int64_t)QB,
-                     fp64_apply ? qw.rinv64 : nullptr, qw.status);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = dispatch<GramArgs, b_gram, 256>(GramArgs{src, lds, M, bw, rpc, qw.gram_part},
+                                           dim3(nchunk), 0, s)) != hipSuccess)
+    return e;
+  if ((e = dispatch<GramReduceArgs, b_gram_reduce, 256>(
+           GramReduceArgs{qw.gram_part, nchunk, bw, qw.gram}, dim3((bw * bw + 255) / 256), 0, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = dispatch<CholArgs, b_chol_inv, 256>(
+           CholArgs{qw.gram, bw, qw.rinv, (int64_t)QB, fp64_apply ? qw.rinv64 : nullptr,
+                    qw.status},
+           dim3(1), 0, s)) != hipSuccess)
+    return e;
   if (fp64_apply) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_rinv64),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)APPLY_LDS)) !=
-          hipSuccess)
-        return e;
-      attr_set = true;
-    }
-    hipLaunchKernelGGL(k_apply_rinv64, dim3((unsigned)((M + APPLY_ROWS - 1) / APPLY_ROWS)),
-                       dim3(512), APPLY_LDS, s, src, lds, M, bw, qw.rinv64, (int64_t)QB, dst, ldd);
-    return hipGetLastError();
+    return dispatch<ApplyArgs, b_apply_rinv64, 512>(
+        ApplyArgs{src, lds, M, bw, qw.rinv64, (int64_t)QB, dst, ldd},
+        dim3((unsigned)((M + APPLY_ROWS - 1) / APPLY_ROWS)), APPLY_LDS, s);
   }
   GemmArgs g;
   g.A = src; g.lda = lds;

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "plu_launch.h"
+
 namespace plu {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -38,6 +40,8 @@ struct GemmArgs {
   double* resid_part = nullptr;
   // set by launch_gemm: rows of A / X start 16-byte aligned (vector loads allowed)
   int avec = 0, xvec = 0;
+  // grouped form only: direction, column tiles per block
+  int mode = 0, nt = 0;
 };
 
 constexpr int GEMM_BP = 128;   // rows of the kept dimension per pass workgroup (2 tiles per wave)
@@ -50,7 +54,10 @@ struct GemmPlan {
   int pblocks, cblocks, nt, nsplit;
   int64_t rsplit;
 };
-GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wgs);
+// kalign: the split length is a multiple of it (the reduction depth of one
+// stage of the kernel that runs the plan).
+GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wgs,
+                   int kalign = GEMM_BK);
 hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const GemmPlan& pl,
                        hipStream_t s);
 hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit,
@@ -59,8 +66,33 @@ hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nspl
 hipError_t launch_sum_doubles(const double* in, int64_t n, double* out, hipStream_t s);
 hipError_t launch_sumsq_matrix(const float* A, int64_t lda, int64_t m, int64_t n,
                                double* part, int nblocks, hipStream_t s);
-hipError_t launch_to_bf16(const float* src, int64_t lds, uint16_t* dst, int64_t ldd,
-                          int64_t rows, int64_t cols, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Precision form of the passes (k_lowp.hip).
+// ---------------------------------------------------------------------------
+// bfloat16 copies of an R x C fp32 matrix: row-major (rm, ld ldr) and/or
+// transposed (tr, Ct x ldt), zero-padded; ldr and ldt multiples of 64.
+// Optional float64 sum-of-squares partials (count returned in *nparts).
+hipError_t launch_cvt_bf16(const float* src, int64_t lds, int64_t R, int64_t C, uint16_t* rm,
+                           int64_t ldr, uint16_t* tr, int64_t ldt, int64_t Ct, double* sumsq_part,
+                           int64_t* nparts, hipStream_t s);
+// Block-scaled FP8 E4M3 copies (blocks of 32 along the contraction index,
+// E8M0 scale bytes): rm/rsc row-major R x ldr (+ R x ldr/32 scales),
+// tr/tsc transposed Ct x ldt (+ Ct x ldt/32); ldr, ldt multiples of 128.
+hipError_t launch_cvt_fp8(const float* src, int64_t lds, int64_t R, int64_t C, uint8_t* rm,
+                          uint8_t* rsc, int64_t ldr, uint8_t* tr, uint8_t* tsc, int64_t ldt,
+                          int64_t Ct, hipStream_t s);
+// out = sum_k dequant(M)[p][k] dequant(Xt)[c][k] on the scaled FP8 MFMA
+// (K a multiple of 128; plan from plan_gemm(P, K, C, ..., 128)).
+hipError_t launch_pass_fp8(int epi, const uint8_t* M, const uint8_t* Ms, int64_t ldm,
+                           const uint8_t* Xt, const uint8_t* Xsc, int64_t ldx, float* out,
+                           int64_t ldo, int64_t part_stride, int64_t P, int64_t K, int64_t C,
+                           const GemmPlan& pl, hipStream_t s);
+// out = M Xt^T on bfloat16 MFMA (M: P x K, Xt: Ct x K, K a multiple of 64);
+// the plan comes from plan_gemm(P, K, C, ..., 64); epi EPI_STORE or EPI_PART.
+hipError_t launch_pass_bf16(int epi, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
+                            int64_t ldx, float* out, int64_t ldo, int64_t part_stride, int64_t P,
+                            int64_t K, int64_t C, const GemmPlan& pl, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Tall-skinny LU with partial pivoting (rows stay in place; see k_getrf.hip).

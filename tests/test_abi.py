@@ -61,3 +61,32 @@ def test_oracle_is_not_imported_by_the_product():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "oracle/" not in txt, f
+
+
+def test_request_and_info_layout_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of plu_request / plu_info have the C
+    layout (compiled with the system C compiler against include/powerlu.h)."""
+    import ctypes
+    import shutil
+    import subprocess
+    import paper_2002_07138_amd as plu
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "lay.c"
+    fields = [f for f, _ in plu.PluRequest._fields_]
+    body = "".join(f'printf("%zu ", offsetof(plu_request, {f}));' for f in fields)
+    ifields = [f for f, _ in plu.PluInfo._fields_]
+    body += "".join(f'printf("%zu ", offsetof(plu_info, {f}));' for f in ifields)
+    rfields = [f for f, _ in plu.PluResult._fields_]
+    body += "".join(f'printf("%zu ", offsetof(plu_result, {f}));' for f in rfields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "powerlu.h"\n'
+                   'int main(void){' + body + 'printf("%zu %zu %zu", sizeof(plu_request), '
+                   'sizeof(plu_info), sizeof(plu_result));return 0;}\n')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [getattr(plu.PluRequest, f).offset for f in fields]
+    want += [getattr(plu.PluInfo, f).offset for f in ifields]
+    want += [getattr(plu.PluResult, f).offset for f in rfields]
+    want += [ctypes.sizeof(plu.PluRequest), ctypes.sizeof(plu.PluInfo), ctypes.sizeof(plu.PluResult)]
+    assert got == want

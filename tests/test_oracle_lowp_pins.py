@@ -113,6 +113,11 @@ def test_precision_form_rounds_exactly_the_range_passes():
         assert a_axes == [(start + i) % 2 for i in range(v - 1)]
         assert all(shape == (120, 90) for (shape, ax) in calls[0::2])
         assert all(ax == 0 for (shape, ax) in calls[1::2])
+        # with exact_last the last range product is not rounded
+        calls.clear()
+        O.powerlu(A, 8, Om, v, pass_round=rec, exact_last=True)
+        assert len(calls) == 2 * (v - 2)
+        assert [ax for (shape, ax) in calls[0::2]] == a_axes[:v - 2]
 
 
 @pytest.mark.parametrize("v", [2, 3, 4])
