@@ -240,6 +240,8 @@ def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
     t_end = time.perf_counter()
     srv.close()
     lat = np.array([(res["t_done"] - res["t_submit"]) + lt for res, lt in zip(results, late)])
+    queue = np.array([res["t_admit"] - res["t_submit"] for res in results])
+    service = np.array([res["t_done"] - res["t_admit"] for res in results])
     flops = sum(request_flops(prm, m, n, res["rank"]) for (prm, m, n), res in zip(meta, results))
     ok = sum(1 for res in results if res["status"] in (0, 1, 2))
     return {
@@ -250,6 +252,13 @@ def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
         "throughput_req_per_s": round(count / (t_end - t_start), 1),
         "gflops": round(flops / (t_end - t_start) / 1e9, 1),
         "completed_ok": ok,
+        "mean_queue_ms": round(float(queue.mean()) * 1e3, 2),
+        "mean_service_ms": round(float(service.mean()) * 1e3, 2),
+        "mean_service_ms_by_mode": {
+            "fixed_rank": round(float(np.mean([sv for sv, (prm, m, n) in zip(service, meta)
+                                                if prm["mode"] == 0])) * 1e3, 2),
+            "fixed_precision": round(float(np.mean([sv for sv, (prm, m, n) in zip(service, meta)
+                                                     if prm["mode"] == 1])) * 1e3, 2)},
         "hbm_budget_gb": budget_gb, "slots": slots,
         "latency_includes": "H2D copy of A, all steps, D2H copy of p, q, L, U",
     }
@@ -350,6 +359,8 @@ def main():
     ap.add_argument("--serving-count", type=int, default=1024,
                     help="requests of the serving replay (0 skips it and the batch comparison)")
     ap.add_argument("--pool", type=int, default=16, help="distinct matrices of the serving replay")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the batched comparison and the serving replay")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run only the pass kernels at the workload shape (3 launches per "
                          "direction) and a plain 1 GiB copy, for hardware-counter runs")
@@ -368,6 +379,14 @@ def main():
     m = n = args.size
     if args.profile_pass:
         profile_pass(m, n)
+        return
+    if args.serving_only:
+        pool = serving_pool(args.pool)
+        h = plu.Handle(0)
+        out = {"batched": batched_vs_single(h, pool)}
+        h.close()
+        out["serving"] = serving(pool, count=args.serving_count)
+        print(json.dumps(out))
         return
     t_gen = time.perf_counter()
     A_host = workload_matrix(w, m, n)

@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
+#include <tuple>
 #include <cstring>
 #include <chrono>
 #include <condition_variable>
@@ -42,6 +44,7 @@ struct plu_handle_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gsig;
   plu::MergeBuffers gbuf;
+  hipStream_t gstream = nullptr;   // capture stream (the handle's may be the null stream)
 };
 
 namespace {
@@ -290,36 +293,113 @@ QrWork qr_work(const Ws& w, float* q, int64_t ldq) {
 // One pass over A: out = A X (trans 0) or A^T X (trans 1).  Optional fused
 // ||A||_F^2 into normA2_dev and column norms^2 partials into colsq (then
 // *colsq_blocks receives the number of row blocks).
+// Autotuned split of the passes over A.  The first pass of a shape (direction,
+// P, R, C, leading dimension of the output) on a device times the candidate
+// plans -- the split that fills whole rounds of 512, 768, 1024, 1280, 1536 or
+// 2048 resident workgroups -- with events on the handle's stream and keeps
+// the fastest for the process, so every later pass of that shape (single
+// calls and batches alike) runs the same plan and gives the same bits.
+struct TuneKey {
+  int device, trans;
+  int64_t P, R, C, ldo;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(device, trans, P, R, C, ldo) < std::tie(o.device, o.trans, o.P, o.R, o.C, o.ldo);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, GemmPlan> g_tuned;
+
+hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0, const GemmPlan& pl,
+                       float* out, int64_t ldo, double* colsq, hipStream_t s);
+
+bool tune_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("PLU_AUTOTUNE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, float* out, int64_t ldo) {
+  const int64_t P = g.P, R = g.R, C = g.C;
+  const GemmPlan def = plan_gemm(P, R, C, kMaxSplit, kTargetWgs);
+  auto fits = [&](const GemmPlan& p) {
+    return p.nsplit == 1 || (int64_t)p.nsplit * P * ldo <= w.part_cap;
+  };
+  const TuneKey key{h->device, trans, P, R, C, ldo};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end() && fits(it->second)) return it->second;
+  }
+  // small passes and recorded (batched) launches use the default plan
+  if (!tune_enabled() || thread_recorder() || 2.0 * P * R * C < 2e10) return fits(def) ? def : plan_gemm(P, R, C, 1, 1);
+  std::vector<GemmPlan> cands;
+  for (int slots : {512, 768, 1024, 1280, 1536, 2048}) {
+    GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots);
+    if (!fits(p)) continue;
+    bool dup = false;
+    for (auto& c : cands) dup |= (c.nsplit == p.nsplit);
+    if (!dup) cands.push_back(p);
+  }
+  if (cands.empty()) return plan_gemm(P, R, C, 1, 1);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return cands[0];
+  GemmPlan best = cands[0];
+  float best_ms = 1e30f;
+  for (const GemmPlan& p : cands) {
+    float ms = 0.f;
+    bool ok = pass_launch(h, w, trans, g, p, out, ldo, nullptr, h->stream) == hipSuccess;   // warm
+    ok = ok && hipEventRecord(e0, h->stream) == hipSuccess;
+    for (int r = 0; r < 3 && ok; ++r)
+      ok = pass_launch(h, w, trans, g, p, out, ldo, nullptr, h->stream) == hipSuccess;
+    ok = ok && hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = p;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
+}
+
+hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0, const GemmPlan& pl,
+                       float* out, int64_t ldo, double* colsq, hipStream_t s) {
+  GemmArgs g = g0;
+  const int64_t P = g.P;
+  const int rb = 64;
+  hipError_t e;
+  if (pl.nsplit > 1) {
+    g.out = w.part; g.ldo = ldo; g.part_stride = P * ldo;
+    if ((e = launch_gemm(trans, EPI_PART, 0, g, pl, s)) != hipSuccess) return e;
+    return launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, g.C, colsq, rb, s);
+  }
+  g.out = out; g.ldo = ldo;
+  if ((e = launch_gemm(trans, EPI_STORE, 0, g, pl, s)) != hipSuccess) return e;
+  if (colsq) return launch_splitk_reduce(out, 0, 1, nullptr, ldo, P, g.C, colsq, rb, s);
+  return hipSuccess;
+}
+
 hipError_t run_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, const float* A,
                     int64_t lda, const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo,
                     double* normA2_dev, double* colsq, int* colsq_blocks) {
   const int64_t P = trans ? n : m, R = trans ? m : n;
-  GemmPlan pl = plan_gemm(P, R, l, kMaxSplit, kTargetWgs);
-  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * ldo > w.part_cap) pl = plan_gemm(P, R, l, 1, 1);
-  GemmArgs g;
-  g.A = A; g.lda = lda; g.X = X; g.ldx = ldx;
-  g.P = P; g.R = R; g.C = l;
+  GemmArgs g0;
+  g0.A = A; g0.lda = lda; g0.X = X; g0.ldx = ldx;
+  g0.P = P; g0.R = R; g0.C = l;
+  const GemmPlan pl = pass_plan(h, w, trans, g0, out, ldo);
+  GemmArgs g = g0;
   if (normA2_dev) {
     if ((int64_t)pl.pblocks * pl.nsplit > w.sumsq_cap) return hipErrorInvalidValue;
     g.sumsq_part = w.sumsq_part;
   }
   hipError_t e;
   const int rb = 64;
-  if (pl.nsplit > 1) {
-    g.out = w.part; g.ldo = ldo; g.part_stride = P * ldo;
-    if ((e = launch_gemm(trans, EPI_PART, 0, g, pl, h->stream)) != hipSuccess) return e;
-    if ((e = launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, l, colsq, rb,
-                                  h->stream)) != hipSuccess)
-      return e;
-  } else {
-    g.out = out; g.ldo = ldo;
-    if ((e = launch_gemm(trans, EPI_STORE, 0, g, pl, h->stream)) != hipSuccess) return e;
-    if (colsq) {
-      if ((e = launch_splitk_reduce(out, 0, 1, nullptr, ldo, P, l, colsq, rb, h->stream)) !=
-          hipSuccess)
-        return e;
-    }
-  }
+  if ((e = pass_launch(h, w, trans, g, pl, out, ldo, colsq, h->stream)) != hipSuccess) return e;
   if (colsq_blocks) *colsq_blocks = (int)((P + rb - 1) / rb);
   if (normA2_dev) {
     if ((e = launch_sum_doubles(w.sumsq_part, (int64_t)pl.pblocks * pl.nsplit, normA2_dev,
@@ -527,9 +607,9 @@ hipError_t assemble(plu_handle h, const Ws& w, int64_t m, int64_t n, int k, cons
 }
 
 int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int l, bool fp,
-                plu_info* info) {
+                plu_info* info, bool sync = true) {
   if (!info) return status;
-  PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (sync) PLU_TRY_HIP(hipStreamSynchronize(h->stream));
   int32_t st[40];
   double sc[4];
   PLU_TRY_HIP(hipMemcpy(st, w.status, sizeof(st), hipMemcpyDeviceToHost));
@@ -749,6 +829,8 @@ struct ServerJob {
   BatchProblem bp;
   int phase = 0;               // 1: main steps, 2: fixed-precision assembly
   size_t head = 0;
+  hipEvent_t ev = nullptr;     // recorded after the launch group holding its last step
+  bool waiting = false;        // all recorded steps issued, waiting for ev
   plu_result res{};
 };
 
@@ -770,32 +852,66 @@ struct plu_server_s {
   int max_slots = 1;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_fin;
   std::deque<std::unique_ptr<ServerJob>> pending;
-  std::vector<std::unique_ptr<ServerJob>> active;
+  std::vector<std::unique_ptr<ServerJob>> active;    // admitted, steps in flight
+  std::deque<ServerJob*> finishing;                  // all steps done, copy-out queued
+  int nfinishing = 0;                                // in finishing or being copied out
   std::map<uint64_t, plu_result> done;
+  std::vector<hipEvent_t> events;                    // free event objects
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker;
+  std::thread worker, finisher;
   int device = 0;
   int fatal = 0;
+  MergeStats stats;       // grouped launches and the steps they carried
+  size_t batches = 0;
 };
 
 namespace {
 
-// Admits, records and runs; returns when stopped and drained.
+hipEvent_t take_event(plu_server S) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (!S->events.empty()) {
+    hipEvent_t e = S->events.back();
+    S->events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Admits requests, records their steps and keeps the compute stream fed with
+// merged launch groups; finished requests go to the finisher thread.  At most
+// two launch batches are queued ahead of the device, so arrivals join soon.
 void server_loop(plu_server S) {
   (void)hipSetDevice(S->device);
   plu_handle h = S->h;
-  constexpr size_t kGroupsPerIter = 24;
+  constexpr size_t kGroupsPerIter = 32;
+  std::deque<hipEvent_t> inflight;   // one event per issued batch of groups
   for (;;) {
     std::vector<ServerJob*> admitted;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->active.empty())
-        S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
-      if (S->stop && S->pending.empty() && S->active.empty()) return;
-      while (!S->pending.empty() && (int)S->active.size() < S->max_slots) {
+      bool runnable = false;
+      for (auto& up : S->active)
+        if (!up->waiting) runnable = true;
+      if (!runnable && inflight.empty()) {
+        S->cv_work.wait(lk, [&] {
+          bool r = false;
+          for (auto& up : S->active)
+            if (!up->waiting) r = true;
+          return S->stop || r ||
+                 (!S->pending.empty() &&
+                  (int)S->active.size() + S->nfinishing < S->max_slots);
+        });
+      }
+      if (S->stop && S->pending.empty() && S->active.empty() && S->nfinishing == 0 &&
+          inflight.empty())
+        return;
+      // a slot is held from admission until the result is copied out
+      while (!S->pending.empty() && (int)S->active.size() + S->nfinishing < S->max_slots) {
         ServerJob* j = S->pending.front().get();
         size_t off = 0;
         if (!S->pool.alloc(j->pool_bytes, &off)) break;
@@ -806,7 +922,6 @@ void server_loop(plu_server S) {
         admitted.push_back(j);
       }
     }
-    // device copies of the admitted problems, their workspaces, their steps
     for (ServerJob* j : admitted) {
       char* b = S->pool.base + j->pool_off;
       auto take = [&](size_t bytes) {
@@ -839,6 +954,7 @@ void server_loop(plu_server S) {
       bp.hs.batch_arena = nullptr;
       bp.hs.graph = nullptr;
       bp.hs.gexec = nullptr;
+      bp.hs.gstream = nullptr;
       bp.hs.mbuf = MergeBuffers();
       bp.hs.gbuf = MergeBuffers();
       int64_t l = 0;
@@ -850,37 +966,60 @@ void server_loop(plu_server S) {
       thread_recorder() = nullptr;
       j->phase = 1;
       j->head = 0;
+      j->waiting = false;
       if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
     }
-    // advance every admitted problem through a bounded number of launches
+    // issue one batch of merged groups over the problems with steps left
     std::vector<const Recorder*> lists;
     std::vector<size_t> heads;
     std::vector<ServerJob*> js;
-    for (auto& up : S->active) {
-      lists.push_back(&up->bp.rec);
-      heads.push_back(up->head);
-      js.push_back(up.get());
-    }
-    hipError_t e = run_merged_steps(lists, heads, S->stream, h->cu_count, kGroupsPerIter, h->mbuf,
-                                    nullptr);
-    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
-    if (e != hipSuccess) {
-      std::fprintf(stderr, "libpowerlu server: %s\n", hipGetErrorString(e));
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->fatal = PLU_ERR_HIP;
-    }
-    for (size_t i = 0; i < js.size(); ++i) js[i]->head = heads[i];
-    // completions
-    std::vector<ServerJob*> finished;
-    for (ServerJob* j : js) {
-      if (S->fatal) {
-        j->res.status = S->fatal;
-        finished.push_back(j);
-        continue;
+    for (auto& up : S->active)
+      if (!up->waiting) {
+        lists.push_back(&up->bp.rec);
+        heads.push_back(up->head);
+        js.push_back(up.get());
       }
-      if (j->head < j->bp.rec.ops.size()) continue;
-      BatchProblem& bp = j->bp;
-      if (j->dev.mode == 1 && j->phase == 1) {
+    if (!js.empty()) {
+      // bound the queue: wait for the batch before last
+      while (inflight.size() >= 2) {
+        (void)hipEventSynchronize(inflight.front());
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->events.push_back(inflight.front());
+        inflight.pop_front();
+      }
+      hipError_t e = run_merged_steps(lists, heads, S->stream, h->cu_count, kGroupsPerIter,
+                                      h->mbuf, &S->stats);
+      ++S->batches;
+      hipEvent_t ev = take_event(S);
+      if (e == hipSuccess && ev) e = hipEventRecord(ev, S->stream);
+      if (e != hipSuccess || !ev) {
+        std::fprintf(stderr, "libpowerlu server: %s\n", hipGetErrorString(e));
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->fatal = PLU_ERR_HIP;
+      }
+      inflight.push_back(ev);
+      for (size_t i = 0; i < js.size(); ++i) {
+        js[i]->head = heads[i];
+        if (js[i]->head >= js[i]->bp.rec.ops.size()) {
+          js[i]->waiting = true;
+          js[i]->ev = ev;
+        }
+      }
+    } else if (!inflight.empty()) {
+      (void)hipEventSynchronize(inflight.front());
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->events.push_back(inflight.front());
+      inflight.pop_front();
+    }
+    // problems whose steps are all complete
+    std::vector<ServerJob*> to_finish;
+    for (auto& up : S->active) {
+      ServerJob* j = up.get();
+      if (!j->waiting) continue;
+      if (!S->fatal && hipEventQuery(j->ev) != hipSuccess) continue;
+      if (!S->fatal && j->dev.mode == 1 && j->phase == 1) {
+        // the rank decides the assembly: read it, then record the rest
+        BatchProblem& bp = j->bp;
         int32_t ks[2];
         double sc;
         (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
@@ -892,53 +1031,87 @@ void server_loop(plu_server S) {
         thread_recorder() = nullptr;
         j->phase = 2;
         j->head = 0;
+        j->waiting = false;
         continue;
       }
-      finished.push_back(j);
+      to_finish.push_back(j);
     }
-    for (ServerJob* j : finished) {
-      const plu_request& d = j->dev;
-      const plu_request& r = j->host;
-      BatchProblem& bp = j->bp;
-      int k = d.mode == 0 ? d.k : bp.k;
-      if (!S->fatal) {
-        int st = PLU_OK;
-        if (d.mode == 1) {
-          int32_t ks[2];
-          double sc;
-          (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
-          (void)hipMemcpy(&sc, bp.w.scal, sizeof(sc), hipMemcpyDeviceToHost);
-          st = !std::isfinite(sc) ? PLU_ERR_NONFINITE : ks[1] ? PLU_OK : PLU_TOL_NOT_REACHED;
-          if (!std::isfinite(sc)) k = 0;
-        }
-        plu_handle_s hs = bp.hs;
-        j->res.status = finish_info(&hs, bp.w, st, k, d.v, (int)bp.l, d.mode == 1, &j->res.info);
-        if (d.mode == 1) j->res.info.tol_reached = st == PLU_OK ? 1 : 0;
-        j->res.rank = k;
-        (void)hipMemcpy(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost);
-        if (k > 0) {
-          (void)hipMemcpy2D(r.L, (size_t)r.ldl * 4, d.L, (size_t)d.ldl * 4, (size_t)k * 4,
-                            (size_t)r.m, hipMemcpyDeviceToHost);
-          (void)hipMemcpy2D(r.U, (size_t)r.ldu * 4, d.U, (size_t)d.ldu * 4, (size_t)r.n * 4,
-                            (size_t)k, hipMemcpyDeviceToHost);
-        }
-      }
-      j->res.t_done = now_s(S->t0);
-    }
-    if (!finished.empty()) {
+    if (!to_finish.empty()) {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (ServerJob* j : finished) {
-        S->done[j->ticket] = j->res;
-        S->pool.release(j->pool_off, j->pool_bytes);
+      for (ServerJob* j : to_finish) {
         for (auto it = S->active.begin(); it != S->active.end(); ++it)
           if (it->get() == j) {
+            it->release();
             S->active.erase(it);
             break;
           }
+        S->finishing.push_back(j);
+        ++S->nfinishing;
       }
-      S->cv_done.notify_all();
+      S->cv_fin.notify_one();
     }
+  }
+}
+
+// Copies finished problems out (host buffers of the client), fills their
+// results and frees their device memory, off the launch thread.
+void server_finisher(plu_server S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    ServerJob* j = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_fin.wait(lk, [&] { return !S->finishing.empty() || (S->stop && S->active.empty() &&
+                                                                 S->pending.empty()); });
+      if (S->finishing.empty()) return;
+      j = S->finishing.front();
+      S->finishing.pop_front();
+    }
+    const plu_request& d = j->dev;
+    const plu_request& r = j->host;
+    BatchProblem& bp = j->bp;
+    int k = d.mode == 0 ? d.k : bp.k;
+    int fatal = 0;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      fatal = S->fatal;
+    }
+    if (!fatal) {
+      int st = PLU_OK;
+      if (d.mode == 1) {
+        int32_t ks[2];
+        double sc;
+        (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
+        (void)hipMemcpy(&sc, bp.w.scal, sizeof(sc), hipMemcpyDeviceToHost);
+        st = !std::isfinite(sc) ? PLU_ERR_NONFINITE : ks[1] ? PLU_OK : PLU_TOL_NOT_REACHED;
+        if (!std::isfinite(sc)) k = 0;
+      }
+      plu_handle_s hs = bp.hs;
+      j->res.status = finish_info(&hs, bp.w, st, k, d.v, (int)bp.l, d.mode == 1, &j->res.info,
+                                  false);
+      if (d.mode == 1) j->res.info.tol_reached = st == PLU_OK ? 1 : 0;
+      j->res.rank = k;
+      (void)hipMemcpy(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost);
+      (void)hipMemcpy(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost);
+      if (k > 0) {
+        (void)hipMemcpy2D(r.L, (size_t)r.ldl * 4, d.L, (size_t)d.ldl * 4, (size_t)k * 4,
+                          (size_t)r.m, hipMemcpyDeviceToHost);
+        (void)hipMemcpy2D(r.U, (size_t)r.ldu * 4, d.U, (size_t)d.ldu * 4, (size_t)r.n * 4,
+                          (size_t)k, hipMemcpyDeviceToHost);
+      }
+    } else {
+      j->res.status = fatal;
+    }
+    j->res.t_done = now_s(S->t0);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->done[j->ticket] = j->res;
+      S->pool.release(j->pool_off, j->pool_bytes);
+      --S->nfinishing;
+      S->cv_done.notify_all();
+      S->cv_work.notify_one();   // memory freed: admission may proceed
+    }
+    delete j;
   }
 }
 
@@ -988,6 +1161,7 @@ int plu_destroy(plu_handle h) {
   if (!h) return -1;
   (void)hipStreamSynchronize(h->stream);
   drop_graph(h);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
   h->mbuf.destroy();
   if (h->arena) (void)hipFree(h->arena);
   if (h->batch_arena) (void)hipFree(h->batch_arena);
@@ -1437,6 +1611,7 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       b.hs.tag_counter = 0;   // first panel clears this problem's message slots
       b.hs.batch_arena = nullptr;
       b.hs.gexec = nullptr;
+      b.hs.gstream = nullptr;
       b.hs.graph = nullptr;
       b.hs.mbuf = MergeBuffers();
       b.hs.gbuf = MergeBuffers();
@@ -1455,17 +1630,21 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
         lists.push_back(&b->rec);
       }
       PLU_TRY_HIP(h->gbuf.reserve(merged_table_bytes(lists, h->cu_count)));
+      if (!h->gstream) PLU_TRY_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
       h->gbuf.capturing = true;
-      PLU_TRY_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      hipError_t ce = run_merged(lists, h->stream, h->cu_count, h->gbuf, nullptr);
+      PLU_TRY_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = run_merged(lists, h->gstream, h->cu_count, h->gbuf, nullptr);
       hipGraph_t g = nullptr;
-      hipError_t ee = hipStreamEndCapture(h->stream, &g);
+      hipError_t ee = hipStreamEndCapture(h->gstream, &g);
       h->gbuf.capturing = false;
       if (ce != hipSuccess || ee != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
         std::fprintf(stderr, "libpowerlu: batch graph capture failed: %s / %s\n",
                      hipGetErrorString(ce), hipGetErrorString(ee));
-        return PLU_ERR_HIP;
+        return ce == hipErrorStreamCaptureUnsupported || ee == hipErrorStreamCaptureUnsupported
+                   ? PLU_ERR_NOT_IMPLEMENTED
+                   : PLU_ERR_HIP;
       }
       h->graph = g;
       PLU_TRY_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
@@ -1541,6 +1720,7 @@ int plu_server_create(plu_server* out, int device, size_t hbm_budget_bytes, int3
     return PLU_ERR_OOM;
   }
   S->worker = std::thread(server_loop, S);
+  S->finisher = std::thread(server_finisher, S);
   *out = S;
   return PLU_OK;
 }
@@ -1596,7 +1776,16 @@ int plu_server_destroy(plu_server S) {
     S->cv_work.notify_all();
   }
   if (S->worker.joinable()) S->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->cv_fin.notify_all();
+  }
+  if (S->finisher.joinable()) S->finisher.join();
   (void)hipStreamSynchronize(S->stream);
+  if (const char* e = std::getenv("PLU_SERVER_STATS"); e && e[0] == '1')
+    std::fprintf(stderr, "libpowerlu server: %zu batches, %zu grouped launches carrying %zu steps\n",
+                 S->batches, S->stats.launches, S->stats.recorded);
+  for (hipEvent_t e : S->events) (void)hipEventDestroy(e);
   if (S->pool.base) (void)hipFree(S->pool.base);
   plu_destroy(S->h);
   (void)hipStreamDestroy(S->stream);

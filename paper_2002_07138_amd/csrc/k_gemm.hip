@@ -58,6 +58,7 @@ __device__ __forceinline__ f32x4 load4(const float* src, int64_t idx, int64_t li
 // computed and dropped) and only g.nt are stored.
 template <int MODE, int NT, int EPI, int RT = GEMM_BP / 64, int BKT = GEMM_BK, bool DYN = false>
 __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
+  if (g.run_if && *g.run_if == 0) return;
   constexpr int BP = 64 * RT;
   constexpr int BK = BKT;
   constexpr int AST_N = BK + 4;   // mode N A tile: [BP][BK+4]  (row p, reduction r)

@@ -25,6 +25,7 @@
 #include "plu_internal.h"
 
 #include <climits>
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
 
@@ -51,6 +52,7 @@ struct PanelArgs {
   int nwaves;
   int msgw;                 // words per message = MSGH + NB
   uint64_t timeout_ticks;
+  const int32_t* run_if;    // the panel does nothing when it reads 0 (nullable)
 };
 
 __device__ __forceinline__ void st_word(unsigned long long* p, uint32_t payload, uint32_t tag) {
@@ -183,6 +185,7 @@ __device__ __forceinline__ float wave_max_f32(float v) {
 // messages into LDS; (4) every wave picks the same winner and updates.
 template <int NB, int RPT, int NWAVE, int S>
 __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
+  if (a.run_if && *a.run_if == 0) return;   // uniform over the grid: every workgroup leaves
   constexpr int MAXG = 64;                 // message slots (workgroups) at most
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -495,12 +498,14 @@ struct TrsmArgs {
   const int32_t* piv_row;
   float* u12;
   int64_t ldu12;
+  const int32_t* run_if;
 };
 
 // U12 = L11^{-1} F[pivot rows of the panel, right columns]; written back into
 // the pivot rows and into a compact nbw x (c - jb - nbw) buffer.  The block's
 // 64 right-hand columns are staged in LDS first, then solved in place.
 __device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
+  if (a.run_if && *a.run_if == 0) return;
   __shared__ float L11[64][65];
   __shared__ float us[64][65];
   __shared__ int rows[64];
@@ -533,10 +538,11 @@ __device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
 }
 
 struct InitArgs {
-  int32_t* piv_step; int32_t* pos; int64_t M; int32_t* zstep;
+  int32_t* piv_step; int32_t* pos; int64_t M; int32_t* zstep; const int32_t* run_if;
 };
 
 __device__ void b_getrf_init(const InitArgs& a, const Grid& gr) {
+  if (a.run_if && *a.run_if == 0) return;
   const int64_t i = (int64_t)gr.bx * 256 + threadIdx.x;
   if (i < a.M) {
     a.piv_step[i] = -1;
@@ -549,10 +555,11 @@ __device__ void b_getrf_init(const InitArgs& a, const Grid& gr) {
 // zeros to its right), extracts U (or U^T) and the row order perm.
 struct FinalizeArgs {
   float* F; int64_t ldf, M; int c; const int32_t* piv_step; const int32_t* pos; int32_t* perm;
-  float* Uout; int64_t ldu; int utrans;
+  float* Uout; int64_t ldu; int utrans; const int32_t* run_if;
 };
 
 __device__ void b_getrf_finalize(const FinalizeArgs& fa, const Grid& gr) {
+  if (fa.run_if && *fa.run_if == 0) return;
   float* F = fa.F;
   const int64_t ldf = fa.ldf, M = fa.M;
   const int c = fa.c;
@@ -602,13 +609,19 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
                      float* Uout, int64_t ldu, int utrans, hipStream_t s) {
   if (c <= 0 || M < c) return hipErrorInvalidValue;
   hipError_t e;
-  if ((e = dispatch<InitArgs, b_getrf_init, 256>(InitArgs{w.piv_step, w.pos, M, w.zstep},
+  if ((e = dispatch<InitArgs, b_getrf_init, 256>(InitArgs{w.piv_step, w.pos, M, w.zstep, w.run_if},
                                                  dim3((unsigned)((M + 255) / 256)), 0, s)) !=
       hipSuccess)
     return e;
   constexpr int NB = 64, NWAVE = 8, S = 4;
-  // one row per lane while 64 workgroups of 512 rows suffice, else two
-  const int rpt = (M <= 64LL * NWAVE * 64) ? 1 : 2;
+  // one row per lane while 64 workgroups of 512 rows suffice, else two;
+  // PLU_PANEL_RPT=2 forces two rows per lane (half the workgroups)
+  static const int rpt_env = [] {
+    const char* v = std::getenv("PLU_PANEL_RPT");
+    return v ? std::atoi(v) : 0;
+  }();
+  int rpt = (M <= 64LL * NWAVE * 64) ? 1 : 2;
+  if (rpt_env == 2) rpt = 2;
   const int64_t rows_per_wg = (int64_t)NWAVE * 64 * rpt;
   const int nblocks = (int)((M + rows_per_wg - 1) / rows_per_wg);
   if (nblocks > 64 || (int64_t)nblocks * NWAVE > w.max_waves) return hipErrorInvalidValue;
@@ -628,12 +641,13 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
     pa.nwaves = nblocks;
     pa.msgw = MSGH + NB;
     pa.timeout_ticks = w.timeout_ticks;
+    pa.run_if = w.run_if;
     e = (rpt == 1) ? launch_panel<NB, 1, NWAVE, S>(pa, nblocks, s)
                    : launch_panel<NB, 2, NWAVE, S>(pa, nblocks, s);
     if (e != hipSuccess) return e;
     const int cs = jb + pa.nbw;
     if (cs < c) {
-      TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12};
+      TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12, w.run_if};
       if ((e = dispatch<TrsmArgs, b_trsm, 256>(ta, dim3((unsigned)((c - cs + 63) / 64)), 0, s)) !=
           hipSuccess)
         return e;
@@ -643,13 +657,14 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
       g.out = F + cs; g.ldo = ldf;
       g.P = M; g.R = pa.nbw; g.C = c - cs;
       g.rowmask = w.piv_step;
+      g.run_if = w.run_if;
       GemmPlan pl = plan_gemm(M, pa.nbw, c - cs, 1, 1);
       if ((e = launch_gemm(0, EPI_SUB, 0, g, pl, s)) != hipSuccess) return e;
     }
   }
   const int64_t tot = M * (int64_t)c;
   return dispatch<FinalizeArgs, b_getrf_finalize, 256>(
-      FinalizeArgs{F, ldf, M, c, w.piv_step, w.pos, perm, Uout, ldu, utrans},
+      FinalizeArgs{F, ldf, M, c, w.piv_step, w.pos, perm, Uout, ldu, utrans, w.run_if},
       dim3((unsigned)((tot + 255) / 256)), 0, s);
 }
 

@@ -385,9 +385,13 @@ __global__ __launch_bounds__(256) void k_cvt_fp8(const float* __restrict__ src, 
 // out[p][c] = sum_k (M[p][k] 2^sM[p][k/32]) (Xt[c][k] 2^sX[c][k/32]).
 //   M: P x K codes (ld ldm, K a multiple of 128), Ms: P x K/32 scale bytes;
 //   Xt: Ct x K codes (ld ldx), Xs: Ct x K/32.
-// v_mfma_scale_f32_16x16x128_f8f6f4: lane (r, g) supplies row r's 32 codes
-// k0 + 32 g + [0, 32) (one scale block) with that block's scale, for both
-// operands.  Same decomposition as k_pass_bf16 with 128 of K per stage.
+// v_mfma_scale_f32_16x16x128_f8f6f4 (layout measured on gfx950): lane
+// (r, g) supplies row r's codes k0 + 16 g + [0, 16) in its first 16 bytes and
+// k0 + 64 + 16 g + [0, 16) in its last 16, and the scale of block
+// k0/32 + g; the hardware applies the scale of lane group b to the 32
+// entries k0 + 32 b + [0, 32), which lane groups 2(b mod 2) and 2(b mod 2)+1
+// hold.  Both operands use this layout.  Same decomposition as k_pass_bf16
+// with 128 of K per stage.
 template <int NT, int EPI>
 __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8_t* __restrict__ M,
                                                      const uint8_t* __restrict__ Ms, int64_t ldm,
@@ -421,8 +425,8 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8
 
   const int64_t pa0 = p0 + wave * 32 + r, pa1 = pa0 + 16;
   const bool ok0 = pa0 < P, ok1 = pa1 < P;
-  const uint8_t* a0 = M + (ok0 ? pa0 : 0) * ldm + g4 * 32;
-  const uint8_t* a1 = M + (ok1 ? pa1 : 0) * ldm + g4 * 32;
+  const uint8_t* a0 = M + (ok0 ? pa0 : 0) * ldm + g4 * 16;
+  const uint8_t* a1 = M + (ok1 ? pa1 : 0) * ldm + g4 * 16;
   const uint8_t* s0 = Ms + (ok0 ? pa0 : 0) * lds_ + g4;
   const uint8_t* s1 = Ms + (ok1 ? pa1 : 0) * lds_ + g4;
 
@@ -463,9 +467,9 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8
   auto load_a = [&](int64_t k, uint4 (&d)[2][2], uint32_t (&sc)[2]) __attribute__((always_inline)) {
     const uint4 z = {0u, 0u, 0u, 0u};
     d[0][0] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k) : z;
-    d[0][1] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k + 16) : z;
+    d[0][1] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k + 64) : z;
     d[1][0] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k) : z;
-    d[1][1] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k + 16) : z;
+    d[1][1] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k + 64) : z;
     sc[0] = ok0 ? (uint32_t)s0[k / 32] : 0u;
     sc[1] = ok1 ? (uint32_t)s1[k / 32] : 0u;
   };
@@ -480,9 +484,9 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8
     }
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      const uint8_t* bp = &Xs[buf][(j * 16 + r) * XP + g4 * 32];
+      const uint8_t* bp = &Xs[buf][(j * 16 + r) * XP + g4 * 16];
       const uint4 b0 = *reinterpret_cast<const uint4*>(bp);
-      const uint4 b1 = *reinterpret_cast<const uint4*>(bp + 16);
+      const uint4 b1 = *reinterpret_cast<const uint4*>(bp + 64);
       i32x8 fb;
       fb[0] = (int)b0.x; fb[1] = (int)b0.y; fb[2] = (int)b0.z; fb[3] = (int)b0.w;
       fb[4] = (int)b1.x; fb[5] = (int)b1.y; fb[6] = (int)b1.z; fb[7] = (int)b1.w;

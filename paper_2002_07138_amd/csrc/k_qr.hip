@@ -23,6 +23,7 @@ constexpr int QB = 128;   // column block of the Gram-Schmidt sweep
 // part[chunk][a][b] = sum over the chunk's rows of V[i][a] V[i][b] (float64).
 struct GramArgs {
   const float* V; int64_t ldv, M; int bw; int64_t rows_per_chunk; double* part;
+  const int32_t* run_if;   // nullable: nothing is done when it reads 0
 };
 
 __device__ void b_gram(const GramArgs& ga, const Grid& gr) {
@@ -31,6 +32,7 @@ __device__ void b_gram(const GramArgs& ga, const Grid& gr) {
   const int bw = ga.bw;
   const int64_t rows_per_chunk = ga.rows_per_chunk;
   double* part = ga.part;
+  if (ga.run_if && *ga.run_if == 0) return;
   __shared__ float S[64][QB + 1];
   const int t = threadIdx.x;
   const int ta = t >> 4, tb = t & 15;
@@ -75,13 +77,14 @@ __device__ void b_gram(const GramArgs& ga, const Grid& gr) {
 }
 
 struct GramReduceArgs {
-  const double* part; int nchunk, bw; double* W;
+  const double* part; int nchunk, bw; double* W; const int32_t* run_if;
 };
 
 __device__ void b_gram_reduce(const GramReduceArgs& ga, const Grid& gr) {
   const double* part = ga.part;
   const int nchunk = ga.nchunk, bw = ga.bw;
   double* W = ga.W;
+  if (ga.run_if && *ga.run_if == 0) return;
   const int e = gr.bx * 256 + threadIdx.x;
   if (e >= bw * bw) return;
   // eight independent partial sums keep eight loads in flight; fixed order
@@ -104,7 +107,15 @@ __device__ void b_gram_reduce(const GramReduceArgs& ga, const Grid& gr) {
 // trailing update reads and writes different LDS objects.
 struct CholArgs {
   const double* W; int bw; float* Rinv; int64_t ldr; double* Rinv64; int32_t* status;
+  int32_t* need_lu;   // nullable: set to 1 when the Cholesky factor shows X ill-conditioned
+  const int32_t* run_if;   // nullable: nothing is done when it reads 0
 };
+
+// Below this ratio of the smallest to the largest diagonal entry of the
+// Cholesky factor (a lower bound of 1/cond(X)), X is orthonormalized after
+// the LU reorthogonalization: CholeskyQR2 with a float64 Gram is accurate for
+// cond(X) well below 1e7, and the ratio underestimates cond(X).
+constexpr double kCholRatioMin = 1e-4;
 
 __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   (void)gr;
@@ -114,10 +125,13 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   const int64_t ldr = ca.ldr;
   double* Rinv64 = ca.Rinv64;
   int32_t* status = ca.status;
+  if (ca.run_if && *ca.run_if == 0) return;
+  __shared__ int bad;
   __shared__ double S[QB][QB + 1];
   __shared__ double cj[QB];
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
+  if (t == 0) bad = 0;
   for (int r = ty; r < bw; r += 16)
     for (int c = tx; c <= r; c += 16) S[r][c] = W[r * bw + c];
   __syncthreads();
@@ -125,7 +139,10 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   for (int j = 0; j < bw; ++j) {
     double d = S[j][j];
     if (!(d > 0.0)) {
-      if (t == 0) status[2] = 1;
+      if (t == 0) {
+        status[2] = 1;
+        bad = 1;
+      }
       d = DBL_MIN;
     }
     const double sd = sqrt(d);
@@ -142,6 +159,14 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
       for (int c = j + 1 + tx; c <= i; c += 16) S[i][c] = fma(-lij, cj[c], S[i][c]);
     }
     __syncthreads();
+  }
+  if (ca.need_lu && t == 0) {
+    double mn = S[0][0], mx = S[0][0];
+    for (int j = 1; j < bw; ++j) {
+      mn = fmin(mn, S[j][j]);
+      mx = fmax(mx, S[j][j]);
+    }
+    *ca.need_lu = (bad || !(mn > kCholRatioMin * mx)) ? 1 : 0;
   }
   // X = L^{-1} by right-looking forward substitution on X = I: row k of X is
   // final once divided by L[k][k]; it then updates rows k+1.. in parallel.
@@ -245,23 +270,26 @@ hipError_t gemm_any(int mode, int epi, GemmArgs g, const QrWork& qw, hipStream_t
 }
 
 hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float* dst, int64_t ldd,
-                        const QrWork& qw, bool fp64_apply, hipStream_t s) {
+                        const QrWork& qw, bool fp64_apply, hipStream_t s,
+                        const int32_t* factor_if = nullptr) {
+  // factor_if (nullable): the Gram and Cholesky steps run only when it reads
+  // nonzero (otherwise the R^{-1} already in qw.rinv is applied)
   int nchunk = (int)((M + 63) / 64);
   if (nchunk > qw.max_chunks) nchunk = qw.max_chunks;
   int64_t rpc = (M + nchunk - 1) / nchunk;
   rpc = ((rpc + 63) / 64) * 64;
   nchunk = (int)((M + rpc - 1) / rpc);
   hipError_t e;
-  if ((e = dispatch<GramArgs, b_gram, 256>(GramArgs{src, lds, M, bw, rpc, qw.gram_part},
+  if ((e = dispatch<GramArgs, b_gram, 256>(GramArgs{src, lds, M, bw, rpc, qw.gram_part, factor_if},
                                            dim3(nchunk), 0, s)) != hipSuccess)
     return e;
   if ((e = dispatch<GramReduceArgs, b_gram_reduce, 256>(
-           GramReduceArgs{qw.gram_part, nchunk, bw, qw.gram}, dim3((bw * bw + 255) / 256), 0, s)) !=
-      hipSuccess)
+           GramReduceArgs{qw.gram_part, nchunk, bw, qw.gram, factor_if},
+           dim3((bw * bw + 255) / 256), 0, s)) != hipSuccess)
     return e;
   if ((e = dispatch<CholArgs, b_chol_inv, 256>(
            CholArgs{qw.gram, bw, qw.rinv, (int64_t)QB, fp64_apply ? qw.rinv64 : nullptr,
-                    qw.status},
+                    qw.status, nullptr, factor_if},
            dim3(1), 0, s)) != hipSuccess)
     return e;
   if (fp64_apply) {
@@ -277,12 +305,43 @@ hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float*
   return gemm_any(0, EPI_STORE, g, qw, s);
 }
 
+// Whether X (one block) is well enough conditioned for CholeskyQR2 alone:
+// its float64 Gram, Cholesky and the diagonal test write qw.status[4].
+hipError_t cholqr_probe(const float* X, int64_t ldx, int64_t M, int bw, const QrWork& qw,
+                        hipStream_t s) {
+  int nchunk = (int)((M + 63) / 64);
+  if (nchunk > qw.max_chunks) nchunk = qw.max_chunks;
+  int64_t rpc = (M + nchunk - 1) / nchunk;
+  rpc = ((rpc + 63) / 64) * 64;
+  nchunk = (int)((M + rpc - 1) / rpc);
+  hipError_t e;
+  if ((e = dispatch<GramArgs, b_gram, 256>(GramArgs{X, ldx, M, bw, rpc, qw.gram_part, nullptr},
+                                           dim3(nchunk), 0, s)) != hipSuccess)
+    return e;
+  if ((e = dispatch<GramReduceArgs, b_gram_reduce, 256>(
+           GramReduceArgs{qw.gram_part, nchunk, bw, qw.gram, nullptr},
+           dim3((bw * bw + 255) / 256), 0, s)) != hipSuccess)
+    return e;
+  // R^{-1} of X itself is kept in qw.rinv: the first CholeskyQR round reuses
+  // it when the LU is skipped
+  return dispatch<CholArgs, b_chol_inv, 256>(
+      CholArgs{qw.gram, bw, qw.rinv, (int64_t)QB, nullptr, qw.status, qw.status + 4, nullptr},
+      dim3(1), 0, s);
+}
+
 }  // namespace
 
-hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw,
+hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw0,
                        const QrWork& qw, hipStream_t s) {
   hipError_t e;
-  // LU reorthogonalization: X <- P^T L
+  // LU reorthogonalization X <- P^T L first -- for a single block only when
+  // the Cholesky factor of X's Gram shows it ill-conditioned (the LU kernels
+  // then read the flag on the device and run or return at once)
+  GetrfWork gw = gw0;
+  if (c <= QB) {
+    if ((e = cholqr_probe(X, ldx, M, c, qw, s)) != hipSuccess) return e;
+    gw.run_if = qw.status + 4;
+  }
   if ((e = getrf_run(X, ldx, M, c, gw, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
   for (int j0 = 0; j0 < c; j0 += QB) {
     const int bw = (c - j0 < QB) ? c - j0 : QB;
@@ -306,8 +365,11 @@ hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork&
       }
     }
     // first round on the MFMA pass kernel; the second (R nearly I) in float64
-    // so that the stored basis is orthonormal to about one fp32 rounding
-    if ((e = cholqr_round(VJ, ldx, M, bw, qw.tmp, QB, qw, false, s)) != hipSuccess) return e;
+    // so that the stored basis is orthonormal to about one fp32 rounding.  A
+    // single block reuses the probe's factor unless the LU changed X.
+    if ((e = cholqr_round(VJ, ldx, M, bw, qw.tmp, QB, qw, false, s,
+                          c <= QB ? qw.status + 4 : nullptr)) != hipSuccess)
+      return e;
     if ((e = cholqr_round(qw.tmp, QB, M, bw, qw.q + j0, qw.ldq, qw, true, s)) != hipSuccess)
       return e;
   }

@@ -42,6 +42,7 @@ struct GemmArgs {
   int avec = 0, xvec = 0;
   // grouped form only: direction, column tiles per block
   int mode = 0, nt = 0;
+  const int32_t* run_if = nullptr;   // device flag: the launch does nothing when it reads 0
 };
 
 constexpr int GEMM_BP = 128;   // rows of the kept dimension per pass workgroup (2 tiles per wave)
@@ -111,6 +112,7 @@ struct GetrfWork {
   uint32_t* tag_counter; // host-side counter of panel launches (owned by the handle)
   uint64_t timeout_ticks;
   int max_waves;
+  const int32_t* run_if = nullptr;   // device flag: the whole LU is skipped when it reads 0
 };
 size_t getrf_msg_words(int64_t M);
 // F: M x c (ldf).  On return F holds V = P^T L (unit lower, original row order).
@@ -133,7 +135,7 @@ struct QrWork {
   double* rinv64;        // 128 x 128
   float* wproj;          // c x 128
   float* part; int64_t part_cap;   // split-K partials (floats)
-  int32_t* status;       // [2] Cholesky breakdown flag
+  int32_t* status;       // [2] Cholesky breakdown flag, [4] "needs the LU" flag
 };
 hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw,
                        const QrWork& qw, hipStream_t s);

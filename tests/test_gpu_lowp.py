@@ -222,8 +222,15 @@ def test_pass_fp8_matches_rounded_product(h, m, n, l, trans):
     ref = (Ar.T if trans else Ar) @ Xr
     K = m if trans else n
     scale = np.abs(Ar.T if trans else Ar) @ np.abs(Xr)
-    # exact products of scaled E4M3 values, fp32 accumulation over K terms
-    assert np.all(np.abs(out - ref) <= 8.0 * K * 6e-8 * scale + 1e-30)
+    # the products of scaled E4M3 values are exact (subnormal codes and
+    # scales included, checked on the matrix core), but the 128 products of
+    # one matrix-core step are not summed in fp32 arithmetic: on rows whose
+    # entries span a wide range (here the transposed copy mixes row scales
+    # of e^6) the step loses up to ~2^-14 of sum |a b| (measured 7.4e-5 at
+    # K = 70).  Gate: the fp32-accumulation bound plus 2^-12 of sum |a b|.
+    err = np.abs(out - ref)
+    print(f"max |err| / sum|a b| = {np.max(err / np.maximum(scale, 1e-30)):.3e}")
+    assert np.all(err <= (8.0 * K * 6e-8 + 2.0 ** -12) * scale + 1e-30)
 
 
 def _check_fp8_fixed_rank(h, A, k, p_over, v, seed):
