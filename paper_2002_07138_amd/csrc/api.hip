@@ -339,8 +339,13 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
     GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots);
     if (!fits(p)) continue;
     bool dup = false;
-    for (auto& c : cands) dup |= (c.nsplit == p.nsplit);
-    if (!dup) cands.push_back(p);
+    for (auto& c : cands) dup |= (c.nsplit == p.nsplit && c.variant == 0);
+    if (dup) continue;
+    cands.push_back(p);
+    if (trans == 0) {   // direction N also tries A straight into registers
+      p.variant = 1;
+      cands.push_back(p);
+    }
   }
   if (cands.empty()) return plan_gemm(P, R, C, 1, 1);
   hipEvent_t e0, e1;
@@ -606,14 +611,41 @@ hipError_t assemble(plu_handle h, const Ws& w, int64_t m, int64_t n, int k, cons
   return launch_transpose_gather(w.bt, lp, q, n, k, U, ldu, h->stream);
 }
 
-int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int l, bool fp,
-                plu_info* info, bool sync = true) {
-  if (!info) return status;
-  if (sync) PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+// Host image of the small device results a call reports (status words,
+// scalars, rank-rule integers, pivot gaps): offsets in bytes.
+constexpr size_t kStageSt = 0, kStageSc = 160, kStageIs = 192, kStageGaps = 256;
+size_t stage_bytes(int rank) { return kStageGaps + 8 * (size_t)std::max(rank, 0); }
+
+// Queues the copies of that image into host memory `host` on stream s.
+hipError_t stage_info(const Ws& w, int rank, unsigned char* host, hipStream_t s) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(host + kStageSt, w.status, 40 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          s)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(host + kStageSc, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                          s)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(host + kStageIs, w.iscal, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          s)) != hipSuccess)
+    return e;
+  if (rank > 0) {
+    if ((e = hipMemcpyAsync(host + kStageGaps, w.gaps1, rank * sizeof(float),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return e;
+    if ((e = hipMemcpyAsync(host + kStageGaps + 4 * (size_t)rank, w.gaps2, rank * sizeof(float),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// Fills *info from a host image of the results (see stage_info).
+int info_from_stage(const unsigned char* host, int status, int rank, int passes, int l, bool fp,
+                    plu_info* info) {
   int32_t st[40];
   double sc[4];
-  PLU_TRY_HIP(hipMemcpy(st, w.status, sizeof(st), hipMemcpyDeviceToHost));
-  PLU_TRY_HIP(hipMemcpy(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost));
+  std::memcpy(st, host + kStageSt, sizeof(st));
+  std::memcpy(sc, host + kStageSc, sizeof(sc));
   std::memset(info, 0, sizeof(*info));
   info->rank = rank;
   info->passes = passes;
@@ -622,16 +654,14 @@ int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int
   info->E_final = fp ? sc[1] : 0.0;
   info->tol_reached = fp ? 1 : 0;
   int zp = INT32_MAX;
-  bool timeout = false;
-  if (st[32] != 0) timeout = true;
+  const bool timeout = st[32] != 0;
   for (int wch = 1; wch <= 2; ++wch) zp = std::min(zp, st[4 * wch]);
   info->zero_pivot_step = (zp == INT32_MAX) ? -1 : zp;
   float mg = 1.f;
-  if (rank > 0) {
-    std::vector<float> g(2 * rank);
-    PLU_TRY_HIP(hipMemcpy(g.data(), w.gaps1, rank * sizeof(float), hipMemcpyDeviceToHost));
-    PLU_TRY_HIP(hipMemcpy(g.data() + rank, w.gaps2, rank * sizeof(float), hipMemcpyDeviceToHost));
-    for (float x : g) mg = std::min(mg, x);
+  for (int i = 0; i < 2 * rank; ++i) {
+    float x;
+    std::memcpy(&x, host + kStageGaps + 4 * (size_t)i, sizeof(x));
+    mg = std::min(mg, x);
   }
   info->min_pivot_gap = mg;
   if (timeout) status = PLU_ERR_TIMEOUT;
@@ -639,6 +669,23 @@ int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int
   else if (status == PLU_OK && info->zero_pivot_step >= 0) status = PLU_WARN_ZERO_PIVOT;
   info->status = status;
   return status;
+}
+
+int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int l, bool fp,
+                plu_info* info) {
+  if (!info) return status;
+  PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+  std::vector<unsigned char> host(stage_bytes(rank));
+  PLU_TRY_HIP(hipMemcpy(host.data() + kStageSt, w.status, 40 * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+  PLU_TRY_HIP(hipMemcpy(host.data() + kStageSc, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost));
+  if (rank > 0) {
+    PLU_TRY_HIP(hipMemcpy(host.data() + kStageGaps, w.gaps1, rank * sizeof(float),
+                          hipMemcpyDeviceToHost));
+    PLU_TRY_HIP(hipMemcpy(host.data() + kStageGaps + 4 * (size_t)rank, w.gaps2,
+                          rank * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  return info_from_stage(host.data(), status, rank, passes, l, fp, info);
 }
 
 void drop_graph(plu_handle h) {
@@ -831,6 +878,9 @@ struct ServerJob {
   size_t head = 0;
   hipEvent_t ev = nullptr;     // recorded after the launch group holding its last step
   bool waiting = false;        // all recorded steps issued, waiting for ev
+  int slot = -1;               // its slot: index of its pinned result image
+  hipEvent_t up = nullptr;     // recorded after the copy of A on the upload stream
+  bool uploaded = false;       // that copy has landed: its steps may be issued
   plu_result res{};
 };
 
@@ -847,8 +897,17 @@ size_t server_footprint(const plu_request& r, int64_t l, int64_t cap, size_t* ws
 
 struct plu_server_s {
   plu_handle h = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;    // compute stream (all recorded steps)
+  hipStream_t cstream = nullptr;   // copy-out stream of the finisher
+  hipStream_t ustream = nullptr;   // upload stream (copies of A)
+  unsigned char* ostage = nullptr; // finisher: pinned staging of strided results
+  size_t ostage_cap = 0;
   Pool pool;
+  // per slot: pinned host image of a problem's small results (stage_info),
+  // written by copies queued on the compute stream behind its last step
+  std::vector<unsigned char*> stage;
+  std::vector<size_t> stage_cap;
+  std::vector<int> free_slots;
   int max_slots = 1;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
@@ -866,6 +925,12 @@ struct plu_server_s {
   int fatal = 0;
   MergeStats stats;       // grouped launches and the steps they carried
   size_t batches = 0;
+  // worker-thread time (seconds): idle, waiting for the device, recording
+  // admitted problems, planning and issuing launch groups; and the sum over
+  // batches of the problems with steps left
+  double t_idle = 0, t_devwait = 0, t_record = 0, t_issue = 0;
+  double t_copyout = 0;   // finisher thread: copying results out
+  size_t sum_ready = 0;
 };
 
 namespace {
@@ -890,22 +955,43 @@ void server_loop(plu_server S) {
   plu_handle h = S->h;
   constexpr size_t kGroupsPerIter = 32;
   std::deque<hipEvent_t> inflight;   // one event per issued batch of groups
+  auto ready = [](const ServerJob* j) { return j->uploaded && !j->waiting; };
   for (;;) {
+    // copies of A that have landed (only this thread changes `active`)
+    hipEvent_t upwait = nullptr;
+    for (auto& up : S->active) {
+      ServerJob* j = up.get();
+      if (j->uploaded) continue;
+      if (!j->up) {   // the upload failed (reported as fatal)
+        j->uploaded = true;
+        continue;
+      }
+      if (hipEventQuery(j->up) == hipSuccess) {
+        j->uploaded = true;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->events.push_back(j->up);
+        j->up = nullptr;
+      } else if (!upwait) {
+        upwait = j->up;
+      }
+    }
     std::vector<ServerJob*> admitted;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       bool runnable = false;
       for (auto& up : S->active)
-        if (!up->waiting) runnable = true;
-      if (!runnable && inflight.empty()) {
+        if (ready(up.get())) runnable = true;
+      if (!runnable && inflight.empty() && !upwait) {
+        const auto tw = std::chrono::steady_clock::now();
         S->cv_work.wait(lk, [&] {
           bool r = false;
           for (auto& up : S->active)
-            if (!up->waiting) r = true;
+            if (ready(up.get())) r = true;
           return S->stop || r ||
                  (!S->pending.empty() &&
                   (int)S->active.size() + S->nfinishing < S->max_slots);
         });
+        S->t_idle += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
       }
       if (S->stop && S->pending.empty() && S->active.empty() && S->nfinishing == 0 &&
           inflight.empty())
@@ -916,12 +1002,15 @@ void server_loop(plu_server S) {
         size_t off = 0;
         if (!S->pool.alloc(j->pool_bytes, &off)) break;
         j->pool_off = off;
+        j->slot = S->free_slots.back();
+        S->free_slots.pop_back();
         j->res.t_admit = now_s(S->t0);
         S->active.push_back(std::move(S->pending.front()));
         S->pending.pop_front();
         admitted.push_back(j);
       }
     }
+    const auto trec = std::chrono::steady_clock::now();
     for (ServerJob* j : admitted) {
       char* b = S->pool.base + j->pool_off;
       auto take = [&](size_t bytes) {
@@ -942,8 +1031,38 @@ void server_loop(plu_server S) {
       d.ldu = r.n;
       d.Omega = nullptr;
       char* ws = take(j->ws_bytes);
-      (void)hipMemcpy2DAsync(const_cast<float*>(d.A), (size_t)r.n * 4, r.A, (size_t)r.lda * 4,
-                             (size_t)r.n * 4, (size_t)r.m, hipMemcpyHostToDevice, S->stream);
+      const size_t sneed = stage_bytes((int)j->cap);
+      if (S->stage_cap[j->slot] < sneed) {
+        // the slot is free: no copy into its old image is in flight
+        if (S->stage[j->slot]) (void)hipHostFree(S->stage[j->slot]);
+        S->stage[j->slot] = nullptr;
+        S->stage_cap[j->slot] = 0;
+        const size_t c = std::max<size_t>(sneed + sneed / 2, 16384);
+        if (hipHostMalloc(reinterpret_cast<void**>(&S->stage[j->slot]), c,
+                          hipHostMallocDefault) == hipSuccess)
+          S->stage_cap[j->slot] = c;
+        else {
+          S->stage[j->slot] = nullptr;
+          std::lock_guard<std::mutex> lk(S->mu);
+          S->fatal = PLU_ERR_OOM;
+        }
+      }
+      // A goes up on its own stream, overlapping the steps of other problems
+      hipError_t eu;
+      if (r.lda == r.n)
+        eu = hipMemcpyAsync(const_cast<float*>(d.A), r.A, (size_t)r.m * r.n * 4,
+                            hipMemcpyHostToDevice, S->ustream);
+      else
+        eu = hipMemcpy2DAsync(const_cast<float*>(d.A), (size_t)r.n * 4, r.A, (size_t)r.lda * 4,
+                              (size_t)r.n * 4, (size_t)r.m, hipMemcpyHostToDevice, S->ustream);
+      j->up = take_event(S);
+      j->uploaded = false;
+      if (eu == hipSuccess && j->up) eu = hipEventRecord(j->up, S->ustream);
+      if (eu != hipSuccess || !j->up) {
+        std::fprintf(stderr, "libpowerlu server: upload: %s\n", hipGetErrorString(eu));
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->fatal = PLU_ERR_HIP;
+      }
       BatchProblem& bp = j->bp;
       bp.r = &d;
       bp.hs = *h;
@@ -969,27 +1088,41 @@ void server_loop(plu_server S) {
       j->waiting = false;
       if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
     }
+    S->t_record += std::chrono::duration<double>(std::chrono::steady_clock::now() - trec).count();
     // issue one batch of merged groups over the problems with steps left
     std::vector<const Recorder*> lists;
     std::vector<size_t> heads;
     std::vector<ServerJob*> js;
     for (auto& up : S->active)
-      if (!up->waiting) {
+      if (ready(up.get())) {
         lists.push_back(&up->bp.rec);
         heads.push_back(up->head);
         js.push_back(up.get());
       }
     if (!js.empty()) {
       // bound the queue: wait for the batch before last
+      const auto tw = std::chrono::steady_clock::now();
       while (inflight.size() >= 2) {
         (void)hipEventSynchronize(inflight.front());
         std::lock_guard<std::mutex> lk(S->mu);
         S->events.push_back(inflight.front());
         inflight.pop_front();
       }
+      const auto ti = std::chrono::steady_clock::now();
+      S->t_devwait += std::chrono::duration<double>(ti - tw).count();
       hipError_t e = run_merged_steps(lists, heads, S->stream, h->cu_count, kGroupsPerIter,
                                       h->mbuf, &S->stats);
+      // problems with all steps issued: queue the copies of their small
+      // results behind them, so that the event below covers those too
+      for (size_t i = 0; i < js.size() && e == hipSuccess; ++i) {
+        ServerJob* j = js[i];
+        if (heads[i] < j->bp.rec.ops.size() || !S->stage[j->slot]) continue;
+        const int rk = j->dev.mode == 0 ? j->dev.k : j->phase == 1 ? 0 : j->bp.k;
+        e = stage_info(j->bp.w, rk, S->stage[j->slot], S->stream);
+      }
+      S->t_issue += std::chrono::duration<double>(std::chrono::steady_clock::now() - ti).count();
       ++S->batches;
+      S->sum_ready += js.size();
       hipEvent_t ev = take_event(S);
       if (e == hipSuccess && ev) e = hipEventRecord(ev, S->stream);
       if (e != hipSuccess || !ev) {
@@ -1006,10 +1139,17 @@ void server_loop(plu_server S) {
         }
       }
     } else if (!inflight.empty()) {
+      const auto tw = std::chrono::steady_clock::now();
       (void)hipEventSynchronize(inflight.front());
+      S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
       std::lock_guard<std::mutex> lk(S->mu);
       S->events.push_back(inflight.front());
       inflight.pop_front();
+    } else if (upwait) {
+      // nothing to issue until a copy of A lands
+      const auto tw = std::chrono::steady_clock::now();
+      (void)hipEventSynchronize(upwait);
+      S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
     }
     // problems whose steps are all complete
     std::vector<ServerJob*> to_finish;
@@ -1022,9 +1162,9 @@ void server_loop(plu_server S) {
         BatchProblem& bp = j->bp;
         int32_t ks[2];
         double sc;
-        (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
-        (void)hipMemcpy(&sc, bp.w.scal, sizeof(sc), hipMemcpyDeviceToHost);
-        bp.k = std::isfinite(sc) ? ks[0] : 0;
+        std::memcpy(ks, S->stage[j->slot] + kStageIs, sizeof(ks));
+        std::memcpy(&sc, S->stage[j->slot] + kStageSc, sizeof(sc));
+        bp.k = std::isfinite(sc) ? std::min<int>(ks[0], (int)j->cap) : 0;
         bp.rec.ops.clear();
         thread_recorder() = &bp.rec;
         (void)batch_phase_b(bp);
@@ -1076,37 +1216,73 @@ void server_finisher(plu_server S) {
       std::lock_guard<std::mutex> lk(S->mu);
       fatal = S->fatal;
     }
+    const auto tc = std::chrono::steady_clock::now();
     if (!fatal) {
+      const unsigned char* img = S->stage[j->slot];
       int st = PLU_OK;
       if (d.mode == 1) {
         int32_t ks[2];
         double sc;
-        (void)hipMemcpy(ks, bp.w.iscal, sizeof(ks), hipMemcpyDeviceToHost);
-        (void)hipMemcpy(&sc, bp.w.scal, sizeof(sc), hipMemcpyDeviceToHost);
+        std::memcpy(ks, img + kStageIs, sizeof(ks));
+        std::memcpy(&sc, img + kStageSc, sizeof(sc));
         st = !std::isfinite(sc) ? PLU_ERR_NONFINITE : ks[1] ? PLU_OK : PLU_TOL_NOT_REACHED;
         if (!std::isfinite(sc)) k = 0;
       }
-      plu_handle_s hs = bp.hs;
-      j->res.status = finish_info(&hs, bp.w, st, k, d.v, (int)bp.l, d.mode == 1, &j->res.info,
-                                  false);
+      j->res.status = info_from_stage(img, st, k, d.v, (int)bp.l, d.mode == 1, &j->res.info);
       if (d.mode == 1) j->res.info.tol_reached = st == PLU_OK ? 1 : 0;
       j->res.rank = k;
-      (void)hipMemcpy(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost);
-      (void)hipMemcpy(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost);
-      if (k > 0) {
-        (void)hipMemcpy2D(r.L, (size_t)r.ldl * 4, d.L, (size_t)d.ldl * 4, (size_t)k * 4,
-                          (size_t)r.m, hipMemcpyDeviceToHost);
-        (void)hipMemcpy2D(r.U, (size_t)r.ldu * 4, d.U, (size_t)d.ldu * 4, (size_t)r.n * 4,
-                          (size_t)k, hipMemcpyDeviceToHost);
+      // p, q and contiguous blocks straight into the client's memory; a
+      // strided block (fewer than ld columns) through pinned staging: copies
+      // of strided rows into pageable memory go row by row
+      hipError_t e = hipMemcpyAsync(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost, S->cstream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost, S->cstream);
+      struct Blk {
+        float* dst;
+        int64_t ldd;
+        const float* src;
+        int64_t lds, rows, cols;
+      };
+      const Blk blks[2] = {{r.L, r.ldl, d.L, d.ldl, r.m, k}, {r.U, r.ldu, d.U, d.ldu, k, r.n}};
+      for (const Blk& bk : blks) {
+        if (k <= 0 || e != hipSuccess) break;
+        const size_t row = (size_t)bk.cols * 4, bytes = row * (size_t)bk.rows;
+        if (bk.ldd == bk.cols && bk.lds == bk.cols) {
+          e = hipMemcpyAsync(bk.dst, bk.src, bytes, hipMemcpyDeviceToHost, S->cstream);
+          continue;
+        }
+        if (S->ostage_cap < bytes) {
+          if ((e = hipStreamSynchronize(S->cstream)) != hipSuccess) break;
+          if (S->ostage) (void)hipHostFree(S->ostage);
+          S->ostage = nullptr;
+          S->ostage_cap = 0;
+          const size_t c = bytes + bytes / 2;
+          if ((e = hipHostMalloc(reinterpret_cast<void**>(&S->ostage), c, hipHostMallocDefault)) !=
+              hipSuccess) {
+            S->ostage = nullptr;
+            break;
+          }
+          S->ostage_cap = c;
+        }
+        e = hipMemcpy2DAsync(S->ostage, row, bk.src, (size_t)bk.lds * 4, row, (size_t)bk.rows,
+                             hipMemcpyDeviceToHost, S->cstream);
+        if (e == hipSuccess) e = hipStreamSynchronize(S->cstream);
+        if (e != hipSuccess) break;
+        for (int64_t i = 0; i < bk.rows; ++i)
+          std::memcpy(bk.dst + i * bk.ldd, S->ostage + i * row, row);
       }
+      if (e == hipSuccess) e = hipStreamSynchronize(S->cstream);
+      if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
     } else {
       j->res.status = fatal;
     }
     j->res.t_done = now_s(S->t0);
     {
       std::lock_guard<std::mutex> lk(S->mu);
+      S->t_copyout += std::chrono::duration<double>(std::chrono::steady_clock::now() - tc).count();
       S->done[j->ticket] = j->res;
       S->pool.release(j->pool_off, j->pool_bytes);
+      S->free_slots.push_back(j->slot);
       --S->nfinishing;
       S->cv_done.notify_all();
       S->cv_work.notify_one();   // memory freed: admission may proceed
@@ -1713,7 +1889,25 @@ int plu_server_create(plu_server* out, int device, size_t hbm_budget_bytes, int3
     return PLU_ERR_HIP;
   }
   h->stream = S->stream;
+  if (hipStreamCreateWithFlags(&S->cstream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(S->stream);
+    plu_destroy(h);
+    delete S;
+    return PLU_ERR_HIP;
+  }
+  if (hipStreamCreateWithFlags(&S->ustream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(S->cstream);
+    (void)hipStreamDestroy(S->stream);
+    plu_destroy(h);
+    delete S;
+    return PLU_ERR_HIP;
+  }
+  S->stage.assign(max_slots, nullptr);
+  S->stage_cap.assign(max_slots, 0);
+  for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
   if (!S->pool.init(hbm_budget_bytes)) {
+    (void)hipStreamDestroy(S->ustream);
+    (void)hipStreamDestroy(S->cstream);
     (void)hipStreamDestroy(S->stream);
     plu_destroy(h);
     delete S;
@@ -1783,11 +1977,21 @@ int plu_server_destroy(plu_server S) {
   if (S->finisher.joinable()) S->finisher.join();
   (void)hipStreamSynchronize(S->stream);
   if (const char* e = std::getenv("PLU_SERVER_STATS"); e && e[0] == '1')
-    std::fprintf(stderr, "libpowerlu server: %zu batches, %zu grouped launches carrying %zu steps\n",
-                 S->batches, S->stats.launches, S->stats.recorded);
+    std::fprintf(stderr,
+                 "libpowerlu server: %zu batches (%.1f problems with steps left on average), "
+                 "%zu grouped launches carrying %zu steps; worker seconds: idle %.2f, device wait "
+                 "%.2f, recording %.2f, issuing %.2f; finisher seconds copying out %.2f\n",
+                 S->batches, S->batches ? (double)S->sum_ready / S->batches : 0.0,
+                 S->stats.launches, S->stats.recorded, S->t_idle, S->t_devwait, S->t_record,
+                 S->t_issue, S->t_copyout);
   for (hipEvent_t e : S->events) (void)hipEventDestroy(e);
   if (S->pool.base) (void)hipFree(S->pool.base);
+  for (unsigned char* p : S->stage)
+    if (p) (void)hipHostFree(p);
+  if (S->ostage) (void)hipHostFree(S->ostage);
   plu_destroy(S->h);
+  (void)hipStreamDestroy(S->ustream);
+  (void)hipStreamDestroy(S->cstream);
   (void)hipStreamDestroy(S->stream);
   delete S;
   return PLU_OK;

@@ -118,6 +118,16 @@ struct CholArgs {
 constexpr double kCholRatioMin = 1e-4;
 
 __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
+  // Blocked (16 columns) right-looking Cholesky of the bw x bw Gram matrix,
+  // then X = L^{-1} by blocks of 16 rows, all in LDS (float64):
+  //   factor: the diagonal block by one wave (16 wave-synchronous steps), the
+  //           panel below by a row-parallel triangular solve, the trailing
+  //           matrix by a rank-16 update -- three barriers per block;
+  //   inverse: for each block I of rows, T = E_I - L(I, :I) X(:I, :) in
+  //           parallel, then X(I, :) = L_II^{-1} T column-parallel -- two
+  //           barriers per block.
+  // X is lower triangular; X[r][c] (c <= r) is stored at S[c][r + 1], the
+  // upper part that the factor does not use.
   (void)gr;
   const double* W = ca.W;
   const int bw = ca.bw;
@@ -126,37 +136,74 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   double* Rinv64 = ca.Rinv64;
   int32_t* status = ca.status;
   if (ca.run_if && *ca.run_if == 0) return;
+  constexpr int NBk = 16;
   __shared__ int bad;
   __shared__ double S[QB][QB + 1];
-  __shared__ double cj[QB];
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const int tx = t & 15, ty = t >> 4;
   if (t == 0) bad = 0;
   for (int r = ty; r < bw; r += 16)
     for (int c = tx; c <= r; c += 16) S[r][c] = W[r * bw + c];
   __syncthreads();
-  // right-looking Cholesky, two barriers per column
-  for (int j = 0; j < bw; ++j) {
-    double d = S[j][j];
-    if (!(d > 0.0)) {
-      if (t == 0) {
-        status[2] = 1;
-        bad = 1;
+  for (int J = 0; J < bw; J += NBk) {
+    const int nb = (bw - J < NBk) ? bw - J : NBk;
+    // (1) diagonal block, one wave; LDS operations of a wave complete in order
+    if (wave == 0) {
+      for (int jj = 0; jj < nb; ++jj) {
+        const int j = J + jj;
+        double d = S[j][j];
+        if (!(d > 0.0)) {
+          if (lane == 0) {
+            status[2] = 1;
+            bad = 1;
+          }
+          d = DBL_MIN;
+        }
+        const double sd = sqrt(d);
+        const double rp = 1.0 / sd;
+        if (lane < nb - jj - 1) S[j + 1 + lane][j] *= rp;
+        if (lane == 0) S[j][j] = sd;
+        __builtin_amdgcn_wave_barrier();
+        // rank-1 update of the rest of the diagonal block
+        const int rem = nb - jj - 1;
+        for (int e = lane; e < rem * rem; e += 64) {
+          const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+          if (c <= i) S[i][c] = fma(-S[i][j], S[c][j], S[i][c]);
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      d = DBL_MIN;
-    }
-    const double sd = sqrt(d);
-    const double rp = 1.0 / sd;
-    for (int i = j + 1 + t; i < bw; i += 256) {
-      const double v = S[i][j] * rp;
-      cj[i] = v;
-      S[i][j] = v;
     }
     __syncthreads();
-    if (t == 0) S[j][j] = sd;
-    for (int i = j + 1 + ty; i < bw; i += 16) {
-      const double lij = cj[i];
-      for (int c = j + 1 + tx; c <= i; c += 16) S[i][c] = fma(-lij, cj[c], S[i][c]);
+    // (2) panel: rows below the block, L(i, J:J+nb) = A(i, J:J+nb) L_JJ^{-T}
+    {
+      const int i = J + nb + t;
+      if (i < bw) {
+        double v[NBk];
+#pragma unroll
+        for (int jj = 0; jj < NBk; ++jj) {
+          if (jj < nb) {
+            double a = S[i][J + jj];
+#pragma unroll
+            for (int kk = 0; kk < jj; ++kk) a = fma(-v[kk], S[J + jj][J + kk], a);
+            v[jj] = a / S[J + jj][J + jj];
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < NBk; ++jj)
+          if (jj < nb) S[i][J + jj] = v[jj];
+      }
+    }
+    __syncthreads();
+    // (3) trailing update, lower triangle
+    for (int i = J + nb + ty; i < bw; i += 16) {
+      for (int c = J + nb + tx; c <= i; c += 16) {
+        double a = S[i][c];
+#pragma unroll
+        for (int kk = 0; kk < NBk; ++kk)
+          if (kk < nb) a = fma(-S[i][J + kk], S[c][J + kk], a);
+        S[i][c] = a;
+      }
     }
     __syncthreads();
   }
@@ -168,18 +215,28 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
     }
     *ca.need_lu = (bad || !(mn > kCholRatioMin * mx)) ? 1 : 0;
   }
-  // X = L^{-1} by right-looking forward substitution on X = I: row k of X is
-  // final once divided by L[k][k]; it then updates rows k+1.. in parallel.
-  for (int i = ty; i < bw; i += 16)
-    for (int c = tx; c <= i; c += 16) S[c][i + 1] = (c == i) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int k = 0; k < bw; ++k) {
-    const double rk = 1.0 / S[k][k];
-    for (int c = t; c <= k; c += 256) S[c][k + 1] *= rk;
+  // X = L^{-1}, block row by block row
+  for (int I0 = 0; I0 < bw; I0 += NBk) {
+    const int nb = (bw - I0 < NBk) ? bw - I0 : NBk;
+    // (a) T(r, c) = [r == c] - sum_{c <= m < I0} L[r][m] X[m][c], r in the block,
+    //     c <= r; stored in X's slots S[c][r + 1]
+    for (int e = t; e < nb * (I0 + nb); e += 256) {
+      const int r = I0 + e / (I0 + nb), c = e % (I0 + nb);
+      if (c > r) continue;
+      double a = (r == c) ? 1.0 : 0.0;
+      for (int m = c; m < I0; ++m) a = fma(-S[r][m], S[c][m + 1], a);
+      S[c][r + 1] = a;
+    }
     __syncthreads();
-    for (int i = k + 1 + ty; i < bw; i += 16) {
-      const double lik = S[i][k];
-      for (int c = tx; c <= k; c += 16) S[c][i + 1] = fma(-lik, S[c][k + 1], S[c][i + 1]);
+    // (b) X(I, c) = L_II^{-1} T(:, c), each column c by one thread
+    for (int c = t; c < I0 + nb; c += 256) {
+      for (int rr = 0; rr < nb; ++rr) {
+        const int r = I0 + rr;
+        if (c > r) continue;
+        double a = S[c][r + 1];
+        for (int m = (c > I0 ? c : I0); m < r; ++m) a = fma(-S[r][m], S[c][m + 1], a);
+        S[c][r + 1] = a / S[r][r];
+      }
     }
     __syncthreads();
   }
