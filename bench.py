@@ -204,12 +204,13 @@ def batched_vs_single(h, pool, count=32):
 def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
     """Replay of a Poisson request stream through the serving loop: requests
     cycle the pool's matrices (host, pinned); latency = completion minus
-    scheduled arrival."""
+    scheduled arrival.  rate None: every request submitted at once (the
+    loop's capacity)."""
     import threading
     import numpy as np
     import paper_2002_07138_amd as plu
     rng = np.random.default_rng(seed + 1)
-    gaps = rng.exponential(1.0 / rate, count)
+    gaps = rng.exponential(1.0 / rate, count) if rate else np.zeros(count)
     sched = np.cumsum(gaps)
     srv = plu.Server(0, hbm_budget_bytes=int(budget_gb) << 30, max_slots=slots)
     tickets, late, meta = [], [], []
@@ -386,6 +387,7 @@ def main():
         out = {"batched": batched_vs_single(h, pool)}
         h.close()
         out["serving"] = serving(pool, count=args.serving_count)
+        out["serving_burst"] = serving(pool, count=max(args.serving_count // 2, 1), rate=None)
         print(json.dumps(out))
         return
     t_gen = time.perf_counter()
@@ -527,6 +529,7 @@ def main():
         torch.cuda.empty_cache()
         result["serving"] = serving(pool, count=args.serving_count)
         result["serving"]["pool_generation_s"] = round(t_pool, 2)
+        result["serving_burst"] = serving(pool, count=max(args.serving_count // 2, 1), rate=None)
     h.close()
     print(json.dumps(result))
 

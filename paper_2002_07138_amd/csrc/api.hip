@@ -876,11 +876,12 @@ struct ServerJob {
   BatchProblem bp;
   int phase = 0;               // 1: main steps, 2: fixed-precision assembly
   size_t head = 0;
-  hipEvent_t ev = nullptr;     // recorded after the launch group holding its last step
+  uint64_t done_seq = 0;       // the launch batch holding its last step
   bool waiting = false;        // all recorded steps issued, waiting for ev
   int slot = -1;               // its slot: index of its pinned result image
   hipEvent_t up = nullptr;     // recorded after the copy of A on the upload stream
   bool uploaded = false;       // that copy has landed: its steps may be issued
+  double t_up = 0, t_issued = 0, t_computed = 0;   // server-side timestamps
   plu_result res{};
 };
 
@@ -898,10 +899,16 @@ size_t server_footprint(const plu_request& r, int64_t l, int64_t cap, size_t* ws
 struct plu_server_s {
   plu_handle h = nullptr;
   hipStream_t stream = nullptr;    // compute stream (all recorded steps)
-  hipStream_t cstream = nullptr;   // copy-out stream of the finisher
   hipStream_t ustream = nullptr;   // upload stream (copies of A)
-  unsigned char* ostage = nullptr; // finisher: pinned staging of strided results
-  size_t ostage_cap = 0;
+  // finisher threads, each with its copy-out stream and pinned staging of
+  // strided results
+  struct Finisher {
+    hipStream_t cs = nullptr;
+    unsigned char* ostage = nullptr;
+    size_t cap = 0;
+    std::thread th;
+  };
+  std::vector<Finisher> fins;
   Pool pool;
   // per slot: pinned host image of a problem's small results (stage_info),
   // written by copies queued on the compute stream behind its last step
@@ -920,7 +927,7 @@ struct plu_server_s {
   std::vector<hipEvent_t> events;                    // free event objects
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker, finisher;
+  std::thread worker;
   int device = 0;
   int fatal = 0;
   MergeStats stats;       // grouped launches and the steps they carried
@@ -930,7 +937,11 @@ struct plu_server_s {
   // batches of the problems with steps left
   double t_idle = 0, t_devwait = 0, t_record = 0, t_issue = 0;
   double t_copyout = 0;   // finisher thread: copying results out
-  size_t sum_ready = 0;
+  // sums over problems: admission to upload landed, to last step issued, to
+  // last step complete, to copied out
+  double s_up = 0, s_issue = 0, s_compute = 0, s_out = 0;
+  size_t n_done = 0;
+  size_t sum_ready = 0, sum_active = 0, sum_pending = 0, budget_stops = 0;
 };
 
 namespace {
@@ -954,7 +965,35 @@ void server_loop(plu_server S) {
   (void)hipSetDevice(S->device);
   plu_handle h = S->h;
   constexpr size_t kGroupsPerIter = 32;
-  std::deque<hipEvent_t> inflight;   // one event per issued batch of groups
+  // issued launch batches (sequence number, event recorded after it), oldest
+  // first; batches complete in order on the one compute stream
+  std::deque<std::pair<uint64_t, hipEvent_t>> inflight;
+  uint64_t seq = 0, completed = 0;
+  // retires completed batches; with block, waits for the oldest first.  An
+  // event goes back to the pool only here, once nothing refers to it.
+  auto retire = [&](bool block) {
+    bool first = true;
+    while (!inflight.empty()) {
+      hipEvent_t e = inflight.front().second;
+      if (!e) {   // no event could be recorded (reported as fatal)
+        completed = inflight.front().first;
+        inflight.pop_front();
+        continue;
+      }
+      if (block && first) {
+        const auto tw = std::chrono::steady_clock::now();
+        (void)hipEventSynchronize(e);
+        S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
+      } else if (hipEventQuery(e) != hipSuccess) {
+        break;
+      }
+      first = false;
+      completed = inflight.front().first;
+      inflight.pop_front();
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->events.push_back(e);
+    }
+  };
   auto ready = [](const ServerJob* j) { return j->uploaded && !j->waiting; };
   for (;;) {
     // copies of A that have landed (only this thread changes `active`)
@@ -968,6 +1007,7 @@ void server_loop(plu_server S) {
       }
       if (hipEventQuery(j->up) == hipSuccess) {
         j->uploaded = true;
+        j->t_up = now_s(S->t0);
         std::lock_guard<std::mutex> lk(S->mu);
         S->events.push_back(j->up);
         j->up = nullptr;
@@ -1000,7 +1040,10 @@ void server_loop(plu_server S) {
       while (!S->pending.empty() && (int)S->active.size() + S->nfinishing < S->max_slots) {
         ServerJob* j = S->pending.front().get();
         size_t off = 0;
-        if (!S->pool.alloc(j->pool_bytes, &off)) break;
+        if (!S->pool.alloc(j->pool_bytes, &off)) {
+          ++S->budget_stops;
+          break;
+        }
         j->pool_off = off;
         j->slot = S->free_slots.back();
         S->free_slots.pop_back();
@@ -1101,15 +1144,8 @@ void server_loop(plu_server S) {
       }
     if (!js.empty()) {
       // bound the queue: wait for the batch before last
-      const auto tw = std::chrono::steady_clock::now();
-      while (inflight.size() >= 2) {
-        (void)hipEventSynchronize(inflight.front());
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->events.push_back(inflight.front());
-        inflight.pop_front();
-      }
+      while (inflight.size() >= 2) retire(true);
       const auto ti = std::chrono::steady_clock::now();
-      S->t_devwait += std::chrono::duration<double>(ti - tw).count();
       hipError_t e = run_merged_steps(lists, heads, S->stream, h->cu_count, kGroupsPerIter,
                                       h->mbuf, &S->stats);
       // problems with all steps issued: queue the copies of their small
@@ -1123,6 +1159,11 @@ void server_loop(plu_server S) {
       S->t_issue += std::chrono::duration<double>(std::chrono::steady_clock::now() - ti).count();
       ++S->batches;
       S->sum_ready += js.size();
+      S->sum_active += S->active.size();
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->sum_pending += S->pending.size();
+      }
       hipEvent_t ev = take_event(S);
       if (e == hipSuccess && ev) e = hipEventRecord(ev, S->stream);
       if (e != hipSuccess || !ev) {
@@ -1130,21 +1171,17 @@ void server_loop(plu_server S) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->fatal = PLU_ERR_HIP;
       }
-      inflight.push_back(ev);
+      inflight.push_back({++seq, ev});
       for (size_t i = 0; i < js.size(); ++i) {
         js[i]->head = heads[i];
         if (js[i]->head >= js[i]->bp.rec.ops.size()) {
           js[i]->waiting = true;
-          js[i]->ev = ev;
+          js[i]->done_seq = seq;
+          js[i]->t_issued = now_s(S->t0);
         }
       }
     } else if (!inflight.empty()) {
-      const auto tw = std::chrono::steady_clock::now();
-      (void)hipEventSynchronize(inflight.front());
-      S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->events.push_back(inflight.front());
-      inflight.pop_front();
+      retire(true);
     } else if (upwait) {
       // nothing to issue until a copy of A lands
       const auto tw = std::chrono::steady_clock::now();
@@ -1152,11 +1189,12 @@ void server_loop(plu_server S) {
       S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
     }
     // problems whose steps are all complete
+    retire(false);
     std::vector<ServerJob*> to_finish;
     for (auto& up : S->active) {
       ServerJob* j = up.get();
       if (!j->waiting) continue;
-      if (!S->fatal && hipEventQuery(j->ev) != hipSuccess) continue;
+      if (!S->fatal && completed < j->done_seq) continue;
       if (!S->fatal && j->dev.mode == 1 && j->phase == 1) {
         // the rank decides the assembly: read it, then record the rest
         BatchProblem& bp = j->bp;
@@ -1185,17 +1223,19 @@ void server_loop(plu_server S) {
             S->active.erase(it);
             break;
           }
+        j->t_computed = now_s(S->t0);
         S->finishing.push_back(j);
         ++S->nfinishing;
       }
-      S->cv_fin.notify_one();
+      S->cv_fin.notify_all();
     }
   }
 }
 
 // Copies finished problems out (host buffers of the client), fills their
 // results and frees their device memory, off the launch thread.
-void server_finisher(plu_server S) {
+void server_finisher(plu_server S, int idx) {
+  plu_server_s::Finisher& F = S->fins[idx];
   (void)hipSetDevice(S->device);
   for (;;) {
     ServerJob* j = nullptr;
@@ -1234,9 +1274,9 @@ void server_finisher(plu_server S) {
       // p, q and contiguous blocks straight into the client's memory; a
       // strided block (fewer than ld columns) through pinned staging: copies
       // of strided rows into pageable memory go row by row
-      hipError_t e = hipMemcpyAsync(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost, S->cstream);
+      hipError_t e = hipMemcpyAsync(r.p, d.p, (size_t)r.m * 4, hipMemcpyDeviceToHost, F.cs);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost, S->cstream);
+        e = hipMemcpyAsync(r.q, d.q, (size_t)r.n * 4, hipMemcpyDeviceToHost, F.cs);
       struct Blk {
         float* dst;
         int64_t ldd;
@@ -1248,30 +1288,30 @@ void server_finisher(plu_server S) {
         if (k <= 0 || e != hipSuccess) break;
         const size_t row = (size_t)bk.cols * 4, bytes = row * (size_t)bk.rows;
         if (bk.ldd == bk.cols && bk.lds == bk.cols) {
-          e = hipMemcpyAsync(bk.dst, bk.src, bytes, hipMemcpyDeviceToHost, S->cstream);
+          e = hipMemcpyAsync(bk.dst, bk.src, bytes, hipMemcpyDeviceToHost, F.cs);
           continue;
         }
-        if (S->ostage_cap < bytes) {
-          if ((e = hipStreamSynchronize(S->cstream)) != hipSuccess) break;
-          if (S->ostage) (void)hipHostFree(S->ostage);
-          S->ostage = nullptr;
-          S->ostage_cap = 0;
+        if (F.cap < bytes) {
+          if ((e = hipStreamSynchronize(F.cs)) != hipSuccess) break;
+          if (F.ostage) (void)hipHostFree(F.ostage);
+          F.ostage = nullptr;
+          F.cap = 0;
           const size_t c = bytes + bytes / 2;
-          if ((e = hipHostMalloc(reinterpret_cast<void**>(&S->ostage), c, hipHostMallocDefault)) !=
+          if ((e = hipHostMalloc(reinterpret_cast<void**>(&F.ostage), c, hipHostMallocDefault)) !=
               hipSuccess) {
-            S->ostage = nullptr;
+            F.ostage = nullptr;
             break;
           }
-          S->ostage_cap = c;
+          F.cap = c;
         }
-        e = hipMemcpy2DAsync(S->ostage, row, bk.src, (size_t)bk.lds * 4, row, (size_t)bk.rows,
-                             hipMemcpyDeviceToHost, S->cstream);
-        if (e == hipSuccess) e = hipStreamSynchronize(S->cstream);
+        e = hipMemcpy2DAsync(F.ostage, row, bk.src, (size_t)bk.lds * 4, row, (size_t)bk.rows,
+                             hipMemcpyDeviceToHost, F.cs);
+        if (e == hipSuccess) e = hipStreamSynchronize(F.cs);
         if (e != hipSuccess) break;
         for (int64_t i = 0; i < bk.rows; ++i)
-          std::memcpy(bk.dst + i * bk.ldd, S->ostage + i * row, row);
+          std::memcpy(bk.dst + i * bk.ldd, F.ostage + i * row, row);
       }
-      if (e == hipSuccess) e = hipStreamSynchronize(S->cstream);
+      if (e == hipSuccess) e = hipStreamSynchronize(F.cs);
       if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
     } else {
       j->res.status = fatal;
@@ -1281,6 +1321,11 @@ void server_finisher(plu_server S) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->t_copyout += std::chrono::duration<double>(std::chrono::steady_clock::now() - tc).count();
       S->done[j->ticket] = j->res;
+      S->s_up += j->t_up - j->res.t_admit;
+      S->s_issue += j->t_issued - j->t_up;
+      S->s_compute += j->t_computed - j->t_issued;
+      S->s_out += j->res.t_done - j->t_computed;
+      ++S->n_done;
       S->pool.release(j->pool_off, j->pool_bytes);
       S->free_slots.push_back(j->slot);
       --S->nfinishing;
@@ -1889,15 +1934,24 @@ int plu_server_create(plu_server* out, int device, size_t hbm_budget_bytes, int3
     return PLU_ERR_HIP;
   }
   h->stream = S->stream;
-  if (hipStreamCreateWithFlags(&S->cstream, hipStreamNonBlocking) != hipSuccess) {
+  // copy-out runs on several threads: one would serialize the staging copies
+  constexpr int kFinishers = 4;
+  S->fins = std::vector<plu_server_s::Finisher>(kFinishers);
+  auto drop_streams = [&]() {
+    for (auto& f : S->fins)
+      if (f.cs) (void)hipStreamDestroy(f.cs);
+    if (S->ustream) (void)hipStreamDestroy(S->ustream);
     (void)hipStreamDestroy(S->stream);
-    plu_destroy(h);
-    delete S;
-    return PLU_ERR_HIP;
-  }
-  if (hipStreamCreateWithFlags(&S->ustream, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipStreamDestroy(S->cstream);
-    (void)hipStreamDestroy(S->stream);
+  };
+  bool ok = hipStreamCreateWithFlags(&S->ustream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) S->ustream = nullptr;
+  for (auto& f : S->fins)
+    if (ok && hipStreamCreateWithFlags(&f.cs, hipStreamNonBlocking) != hipSuccess) {
+      f.cs = nullptr;
+      ok = false;
+    }
+  if (!ok) {
+    drop_streams();
     plu_destroy(h);
     delete S;
     return PLU_ERR_HIP;
@@ -1906,15 +1960,13 @@ int plu_server_create(plu_server* out, int device, size_t hbm_budget_bytes, int3
   S->stage_cap.assign(max_slots, 0);
   for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
   if (!S->pool.init(hbm_budget_bytes)) {
-    (void)hipStreamDestroy(S->ustream);
-    (void)hipStreamDestroy(S->cstream);
-    (void)hipStreamDestroy(S->stream);
+    drop_streams();
     plu_destroy(h);
     delete S;
     return PLU_ERR_OOM;
   }
   S->worker = std::thread(server_loop, S);
-  S->finisher = std::thread(server_finisher, S);
+  for (int i = 0; i < kFinishers; ++i) S->fins[i].th = std::thread(server_finisher, S, i);
   *out = S;
   return PLU_OK;
 }
@@ -1974,24 +2026,36 @@ int plu_server_destroy(plu_server S) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->cv_fin.notify_all();
   }
-  if (S->finisher.joinable()) S->finisher.join();
+  for (auto& f : S->fins)
+    if (f.th.joinable()) f.th.join();
   (void)hipStreamSynchronize(S->stream);
   if (const char* e = std::getenv("PLU_SERVER_STATS"); e && e[0] == '1')
     std::fprintf(stderr,
-                 "libpowerlu server: %zu batches (%.1f problems with steps left on average), "
+                 "libpowerlu server: %zu batches (on average %.1f problems with steps left, %.1f "
+                 "admitted, %.1f pending; %zu admission stops on the budget), "
                  "%zu grouped launches carrying %zu steps; worker seconds: idle %.2f, device wait "
-                 "%.2f, recording %.2f, issuing %.2f; finisher seconds copying out %.2f\n",
+                 "%.2f, recording %.2f, issuing %.2f; finisher seconds copying out (all threads) %.2f\n",
                  S->batches, S->batches ? (double)S->sum_ready / S->batches : 0.0,
+                 S->batches ? (double)S->sum_active / S->batches : 0.0,
+                 S->batches ? (double)S->sum_pending / S->batches : 0.0, S->budget_stops,
                  S->stats.launches, S->stats.recorded, S->t_idle, S->t_devwait, S->t_record,
                  S->t_issue, S->t_copyout);
+  if (const char* e = std::getenv("PLU_SERVER_STATS"); e && e[0] == '1' && S->n_done)
+    std::fprintf(stderr,
+                 "libpowerlu server: mean ms from admission: upload %.2f, then all steps issued "
+                 "%.2f, then complete %.2f, then copied out %.2f\n",
+                 1e3 * S->s_up / S->n_done, 1e3 * S->s_issue / S->n_done,
+                 1e3 * S->s_compute / S->n_done, 1e3 * S->s_out / S->n_done);
   for (hipEvent_t e : S->events) (void)hipEventDestroy(e);
   if (S->pool.base) (void)hipFree(S->pool.base);
   for (unsigned char* p : S->stage)
     if (p) (void)hipHostFree(p);
-  if (S->ostage) (void)hipHostFree(S->ostage);
+  for (auto& f : S->fins) {
+    if (f.ostage) (void)hipHostFree(f.ostage);
+    (void)hipStreamDestroy(f.cs);
+  }
   plu_destroy(S->h);
   (void)hipStreamDestroy(S->ustream);
-  (void)hipStreamDestroy(S->cstream);
   (void)hipStreamDestroy(S->stream);
   delete S;
   return PLU_OK;
