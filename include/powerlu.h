@@ -63,6 +63,17 @@ typedef enum {
                               rounded iterate; for v = 2 nothing is then rounded */
 } plu_prec;
 
+/* Storage order of the input matrix A (the paper's A is m x n, Def. 1.1).
+ * Row-major: element (i, j) at A[i * lda + j], lda >= n.  Column-major:
+ * element (i, j) at A[i + j * lda], lda >= m.  Only A takes a layout; every
+ * output (p, q, L, U) is row-major.  Both orders run the same kernels: a
+ * column-major A is the row-major storage of A^T, so A X and A^T Y swap
+ * directions. */
+typedef enum {
+  PLU_ROW_MAJOR = 0,
+  PLU_COL_MAJOR = 1
+} plu_layout;
+
 typedef struct plu_handle_s* plu_handle;
 
 /* Filled on request after the stream has synchronized. */
@@ -93,6 +104,7 @@ const char* plu_status_string(int status);
 
 /* ---- Fixed-rank problem (Def. 1.1, Sec. 1) solved by PowerLU: Alg. 5 with
  * its steps 1-2 replaced by Alg. 7 (Sec. 3.4).
+ *   layout storage order of A (plu_layout); lda >= n (row-major) or >= m.
  *   A      device, m x n, lda.
  *   k      target rank, 1 <= k;  p_over >= 0 oversampling (the paper's q);
  *          l = k + p_over must satisfy l < min(m, n) (Alg. 7 REQUIRE).
@@ -111,8 +123,8 @@ const char* plu_status_string(int status);
  *   p, q   device int32 outputs, lengths m and n.
  *   L, U   device outputs: L m x k (ldl >= k), U k x n (ldu >= n).
  *   info   host, nullable (non-NULL synchronizes).                        */
-int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
-                   int32_t k, int32_t p_over, int32_t v, int32_t prec,
+int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                   int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
                    const float* Omega, uint64_t seed,
                    int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
                    plu_info* info);
@@ -121,6 +133,7 @@ int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t l
  * discussion) solved by PowerLU_FP: Alg. 9 on top of Alg. 8 (block rule) or
  * Alg. 11 (column rule, column_exact = 1), with the error indicator of
  * Thm 4.3 accumulated in float64 and the stopping test E <= eps^2 ||A||_F^2.
+ *   layout, A, lda, prec, Omega, seed, p, q   as for plu_fixed_rank.
  *   eps    > 0 relative Frobenius tolerance.
  *   b      block size >= 1; l (sketch width) must be a multiple of b and
  *          < min(m, n); l = 0 selects min(50 b, b * floor((min(m,n)-1)/b)).
@@ -130,16 +143,18 @@ int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t l
  *          it; the rank is also in info).
  * If eps is not met within l columns the rank-l factorization is returned
  * with PLU_TOL_NOT_REACHED.  A zero matrix gives rank 0.                  */
-int plu_fixed_precision(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
-                        double eps, int32_t b, int32_t l, int32_t v, int32_t column_exact,
+int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                        int64_t lda, double eps, int32_t b, int32_t l, int32_t v, int32_t column_exact,
                         int32_t prec, const float* Omega, uint64_t seed,
                         int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
                         int32_t* rank_out, plu_info* info);
 
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
- *   all matrix/vector pointers device; rel_resid host.  Synchronizes.     */
-int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
+ *   all matrix/vector pointers device; rel_resid host; layout of A as in
+ *   plu_fixed_rank (L and U row-major).  Synchronizes.                      */
+int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                 int64_t lda,
                  const int32_t* p, const int32_t* q, int32_t k,
                  const float* L, int64_t ldl, const float* U, int64_t ldu,
                  double* rel_resid);
@@ -163,6 +178,25 @@ int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda
  * when the next call has the same requests (same shapes and pointers).
  * Returns PLU_OK, or -3 when some request is invalid (its status then holds
  * -i for its i-th field, counted from 1 in declaration order).             */
+/* ---- Pivot trace: the pivot rows and relative pivot gaps of every GETRF of
+ * the last plu_fixed_rank / plu_fixed_precision / plu_range_basis /
+ * plu_getrf call on the handle, in the order the paper's algorithm makes
+ * them: the LU reorthogonalizations of Alg. 7 (l steps each, lu(.) of
+ * Alg. 6/7), then lu(Y) and lu(B^T) of Alg. 5 steps 4 and 6 (k steps each).
+ * The LU inside the thin QR is an implementation detail and not traced.
+ * Entry j of a GETRF: the input row chosen as pivot at step j, and
+ * (|top1| - |top2|) / |top1| over the candidates of that step.
+ *   plu_set_pivot_trace  capacity > 0: record up to that many entries per
+ *                        call (device memory, owned by the handle); 0 stops
+ *                        recording and frees it.  Off by default.
+ *   plu_pivot_trace      synchronizes; *n_out = entries the last call made;
+ *                        copies min(cap, recorded) of them into the host
+ *                        arrays (either may be NULL).  PLU_ERR_OOM when the
+ *                        call made more entries than the capacity held.    */
+int plu_set_pivot_trace(plu_handle h, int64_t capacity);
+int plu_pivot_trace(plu_handle h, int32_t* ipiv_out, float* gaps_out, int32_t cap,
+                    int32_t* n_out);
+
 typedef struct {
   int32_t mode;            /* 0: fixed rank, 1: fixed precision */
   int32_t column_exact;    /* fixed precision: Alg. 11 column rule */
@@ -181,6 +215,7 @@ typedef struct {
   int64_t ldl;
   float* U;
   int64_t ldu;
+  int32_t layout;          /* plu_layout of A */
   int32_t rank;            /* out */
   int32_t status;          /* out: PLU_* status of this problem */
   plu_info info;           /* out */
@@ -284,10 +319,11 @@ int plu_getrf(plu_handle h, int64_t M, int32_t c, float* F, int64_t ldf,
 int plu_thin_qr(plu_handle h, int64_t M, int32_t c, float* X, int64_t ldx);
 
 /* Alg. 7 alone: V (device, n x l, ldv) = orthonormal basis after v-1 passes.
- * Omega as in plu_fixed_rank (nullable -> drawn from seed).              */
-int plu_range_basis(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
-                    int32_t l, int32_t v, int32_t prec, const float* Omega, uint64_t seed,
-                    float* V, int64_t ldv);
+ * layout, A, lda, Omega as in plu_fixed_rank (Omega nullable -> drawn from
+ * seed).                                                                  */
+int plu_range_basis(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                    int64_t lda, int32_t l, int32_t v, int32_t prec, const float* Omega,
+                    uint64_t seed, float* V, int64_t ldv);
 
 /* Thm 4.3 indicator and the Alg. 8 / Alg. 11 rule on G = A V (device,
  * m x l, ldg): column norms^2 in float64, E_j = normA2 - sum_{i<=j}, k = the

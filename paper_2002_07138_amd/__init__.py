@@ -28,12 +28,15 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 PREC_FP8_E4M3 = 2
 PREC_REFINE_LAST = 16
+LAYOUT_ROW = 0
+LAYOUT_COL = 1
 
 _ENTRY_POINTS = [
     "plu_create", "plu_destroy", "plu_set_stream", "plu_workspace_size", "plu_status_string",
     "plu_fixed_rank", "plu_fixed_precision", "plu_residual", "plu_gaussian", "plu_pass",
     "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule", "plu_quantize",
-    "plu_batched", "plu_server_create", "plu_server_submit", "plu_server_poll",
+    "plu_batched", "plu_set_pivot_trace", "plu_pivot_trace", "plu_server_create",
+    "plu_server_submit", "plu_server_poll",
     "plu_server_wait", "plu_server_destroy",
 ]
 BATCH_GRAPH = 1
@@ -64,6 +67,7 @@ class PluRequest(ctypes.Structure):
         ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
         ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
         ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+        ("layout", ctypes.c_int32),
         ("rank", ctypes.c_int32), ("status", ctypes.c_int32),
         ("info", PluInfo),
     ]
@@ -104,21 +108,24 @@ def _lib():
             "plu_set_stream": [vp, vp],
             "plu_workspace_size": [vp, i64, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
             "plu_status_string": [ctypes.c_int],
-            "plu_fixed_rank": [vp, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
+            "plu_fixed_rank": [vp, i32, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
                                vp, vp, vp, i64, vp, i64, pinfo],
-            "plu_fixed_precision": [vp, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, vp, u64,
+            "plu_fixed_precision": [vp, i32, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, vp, u64,
                                     vp, vp, vp, i64, vp, i64, ctypes.POINTER(i32), pinfo],
-            "plu_residual": [vp, i64, i64, vp, i64, vp, vp, i32, vp, i64, vp, i64,
+            "plu_residual": [vp, i32, i64, i64, vp, i64, vp, vp, i32, vp, i64, vp, i64,
                              ctypes.POINTER(dbl)],
             "plu_gaussian": [vp, i64, i64, u64, vp, i64],
             "plu_pass": [vp, i32, i64, i64, vp, i64, i32, vp, i64, vp, i64, i32, vp],
             "plu_getrf": [vp, i64, i32, vp, i64, vp, vp, i64, pinfo],
             "plu_thin_qr": [vp, i64, i32, vp, i64],
-            "plu_range_basis": [vp, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, i64],
+            "plu_range_basis": [vp, i32, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, i64],
             "plu_rank_rule": [vp, i64, i32, vp, i64, dbl, dbl, i32, i32, ctypes.POINTER(i32),
                               ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
             "plu_quantize": [vp, i32, i64, i64, vp, i64, i32, vp, i64, vp],
             "plu_batched": [vp, i32, ctypes.POINTER(PluRequest), i32],
+            "plu_set_pivot_trace": [vp, i64],
+            "plu_pivot_trace": [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32,
+                                ctypes.POINTER(i32)],
             "plu_server_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, i32],
             "plu_server_submit": [vp, ctypes.POINTER(PluRequest), ctypes.POINTER(u64)],
             "plu_server_poll": [vp, u64, ctypes.POINTER(PluResult)],
@@ -142,7 +149,7 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _check_mat(t, name, dtype="float32"):
+def _check_mat(t, name, dtype="float32", allow_col=False):
     import torch
     if t is None:
         return
@@ -152,11 +159,30 @@ def _check_mat(t, name, dtype="float32"):
     if not t.is_cuda:
         raise TypeError(f"{name}: expected a device tensor")
     if t.dim() == 2 and t.stride(1) != 1:
-        raise ValueError(f"{name}: rows must be contiguous (row-major)")
+        if not (allow_col and t.stride(0) == 1):
+            raise ValueError(f"{name}: rows must be contiguous (row-major)"
+                             + (" or columns contiguous (column-major)" if allow_col else ""))
 
 
 def _ld(t):
     return t.stride(0) if t.dim() == 2 else 1
+
+
+def _a_layout(shape, strides):
+    """Storage order of A from its element strides: rows contiguous gives
+    (LAYOUT_ROW, lda = row stride); columns contiguous gives (LAYOUT_COL,
+    lda = column stride)."""
+    m, n = shape
+    if strides[1] == 1 and (m == 1 or strides[0] >= n):
+        return LAYOUT_ROW, max(strides[0], n)
+    if strides[0] == 1 and (n == 1 or strides[1] >= m):
+        return LAYOUT_COL, max(strides[1], m)
+    raise ValueError("A: rows or columns must be contiguous")
+
+
+def _layout_of(A):
+    _check_mat(A, "A", allow_col=True)
+    return _a_layout(tuple(A.shape), (A.stride(0), A.stride(1)))
 
 
 @dataclass
@@ -275,11 +301,12 @@ class Handle:
 
     def range_basis(self, A, l, v, Omega=None, seed=0, prec=PREC_FP32):
         t = self._torch
-        _check_mat(A, "A"); _check_mat(Omega, "Omega")
+        _check_mat(Omega, "Omega")
         m, n = A.shape
         V = t.empty((n, l), dtype=t.float32, device=A.device)
-        self._rc(_lib().plu_range_basis(self._h, m, n, _ptr(A), _ld(A), l, v, prec, _ptr(Omega),
-                                        seed, _ptr(V), _ld(V)), "plu_range_basis")
+        lay, lda = _layout_of(A)
+        self._rc(_lib().plu_range_basis(self._h, lay, m, n, _ptr(A), lda, l, v, prec,
+                                        _ptr(Omega), seed, _ptr(V), _ld(V)), "plu_range_basis")
         return V
 
     def rank_rule(self, G, normA2, eps, b, column_exact=True):
@@ -297,7 +324,8 @@ class Handle:
     def fixed_rank(self, A, k, p_over, v, Omega=None, seed=0, prec=PREC_FP32, sync_info=True,
                    out=None):
         t = self._torch
-        _check_mat(A, "A"); _check_mat(Omega, "Omega")
+        _check_mat(Omega, "Omega")
+        lay, lda = _layout_of(A)
         m, n = A.shape
         dev = A.device
         if out is None:
@@ -308,7 +336,7 @@ class Handle:
         else:
             p, q, L, U = out
         info = PluInfo()
-        rc = _lib().plu_fixed_rank(self._h, m, n, _ptr(A), _ld(A), k, p_over, v, prec,
+        rc = _lib().plu_fixed_rank(self._h, lay, m, n, _ptr(A), lda, k, p_over, v, prec,
                                    _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U),
                                    _ld(U), ctypes.byref(info) if sync_info else None)
         self._rc(rc, "plu_fixed_rank", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
@@ -317,7 +345,8 @@ class Handle:
     def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,
                         prec=PREC_FP32):
         t = self._torch
-        _check_mat(A, "A"); _check_mat(Omega, "Omega")
+        _check_mat(Omega, "Omega")
+        lay, lda = _layout_of(A)
         m, n = A.shape
         dev = A.device
         lcap = l if l else min(50 * b, b * ((min(m, n) - 1) // b))
@@ -327,7 +356,7 @@ class Handle:
         U = t.empty((lcap, n), dtype=t.float32, device=dev)
         k = ctypes.c_int32()
         info = PluInfo()
-        rc = _lib().plu_fixed_precision(self._h, m, n, _ptr(A), _ld(A), float(eps), b, l, v,
+        rc = _lib().plu_fixed_precision(self._h, lay, m, n, _ptr(A), lda, float(eps), b, l, v,
                                         1 if column_exact else 0, prec, _ptr(Omega), seed,
                                         _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
                                         ctypes.byref(k), ctypes.byref(info))
@@ -346,12 +375,12 @@ class Handle:
         keep = []
         for r, pr in zip(reqs, problems):
             A = pr["A"]
-            _check_mat(A, "A")
+            lay, lda = _layout_of(A)
             m, n = A.shape
             mode = int(pr.get("mode", 0))
             r.mode = mode
             r.column_exact = 1 if pr.get("column_exact", True) else 0
-            r.m, r.n, r.lda = m, n, _ld(A)
+            r.m, r.n, r.lda, r.layout = m, n, lda, lay
             r.A = A.data_ptr()
             r.v = int(pr["v"])
             r.prec = int(pr.get("prec", PREC_FP32))
@@ -385,12 +414,32 @@ class Handle:
             out.append(Factors(p, q, L[:, :k], U[:k], k, r.info.as_dict()))
         return out
 
+    def set_pivot_trace(self, capacity):
+        """Record the pivots of every GETRF of each following call (up to
+        `capacity` entries); 0 turns recording off."""
+        self._rc(_lib().plu_set_pivot_trace(self._h, int(capacity)), "plu_set_pivot_trace")
+
+    def pivot_trace(self):
+        """(pivot rows, gaps) of every GETRF of the last call, in order, as
+        numpy arrays."""
+        import numpy as np
+        n = ctypes.c_int32()
+        self._rc(_lib().plu_pivot_trace(self._h, None, None, 0, ctypes.byref(n)),
+                 "plu_pivot_trace", ok=(PLU_OK, PLU_ERR_OOM))
+        piv = np.zeros(n.value, np.int32)
+        gaps = np.zeros(n.value, np.float32)
+        self._rc(_lib().plu_pivot_trace(
+            self._h, piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            gaps.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n.value, ctypes.byref(n)),
+            "plu_pivot_trace")
+        return piv, gaps
+
     def residual(self, A, f: Factors):
-        _check_mat(A, "A")
+        lay, lda = _layout_of(A)
         m, n = A.shape
         r = ctypes.c_double()
         L, U = f.L, f.U
-        self._rc(_lib().plu_residual(self._h, m, n, _ptr(A), _ld(A), _ptr(f.p), _ptr(f.q), f.rank,
+        self._rc(_lib().plu_residual(self._h, lay, m, n, _ptr(A), lda, _ptr(f.p), _ptr(f.q), f.rank,
                                      _ptr(L), _ld(L), _ptr(U), _ld(U), ctypes.byref(r)),
                  "plu_residual")
         return r.value
@@ -420,7 +469,7 @@ class Server:
 
     def submit(self, A, mode=0, k=0, p_over=0, v=4, eps=0.0, b=1, l=0, column_exact=True,
                seed=0, out=None):
-        """A: host fp32 m x n (row-major, contiguous rows).  out: optional
+        """A: host fp32 m x n, rows or columns contiguous.  out: optional
         (p, q, L, U) host arrays (int32 m, int32 n, fp32 m x cap, fp32 cap x n);
         allocated (numpy) when omitted.  Returns the ticket."""
         import numpy as np
@@ -433,7 +482,11 @@ class Server:
         r = PluRequest()
         r.mode, r.column_exact = mode, 1 if column_exact else 0
         r.m, r.n = m, n
-        r.lda = A.stride(0) if hasattr(A, "stride") and callable(A.stride) else A.strides[0] // 4
+        if hasattr(A, "stride") and callable(A.stride):
+            strides = (A.stride(0), A.stride(1))
+        else:
+            strides = (A.strides[0] // 4, A.strides[1] // 4)
+        r.layout, r.lda = _a_layout((m, n), strides)
         r.A = self._hptr(A)
         r.k, r.p_over, r.v, r.b, r.l, r.eps = k, p_over, v, b, l, float(eps)
         r.prec, r.Omega, r.seed = PREC_FP32, None, seed

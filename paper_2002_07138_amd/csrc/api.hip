@@ -45,6 +45,11 @@ struct plu_handle_s {
   std::vector<unsigned char> gsig;
   plu::MergeBuffers gbuf;
   hipStream_t gstream = nullptr;   // capture stream (the handle's may be the null stream)
+  // pivot trace of the last call (plu_set_pivot_trace / plu_pivot_trace):
+  // device copies of every GETRF's pivot rows and gaps, in order
+  int32_t* trace_piv = nullptr;
+  float* trace_gaps = nullptr;
+  int64_t trace_cap = 0, trace_n = 0, trace_need = 0;
 };
 
 namespace {
@@ -57,7 +62,9 @@ constexpr int kLowpWgs = 512;     // concurrent bfloat16 pass workgroups: 2 per 
 
 inline int64_t ru4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
-inline bool valid_prec(int prec) {
+inline bool valid_layout(int32_t layout) { return layout == PLU_ROW_MAJOR || layout == PLU_COL_MAJOR; }
+
+bool valid_prec(int prec) {
   const int fmt = prec & PLU_PREC_FORMAT_MASK;
   return fmt >= PLU_PREC_FP32 && fmt <= PLU_PREC_FP8_E4M3 &&
          (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST)) == 0;
@@ -106,6 +113,10 @@ struct Ws {
   // FP8 form: codes and E8M0 scales of A (both layouts) and of the sketch
   uint8_t *a8, *a8s, *a8t, *a8ts, *x8, *x8s;
   int64_t lda8, lda8t, ldx8, x8_rows;
+  // A is stored column-major (lda >= m): it is then the row-major n x m
+  // matrix A^T, so A X is the transposed-direction pass over that storage
+  // and A^T Y the direct one
+  bool acol = false;
 };
 
 int64_t part_need(int64_t m, int64_t n, int64_t l) {
@@ -200,7 +211,7 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32) 
     w.ab = L.take<uint16_t>((size_t)m * w.ldab);
     w.abt = L.take<uint16_t>((size_t)n * w.ldabt);
     w.xt = L.take<uint16_t>((size_t)w.xt_rows * w.ldxt);
-    w.cvt_cap = ((std::max(m, w.ldabt) + 63) / 64) * 8;
+    w.cvt_cap = ((std::max(ru(m, 64), ru(n, 64)) + 63) / 64) * 8;   // either storage order
     w.cvt_part = L.take<double>(w.cvt_cap);
   } else if (prec == PLU_PREC_FP8_E4M3) {
     w.lda8 = ru(n, 128);
@@ -272,6 +283,24 @@ GetrfWork getrf_work(plu_handle h, const Ws& w, int which) {
   g.max_waves = h->cu_count * 8;
   return g;
 }
+
+// Appends the pivot rows and gaps of the GETRF just queued with work g (c
+// steps) to the handle's pivot trace, when tracing is on.
+hipError_t trace_getrf(plu_handle h, const GetrfWork& g, int c) {
+  if (!h->trace_cap || thread_recorder()) return hipSuccess;
+  const int64_t at = h->trace_need;
+  h->trace_need += c;
+  if (at + c > h->trace_cap) return hipSuccess;   // reported by plu_pivot_trace
+  hipError_t e = hipMemcpyAsync(h->trace_piv + at, g.piv_row, c * sizeof(int32_t),
+                                hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->trace_gaps + at, g.gaps, c * sizeof(float), hipMemcpyDeviceToDevice,
+                       h->stream);
+  h->trace_n = at + c;
+  return e;
+}
+
+void trace_reset(plu_handle h) { h->trace_n = h->trace_need = 0; }
 
 QrWork qr_work(const Ws& w, float* q, int64_t ldq) {
   QrWork r;
@@ -392,6 +421,10 @@ hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0,
 hipError_t run_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, const float* A,
                     int64_t lda, const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo,
                     double* normA2_dev, double* colsq, int* colsq_blocks) {
+  if (w.acol) {   // the storage is A^T, row-major
+    trans ^= 1;
+    std::swap(m, n);
+  }
   const int64_t P = trans ? n : m, R = trans ? m : n;
   GemmArgs g0;
   g0.A = A; g0.lda = lda; g0.X = X; g0.ldx = ldx;
@@ -420,9 +453,13 @@ hipError_t convert_a_bf16(plu_handle h, const Ws& w, int64_t m, int64_t n, const
                           int64_t lda, double* normA2_dev) {
   hipError_t e;
   int64_t np = 0;
-  if ((e = launch_cvt_bf16(A, lda, m, n, w.ab, w.ldab, w.abt, w.ldabt, n, w.cvt_part, &np,
-                           h->stream)) != hipSuccess)
-    return e;
+  if (w.acol)   // the storage is A^T: its row-major copy is the transposed one
+    e = launch_cvt_bf16(A, lda, n, m, w.abt, w.ldabt, w.ab, w.ldab, m, w.cvt_part, &np,
+                        h->stream);
+  else
+    e = launch_cvt_bf16(A, lda, m, n, w.ab, w.ldab, w.abt, w.ldabt, n, w.cvt_part, &np,
+                        h->stream);
+  if (e != hipSuccess) return e;
   if (np > w.cvt_cap) return hipErrorInvalidValue;
   if (normA2_dev) return launch_sum_doubles(w.cvt_part, np, normA2_dev, h->stream);
   return hipSuccess;
@@ -460,13 +497,17 @@ hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_
 hipError_t convert_a_fp8(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A,
                          int64_t lda, double* normA2_dev) {
   hipError_t e;
-  if ((e = launch_cvt_fp8(A, lda, m, n, w.a8, w.a8s, w.lda8, w.a8t, w.a8ts, w.lda8t, n,
-                          h->stream)) != hipSuccess)
-    return e;
+  if (w.acol)   // the storage is A^T: its row-major copy is the transposed one
+    e = launch_cvt_fp8(A, lda, n, m, w.a8t, w.a8ts, w.lda8t, w.a8, w.a8s, w.lda8, m, h->stream);
+  else
+    e = launch_cvt_fp8(A, lda, m, n, w.a8, w.a8s, w.lda8, w.a8t, w.a8ts, w.lda8t, n, h->stream);
+  if (e != hipSuccess) return e;
   if (normA2_dev) {
     const int nb = 1024;
     if (nb > w.sumsq_cap) return hipErrorInvalidValue;
-    if ((e = launch_sumsq_matrix(A, lda, m, n, w.sumsq_part, nb, h->stream)) != hipSuccess)
+    if ((e = w.acol ? launch_sumsq_matrix(A, lda, n, m, w.sumsq_part, nb, h->stream)
+                    : launch_sumsq_matrix(A, lda, m, n, w.sumsq_part, nb, h->stream)) !=
+        hipSuccess)
       return e;
     return launch_sum_doubles(w.sumsq_part, nb, normA2_dev, h->stream);
   }
@@ -551,6 +592,7 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
     if (v > 2) {
       if ((e = getrf_run(w.zn, lp, n, l, gw, nullptr, nullptr, 0, 0, h->stream)) != hipSuccess)
         return e;
+      if ((e = trace_getrf(h, gw, l)) != hipSuccess) return e;
       V = w.zn;
     } else {
       if ((e = thin_qr_run(w.zn, lp, n, l, gw, qw, h->stream)) != hipSuccess) return e;
@@ -562,7 +604,8 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
   for (int i = 1; i <= P; ++i) {
     if ((e = pass(0, V, w.ym)) != hipSuccess) return e;
     ++np;
-    if ((e = getrf_run(w.ym, lp, m, l, gw, nullptr, nullptr, 0, 0, h->stream)) != hipSuccess)
+    if ((e = getrf_run(w.ym, lp, m, l, gw, nullptr, nullptr, 0, 0, h->stream)) != hipSuccess ||
+        (e = trace_getrf(h, gw, l)) != hipSuccess)
       return e;
     if ((e = pass(1, w.ym, w.zn)) != hipSuccess) return e;
     ++np;
@@ -572,6 +615,7 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
     } else {
       if ((e = getrf_run(w.zn, lp, n, l, gw, nullptr, nullptr, 0, 0, h->stream)) != hipSuccess)
         return e;
+      if ((e = trace_getrf(h, gw, l)) != hipSuccess) return e;
       V = w.zn;
     }
   }
@@ -589,6 +633,7 @@ hipError_t assemble(plu_handle h, const Ws& w, int64_t m, int64_t n, int k, cons
   const GetrfWork g2 = getrf_work(h, w, 2);
   // [L1, U1, P] = lu(Y): ym <- P^T L1, ut1 <- U1^T
   if ((e = getrf_run(w.ym, lp, m, k, g1, p, w.ut1, lp, 1, h->stream)) != hipSuccess) return e;
+  if ((e = trace_getrf(h, g1, k)) != hipSuccess) return e;
   // B^T = V(:, :k) U1^T  (n x k)
   {
     GemmArgs g;
@@ -599,6 +644,7 @@ hipError_t assemble(plu_handle h, const Ws& w, int64_t m, int64_t n, int k, cons
   }
   // [L2, U2, Q] = lu(B^T): bt <- Q^T L2, ut2 <- U2^T
   if ((e = getrf_run(w.bt, lp, n, k, g2, q, w.ut2, lp, 1, h->stream)) != hipSuccess) return e;
+  if ((e = trace_getrf(h, g2, k)) != hipSuccess) return e;
   // L = L1 U2^T with L1 = (P^T L1)[p]
   {
     GemmArgs g;
@@ -703,7 +749,8 @@ int check_request(const plu_request& r, int64_t* l_out) {
   if (r.mode != 0 && r.mode != 1) return -1;
   if (r.m <= 0) return -3;
   if (r.n <= 0) return -4;
-  if (r.lda < r.n) return -5;
+  if (!valid_layout(r.layout)) return -22;
+  if (r.lda < (r.layout == PLU_COL_MAJOR ? r.m : r.n)) return -5;
   if (!r.A || (reinterpret_cast<uintptr_t>(r.A) & 3u)) return -6;
   const int64_t mn = std::min(r.m, r.n);
   int64_t l = 0;
@@ -751,6 +798,7 @@ hipError_t batch_phase_a(BatchProblem& b) {
   hipError_t e;
   int st = ensure_ws(hs, r.m, r.n, b.l, &b.w);
   if (st) return hipErrorOutOfMemory;
+  b.w.acol = r.layout == PLU_COL_MAJOR;
   if ((e = range_basis(hs, b.w, r.m, r.n, r.A, r.lda, (int)b.l, r.v, r.Omega, r.seed, &b.V,
                        &b.np)) != hipSuccess)
     return e;
@@ -1065,7 +1113,10 @@ void server_loop(plu_server S) {
       plu_request& d = j->dev;
       d = r;
       d.A = reinterpret_cast<float*>(take((size_t)r.m * r.n * 4));
-      d.lda = r.n;
+      // the device copy keeps the request's storage order, packed
+      const bool col = r.layout == PLU_COL_MAJOR;
+      const int64_t inner = col ? r.m : r.n, outer = col ? r.n : r.m;
+      d.lda = inner;
       d.p = reinterpret_cast<int32_t*>(take((size_t)r.m * 4));
       d.q = reinterpret_cast<int32_t*>(take((size_t)r.n * 4));
       d.L = reinterpret_cast<float*>(take((size_t)r.m * j->cap * 4));
@@ -1092,12 +1143,13 @@ void server_loop(plu_server S) {
       }
       // A goes up on its own stream, overlapping the steps of other problems
       hipError_t eu;
-      if (r.lda == r.n)
+      if (r.lda == inner)
         eu = hipMemcpyAsync(const_cast<float*>(d.A), r.A, (size_t)r.m * r.n * 4,
                             hipMemcpyHostToDevice, S->ustream);
       else
-        eu = hipMemcpy2DAsync(const_cast<float*>(d.A), (size_t)r.n * 4, r.A, (size_t)r.lda * 4,
-                              (size_t)r.n * 4, (size_t)r.m, hipMemcpyHostToDevice, S->ustream);
+        eu = hipMemcpy2DAsync(const_cast<float*>(d.A), (size_t)inner * 4, r.A,
+                              (size_t)r.lda * 4, (size_t)inner * 4, (size_t)outer,
+                              hipMemcpyHostToDevice, S->ustream);
       j->up = take_event(S);
       j->uploaded = false;
       if (eu == hipSuccess && j->up) eu = hipEventRecord(j->up, S->ustream);
@@ -1117,6 +1169,7 @@ void server_loop(plu_server S) {
       bp.hs.graph = nullptr;
       bp.hs.gexec = nullptr;
       bp.hs.gstream = nullptr;
+      bp.hs.trace_cap = 0;
       bp.hs.mbuf = MergeBuffers();
       bp.hs.gbuf = MergeBuffers();
       int64_t l = 0;
@@ -1386,6 +1439,8 @@ int plu_destroy(plu_handle h) {
   h->mbuf.destroy();
   if (h->arena) (void)hipFree(h->arena);
   if (h->batch_arena) (void)hipFree(h->batch_arena);
+  if (h->trace_piv) (void)hipFree(h->trace_piv);
+  if (h->trace_gaps) (void)hipFree(h->trace_gaps);
   delete h;
   return PLU_OK;
 }
@@ -1505,7 +1560,9 @@ int plu_getrf(plu_handle h, int64_t M, int32_t c, float* F, int64_t ldf, int32_t
   int st = ensure_ws(h, M, c + 1, c, &w);
   if (st) return st;
   const GetrfWork g = getrf_work(h, w, 1);
+  trace_reset(h);
   PLU_TRY_HIP(getrf_run(F, ldf, M, c, g, perm, Ufac, ldu, 0, h->stream));
+  PLU_TRY_HIP(trace_getrf(h, g, c));
   if (info) {
     PLU_TRY_HIP(hipStreamSynchronize(h->stream));
     int32_t s[2];
@@ -1546,23 +1603,26 @@ int plu_thin_qr(plu_handle h, int64_t M, int32_t c, float* X, int64_t ldx) {
   return PLU_OK;
 }
 
-int plu_range_basis(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda, int32_t l,
-                    int32_t v, int32_t prec, const float* Omega, uint64_t seed, float* V,
-                    int64_t ldv) {
+int plu_range_basis(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                    int64_t lda, int32_t l, int32_t v, int32_t prec, const float* Omega,
+                    uint64_t seed, float* V, int64_t ldv) {
   if (!h) return -1;
-  if (m <= 0) return -2;
-  if (n <= 0) return -3;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -4;
-  if (lda < n) return -5;
-  if (l <= 0 || l >= std::min(m, n)) return -6;
-  if (v < 2) return -7;
-  if (!valid_prec(prec)) return -8;
-  if (!V) return -11;
-  if (ldv < l) return -12;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
+  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (l <= 0 || l >= std::min(m, n)) return -7;
+  if (v < 2) return -8;
+  if (!valid_prec(prec)) return -9;
+  if (!V) return -12;
+  if (ldv < l) return -13;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
+  w.acol = layout == PLU_COL_MAJOR;
+  trace_reset(h);
   float* Vw = nullptr;
   int np = 0;
   PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, Omega, seed, &Vw, &np, prec));
@@ -1571,31 +1631,34 @@ int plu_range_basis(plu_handle h, int64_t m, int64_t n, const float* A, int64_t 
   return PLU_OK;
 }
 
-int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda, int32_t k,
-                   int32_t p_over, int32_t v, int32_t prec, const float* Omega, uint64_t seed,
-                   int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
-                   plu_info* info) {
+int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                   int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
+                   const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                   int64_t ldl, float* U, int64_t ldu, plu_info* info) {
   if (!h) return -1;
-  if (m <= 0) return -2;
-  if (n <= 0) return -3;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -4;
-  if (lda < n) return -5;
-  if (k < 1) return -6;
-  if (p_over < 0) return -7;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
+  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (k < 1) return -7;
+  if (p_over < 0) return -8;
   const int64_t l = (int64_t)k + p_over;
-  if (l >= std::min(m, n)) return -7;
-  if (v < 2) return -8;
-  if (!valid_prec(prec)) return -9;
-  if (!p) return -12;
-  if (!q) return -13;
-  if (!L) return -14;
-  if (ldl < k) return -15;
-  if (!U) return -16;
-  if (ldu < n) return -17;
+  if (l >= std::min(m, n)) return -8;
+  if (v < 2) return -9;
+  if (!valid_prec(prec)) return -10;
+  if (!p) return -13;
+  if (!q) return -14;
+  if (!L) return -15;
+  if (ldl < k) return -16;
+  if (!U) return -17;
+  if (ldu < n) return -18;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
+  w.acol = layout == PLU_COL_MAJOR;
+  trace_reset(h);
   float* V = nullptr;
   int np = 0;
   PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, (int)l, v, Omega, seed, &V, &np, prec));
@@ -1606,33 +1669,36 @@ int plu_fixed_rank(plu_handle h, int64_t m, int64_t n, const float* A, int64_t l
   return finish_info(h, w, PLU_OK, k, np, (int)l, false, info);
 }
 
-int plu_fixed_precision(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
-                        double eps, int32_t b, int32_t l, int32_t v, int32_t column_exact,
-                        int32_t prec, const float* Omega, uint64_t seed, int32_t* p, int32_t* q,
-                        float* L, int64_t ldl, float* U, int64_t ldu, int32_t* rank_out,
-                        plu_info* info) {
+int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                        int64_t lda, double eps, int32_t b, int32_t l, int32_t v,
+                        int32_t column_exact, int32_t prec, const float* Omega, uint64_t seed,
+                        int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                        int32_t* rank_out, plu_info* info) {
   if (!h) return -1;
-  if (m <= 0) return -2;
-  if (n <= 0) return -3;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -4;
-  if (lda < n) return -5;
-  if (!(eps > 0.0)) return -6;
-  if (b < 1) return -7;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
+  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (!(eps > 0.0)) return -7;
+  if (b < 1) return -8;
   const int64_t mn = std::min(m, n);
   if (l == 0) l = (int32_t)std::min<int64_t>(50LL * b, b * ((mn - 1) / b));
-  if (l <= 0 || l % b != 0 || l >= mn) return -8;
-  if (v < 2) return -9;
-  if (!valid_prec(prec)) return -11;
-  if (!p) return -14;
-  if (!q) return -15;
-  if (!L) return -16;
-  if (ldl < l) return -17;
-  if (!U) return -18;
-  if (ldu < n) return -19;
+  if (l <= 0 || l % b != 0 || l >= mn) return -9;
+  if (v < 2) return -10;
+  if (!valid_prec(prec)) return -12;
+  if (!p) return -15;
+  if (!q) return -16;
+  if (!L) return -17;
+  if (ldl < l) return -18;
+  if (!U) return -19;
+  if (ldu < n) return -20;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
+  w.acol = layout == PLU_COL_MAJOR;
+  trace_reset(h);
   float* V = nullptr;
   int np = 0;
   PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, Omega, seed, &V, &np, prec));
@@ -1710,22 +1776,24 @@ int plu_rank_rule(plu_handle h, int64_t m, int32_t l, const float* G, int64_t ld
   return ks[1] ? PLU_OK : PLU_TOL_NOT_REACHED;
 }
 
-int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda,
-                 const int32_t* p, const int32_t* q, int32_t k, const float* L, int64_t ldl,
-                 const float* U, int64_t ldu, double* rel_resid) {
+int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                 int64_t lda, const int32_t* p, const int32_t* q, int32_t k, const float* L,
+                 int64_t ldl, const float* U, int64_t ldu, double* rel_resid) {
   if (!h) return -1;
-  if (m <= 0) return -2;
-  if (n <= 0) return -3;
-  if (!A) return -4;
-  if (lda < n) return -5;
-  if (!p) return -6;
-  if (!q) return -7;
-  if (k < 1) return -8;
-  if (!L) return -9;
-  if (ldl < k) return -10;
-  if (!U) return -11;
-  if (ldu < n) return -12;
-  if (!rel_resid) return -13;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A) return -5;
+  const bool col = layout == PLU_COL_MAJOR;
+  if (lda < (col ? m : n)) return -6;
+  if (!p) return -7;
+  if (!q) return -8;
+  if (k < 1) return -9;
+  if (!L) return -10;
+  if (ldl < k) return -11;
+  if (!U) return -12;
+  if (ldu < n) return -13;
+  if (!rel_resid) return -14;
   PLU_TRY_HIP(hipSetDevice(h->device));
   char* extra = nullptr;
   const GemmPlan pl = plan_gemm(m, k, n, 1, 1);
@@ -1746,10 +1814,16 @@ int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda
     GemmArgs g;
     g.A = L; g.lda = ldl; g.X = U; g.ldx = ldu;
     g.P = m; g.R = k; g.C = n;
-    g.Aref = A; g.ldaref = lda; g.pidx = p; g.qidx = q; g.resid_part = rpart;
+    g.Aref = A; g.pidx = p; g.qidx = q; g.resid_part = rpart;
+    g.ldaref = col ? 1 : lda;     // element (i, j) of A at i * ldaref + j * aref_cs
+    g.aref_cs = col ? lda : 1;
     if (launch_gemm(0, EPI_RESID, 0, g, pl, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
     if (launch_sum_doubles(rpart, nparts, sums + 0, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
-    if (launch_sumsq_matrix(A, lda, m, n, spart, sq_blocks, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
+    if ((col ? launch_sumsq_matrix(A, lda, n, m, spart, sq_blocks, h->stream)
+             : launch_sumsq_matrix(A, lda, m, n, spart, sq_blocks, h->stream)) != hipSuccess) {
+      rc = PLU_ERR_HIP;
+      break;
+    }
     if (launch_sum_doubles(spart, sq_blocks, sums + 1, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
     double hs[2];
     if (hipStreamSynchronize(h->stream) != hipSuccess ||
@@ -1762,6 +1836,48 @@ int plu_residual(plu_handle h, int64_t m, int64_t n, const float* A, int64_t lda
   hipStreamSynchronize(h->stream);
   hipFree(extra);
   return rc;
+}
+
+int plu_set_pivot_trace(plu_handle h, int64_t capacity) {
+  if (!h) return -1;
+  if (capacity < 0) return -2;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (h->trace_piv) (void)hipFree(h->trace_piv);
+  if (h->trace_gaps) (void)hipFree(h->trace_gaps);
+  h->trace_piv = nullptr;
+  h->trace_gaps = nullptr;
+  h->trace_cap = h->trace_n = h->trace_need = 0;
+  if (capacity == 0) return PLU_OK;
+  if (hipMalloc(reinterpret_cast<void**>(&h->trace_piv), capacity * sizeof(int32_t)) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&h->trace_gaps), capacity * sizeof(float)) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    if (h->trace_piv) (void)hipFree(h->trace_piv);
+    h->trace_piv = nullptr;
+    h->trace_gaps = nullptr;
+    return PLU_ERR_OOM;
+  }
+  h->trace_cap = capacity;
+  return PLU_OK;
+}
+
+int plu_pivot_trace(plu_handle h, int32_t* ipiv_out, float* gaps_out, int32_t cap,
+                    int32_t* n_out) {
+  if (!h) return -1;
+  if (cap < 0) return -4;
+  if (!n_out) return -5;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+  *n_out = (int32_t)h->trace_need;
+  const int64_t c = std::min<int64_t>(cap, h->trace_n);
+  if (c > 0 && ipiv_out)
+    PLU_TRY_HIP(hipMemcpy(ipiv_out, h->trace_piv, c * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (c > 0 && gaps_out)
+    PLU_TRY_HIP(hipMemcpy(gaps_out, h->trace_gaps, c * sizeof(float), hipMemcpyDeviceToHost));
+  if (h->trace_need > h->trace_n) return PLU_ERR_OOM;   // the device trace was too small
+  return PLU_OK;
 }
 
 int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
@@ -1834,6 +1950,7 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       b.hs.gexec = nullptr;
       b.hs.gstream = nullptr;
       b.hs.graph = nullptr;
+      b.hs.trace_cap = 0;
       b.hs.mbuf = MergeBuffers();
       b.hs.gbuf = MergeBuffers();
       all.push_back(&b);

@@ -254,7 +254,7 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
         } else if (epi == EPI_SUB) {
           g.out[p * g.ldo + c] -= v;
         } else {
-          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + g.qidx[c]] - (double)v;
+          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + (int64_t)g.qidx[c] * g.aref_cs] - (double)v;
           rs = fma(d, d, rs);
         }
       }
@@ -438,7 +438,7 @@ __device__ __forceinline__ void pass_direct_body(const GemmArgs& g, const Grid& 
         } else if (epi == EPI_SUB) {
           g.out[p * g.ldo + c] -= v;
         } else {
-          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + g.qidx[c]] - (double)v;
+          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + (int64_t)g.qidx[c] * g.aref_cs] - (double)v;
           rs = fma(d, d, rs);
         }
       }

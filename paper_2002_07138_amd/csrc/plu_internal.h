@@ -35,7 +35,7 @@ struct GemmArgs {
   const int32_t* rowmask = nullptr;   // EPI_SUB: rows with rowmask[p] >= 0 are left alone
   double* sumsq_part = nullptr;       // fused ||A||_F^2: one partial per workgroup (column block 0)
   // EPI_RESID
-  const float* Aref = nullptr; int64_t ldaref = 0;
+  const float* Aref = nullptr; int64_t ldaref = 0, aref_cs = 1;   // element (i, j) at i*ldaref + j*aref_cs
   const int32_t* pidx = nullptr; const int32_t* qidx = nullptr;
   double* resid_part = nullptr;
   // set by launch_gemm: rows of A / X start 16-byte aligned (vector loads allowed)
