@@ -187,6 +187,7 @@ template <int NB, int RPT, int NWAVE, int S>
 __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
   if (a.run_if && *a.run_if == 0) return;   // uniform over the grid: every workgroup leaves
   constexpr int MAXG = 64;                 // message slots (workgroups) at most
+  constexpr int kFirstPollSleep = 24;      // s_sleep units of 64 clocks: about 0.7 us
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int G = gr.gx;
@@ -296,7 +297,18 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
     float bsec = -1.f;
 #pragma unroll
     for (int v = 0; v < NWAVE; ++v) bsec = fmaxf(bsec, (v == bw) ? wcs[v] : key_abs(wck[v]));
-    // ---- (2) publish the workgroup's candidate
+    // ---- (2) publish the workgroup's candidate: a message to every
+    // workgroup, or, when the grid is one workgroup, straight into the LDS
+    // copy the polling would fill
+    const bool local = (G == 1);
+    auto put_h = [&](uint32_t v) __attribute__((always_inline)) {
+      if (local) hdr[0][lane] = v;
+      else st_word(slot(J, wg) + lane, v, tag);
+    };
+    auto put_d = [&](uint32_t v) __attribute__((always_inline)) {
+      if (local) dat[0][lane] = __uint_as_float(v);
+      else st_word(slot(J, wg) + MSGH + lane, v, tag);
+    };
     if (bk != 0ull && wv == bw) {
       if (lane == wl) {
 #pragma unroll
@@ -312,25 +324,27 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
           *reinterpret_cast<f32x4*>(&rowbuf[wv][jj]) = v4;
         }
       }
-      unsigned long long* sl = slot(J, wg);
       const float mine = rowbuf[wv][lane < NB ? lane : 0];
-      if (lane > s && lane < NB) st_word(sl + MSGH + lane, __float_as_uint(mine), tag);
+      if (lane > s && lane < NB) put_d(__float_as_uint(mine));
       if (lane < MSGH) {
         uint32_t pl = 0;
         if (lane == 0) pl = __float_as_uint(rowbuf[wv][s]);
         if (lane == 1) pl = (uint32_t)(wave_base + wq * 64 + wl);
         if (lane == 2) pl = 0xFFFFFFFFu - (uint32_t)bk;
         if (lane == 3) pl = __float_as_uint(bsec);
-        st_word(sl + lane, pl, tag);
+        put_h(pl);
       }
-    } else if (bk == 0ull && wv == 0) {
-      unsigned long long* sl = slot(J, wg);          // no candidate in this workgroup
-      if (lane < MSGH) st_word(sl + lane, lane == 1 ? 0xFFFFFFFFu : 0u, tag);
-      if (lane > s && lane < NB) st_word(sl + MSGH + lane, 0u, tag);
+    } else if (bk == 0ull && wv == 0) {              // no candidate in this workgroup
+      if (lane < MSGH) put_h(lane == 1 ? 0xFFFFFFFFu : 0u);
+      if (lane > s && lane < NB) put_d(0u);
     }
     // ---- (3) poll the messages of workgroups wv, wv+NWAVE, ... into LDS;
-    // all of a wave's slots are in flight together
-    {
+    // all of a wave's slots are in flight together.  A poll costs one
+    // round trip to memory (about 1 us across XCDs); the first one waits
+    // about 0.7 us for the other workgroups' messages to land, so most
+    // steps need one poll instead of two.
+    if (!local) {
+      __builtin_amdgcn_s_sleep(kFirstPollSleep);
       constexpr int TS = MAXG / NWAVE;
       uint32_t pend_h = 0, pend_d = 0;
 #pragma unroll
@@ -441,7 +455,8 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
         if (jj > s) {
 #pragma unroll
           for (int q = 0; q < RPT; ++q)
-            if (act[q]) x[q][jj] = fmaf(-lm[q], u4[e], x[q][jj]);
+            // rows no longer active have lm = 0; their window is not read again
+            x[q][jj] = fmaf(-lm[q], u4[e], x[q][jj]);
         }
       }
     }
