@@ -92,48 +92,12 @@ __device__ __forceinline__ unsigned long long cand_key(float a, int pos) {
          (unsigned long long)(0xFFFFFFFFu - (uint32_t)pos);
 }
 
-struct Cand {
-  unsigned long long key;
-  int row;        // -1 if none
-  float sv;       // signed value
-  int src;        // publishing wave (global winner search) or q (local search)
-  float sec;      // runner-up |value| among merged candidates, -1 if none
-};
-
 __device__ __forceinline__ float key_abs(unsigned long long key) {
   return key == 0ull ? -1.f : __uint_as_float((uint32_t)(key >> 32));
 }
 
-__device__ __forceinline__ void merge(Cand& x, const Cand& y) {
-  if (y.key > x.key) {
-    const float la = key_abs(x.key);
-    float s = y.sec > la ? y.sec : la;
-    s = s > x.sec ? s : x.sec;
-    x.key = y.key; x.row = y.row; x.sv = y.sv; x.src = y.src; x.sec = s;
-  } else {
-    const float la = key_abs(y.key);
-    float s = x.sec > la ? x.sec : la;
-    s = s > y.sec ? s : y.sec;
-    x.sec = s;
-  }
-}
-
-__device__ __forceinline__ Cand wave_reduce(Cand c) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    Cand y;
-    y.key = __shfl_xor(c.key, o, 64);
-    y.row = __shfl_xor(c.row, o, 64);
-    y.sv = __shfl_xor(c.sv, o, 64);
-    y.src = __shfl_xor(c.src, o, 64);
-    y.sec = __shfl_xor(c.sec, o, 64);
-    merge(c, y);
-  }
-  return c;
-}
-
-// Wave-wide maxima: rotations inside each row of 16 lanes (DPP), then the
-// two cross-row exchanges.
+// Wave-wide reductions: rotations inside each row of 16 lanes (DPP), then
+// the two cross-row exchanges.
 template <int R>
 __device__ __forceinline__ uint32_t dpp_ror(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + R, 0xF, 0xF, false);
@@ -149,24 +113,44 @@ __device__ __forceinline__ unsigned long long dpp_ror64(unsigned long long v) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-  v = umax64(v, dpp_ror64<1>(v));
-  v = umax64(v, dpp_ror64<2>(v));
-  v = umax64(v, dpp_ror64<4>(v));
-  v = umax64(v, dpp_ror64<8>(v));
-  v = umax64(v, __shfl_xor(v, 16, 64));
-  v = umax64(v, __shfl_xor(v, 32, 64));
-  return v;
+// The cross-row steps use gfx950's row swaps (VALU, no LDS round trip).  A
+// value swapped with itself comes back as the pair (lower row's, upper row's)
+// in every lane: rows 16 apart for the 16-lane swap, halves 32 apart for the
+// 32-lane one.  Both entries of the pair go into the reduction, so the result
+// covers the lane and its partner whatever the lane's side.
+//
+// Wave-wide top two in one pass: k becomes the largest key, s the largest
+// |value| among all other candidates.  Each lane enters its key and its own
+// runner-up |value| (-1 if none); a key that loses a comparison passes its
+// |value| on to s.
+__device__ __forceinline__ void top2_merge(unsigned long long& k, float& s, unsigned long long k2,
+                                           float s2) {
+  const unsigned long long lo = k < k2 ? k : k2;
+  k = k < k2 ? k2 : k;
+  s = fmaxf(fmaxf(s, s2), key_abs(lo));
 }
 
-__device__ __forceinline__ float wave_max_f32(float v) {
-  v = fmaxf(v, __uint_as_float(dpp_ror<1>(__float_as_uint(v))));
-  v = fmaxf(v, __uint_as_float(dpp_ror<2>(__float_as_uint(v))));
-  v = fmaxf(v, __uint_as_float(dpp_ror<4>(__float_as_uint(v))));
-  v = fmaxf(v, __uint_as_float(dpp_ror<8>(__float_as_uint(v))));
-  v = fmaxf(v, __shfl_xor(v, 16, 64));
-  v = fmaxf(v, __shfl_xor(v, 32, 64));
-  return v;
+template <int W>
+__device__ __forceinline__ void xrow_top2(unsigned long long& k, float& s) {
+  const uint32_t lo = (uint32_t)k, hi = (uint32_t)(k >> 32), su = __float_as_uint(s);
+  const auto a = W == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                         : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = W == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                         : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const auto c = W == 16 ? __builtin_amdgcn_permlane16_swap(su, su, false, false)
+                         : __builtin_amdgcn_permlane32_swap(su, su, false, false);
+  k = ((unsigned long long)b[0] << 32) | a[0];
+  s = __uint_as_float(c[0]);
+  top2_merge(k, s, ((unsigned long long)b[1] << 32) | a[1], __uint_as_float(c[1]));
+}
+
+__device__ __forceinline__ void wave_top2(unsigned long long& k, float& s) {
+  top2_merge(k, s, dpp_ror64<1>(k), __uint_as_float(dpp_ror<1>(__float_as_uint(s))));
+  top2_merge(k, s, dpp_ror64<2>(k), __uint_as_float(dpp_ror<2>(__float_as_uint(s))));
+  top2_merge(k, s, dpp_ror64<4>(k), __uint_as_float(dpp_ror<4>(__float_as_uint(s))));
+  top2_merge(k, s, dpp_ror64<8>(k), __uint_as_float(dpp_ror<8>(__float_as_uint(s))));
+  xrow_top2<16>(k, s);
+  xrow_top2<32>(k, s);
 }
 
 // One cooperative grid factors a panel of up to NB columns.  A workgroup of
@@ -177,8 +161,9 @@ __device__ __forceinline__ float wave_max_f32(float v) {
 // enough for the instruction cache.  Multipliers and the pivot row's U
 // entries are stored to F as soon as they are final.
 //
-// Pivot step: (1) each wave finds its best candidate (DPP max of the 64-bit
-// key |value|, position), the workgroup combines them in LDS; (2) the owner
+// Pivot step: (1) each wave finds its best candidate and runner-up (one
+// top-two reduction of the 64-bit key |value|, position), the workgroup
+// combines them in LDS; (2) the owner
 // of the workgroup's candidate publishes one message: header (value, row,
 // position, runner-up) and the candidate's window entries to the right of
 // the pivot column; (3) the waves of every workgroup share the polling of all
@@ -274,10 +259,11 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
         }
       }
     }
-    const unsigned long long wk = wave_max_u64(mykey);
+    unsigned long long wk = mykey;
+    float wsec = mysec;
+    wave_top2(wk, wsec);
     const unsigned long long bal = __ballot(wk != 0ull && mykey == wk);
     const int wl = bal ? (int)__ffsll((long long)bal) - 1 : 0;
-    const float wsec = wave_max_f32((lane == wl) ? mysec : key_abs(mykey));
     const int wq = __builtin_amdgcn_readlane(myq, wl);
     if (lane == 0) {
       wck[wv] = wk;
@@ -407,10 +393,11 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
         gsec = __uint_as_float(hdr[lane][3]);
       }
     }
-    const unsigned long long best = wave_max_u64(gkey);
+    unsigned long long best = gkey;
+    float runner = gsec;
+    wave_top2(best, runner);
     const unsigned long long gb = __ballot(best != 0ull && gkey == best);
     const int gs = gb ? (int)__ffsll((long long)gb) - 1 : 0;
-    const float runner = wave_max_f32((lane == gs) ? gsec : gabs);
     const float piv = __uint_as_float(hdr[gs][0]);
     const int prow = (best != 0ull) ? (int)hdr[gs][1] : -1;
     const float aw = key_abs(best);
