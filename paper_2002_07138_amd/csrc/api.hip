@@ -368,13 +368,9 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
     GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots);
     if (!fits(p)) continue;
     bool dup = false;
-    for (auto& c : cands) dup |= (c.nsplit == p.nsplit && c.variant == 0);
+    for (auto& c : cands) dup |= c.nsplit == p.nsplit;
     if (dup) continue;
     cands.push_back(p);
-    if (trans == 0) {   // direction N also tries A straight into registers
-      p.variant = 1;
-      cands.push_back(p);
-    }
   }
   if (cands.empty()) return plan_gemm(P, R, C, 1, 1);
   hipEvent_t e0, e1;

@@ -271,195 +271,6 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
   }
 }
 
-// Mode N with A read straight into the MFMA operand registers: the 32 rows
-// of A a wave multiplies are its own, so only the sketch stage goes through
-// LDS (double-buffered, one barrier per stage) and A is prefetched one stage
-// ahead in registers.  The products are issued in the same order as in
-// pass_body, so both variants give the same bits.
-template <int NT, int EPI>
-__device__ __forceinline__ void pass_direct_body(const GemmArgs& g, const Grid& gr) {
-  if (g.run_if && *g.run_if == 0) return;
-  constexpr int RT = GEMM_BP / 64;
-  constexpr int BP = 64 * RT;
-  constexpr int BK = GEMM_BK;
-  constexpr int XC = NT * 16;
-  constexpr int XST = XC + 4;
-  constexpr int XV = BK * NT * 4;            // float4 slots of a sketch stage
-  constexpr int XIT = (XV + 255) / 256;
-  static_assert(BK == 32 && RT == 2, "direct variant: 32-deep stages, two row tiles per wave");
-  __shared__ __attribute__((aligned(16))) float Xs[2][BK * XST];
-  __shared__ double red[4];
-  constexpr bool DYN = false;
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, pr = lane & 15, g4 = lane >> 4;
-  const int nwg = gr.gx;
-  const int xcd = gr.bx & 7, idx = gr.bx >> 3;
-  const int per = nwg >> 3, rem = nwg & 7;
-  const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-  const int npb = nwg / g.nsplit;
-  const int split = lid / npb;
-  const int64_t p0 = (int64_t)(lid % npb) * BP;
-  const int ntr = NT;
-  const int64_t c0 = (int64_t)gr.by * XC;
-  const int64_t rb = (int64_t)split * g.rsplit;
-  const int64_t re = (rb + g.rsplit < g.R) ? rb + g.rsplit : g.R;
-  const bool do_ss = (g.sumsq_part != nullptr) && gr.by == 0;
-  constexpr int epi = EPI;
-  double ss = 0.0;
-  (void)ntr;
-
-  const float* arow[RT];
-  bool aok[RT];
-#pragma unroll
-  for (int i = 0; i < RT; ++i) {
-    const int64_t p = p0 + wave * 16 * RT + i * 16 + pr;
-    aok[i] = p < g.P;
-    const int64_t srow = aok[i] ? (g.arow ? (int64_t)g.arow[p] : p) : 0;
-    arow[i] = g.A + srow * g.lda;
-  }
-  f32x4 ra0[RT][2], ra1[RT][2];
-  f32x4 rx[XIT];
-  f32x4 acc[RT][NT];
-#pragma unroll
-  for (int i = 0; i < RT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  auto load_a = [&](int64_t r, f32x4 (&d)[RT][2]) __attribute__((always_inline)) {
-#pragma unroll
-    for (int i = 0; i < RT; ++i)
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (aok[i]) v = load4(arow[i], r + kk * 16 + g4 * 4, re, g.avec);
-        d[i][kk] = v;
-      }
-  };
-  auto load_x = [&](int64_t r) __attribute__((always_inline)) {
-#pragma unroll
-    for (int it = 0; it < XIT; ++it) {
-      const int q = it * 256 + tid;
-      f32x4 v = {0.f, 0.f, 0.f, 0.f};
-      if (q < XV) {
-        const int row = q / (NT * 4);
-        const int col = (q % (NT * 4)) * 4;
-        const int64_t rr = r + row;
-        if (rr < re) v = load4(g.X + rr * g.ldx, c0 + col, g.C, g.xvec);
-      }
-      rx[it] = v;
-    }
-  };
-  auto store_x = [&](int buf) __attribute__((always_inline)) {
-#pragma unroll
-    for (int it = 0; it < XIT; ++it) {
-      const int q = it * 256 + tid;
-      if (q < XV) {
-        const int row = q / (NT * 4);
-        const int col = (q % (NT * 4)) * 4;
-        *reinterpret_cast<f32x4*>(&Xs[buf][row * XST + col]) = rx[it];
-      }
-    }
-  };
-  auto compute = [&](int buf, const f32x4 (&a)[RT][2]) __attribute__((always_inline)) {
-    if (do_ss) {
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const double d = a[i][kk][e];
-            ss = fma(d, d, ss);
-          }
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK / 16; ++kk) {
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        float b[NT];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) b[j] = Xs[buf][(kk * 16 + g4 * 4 + s4) * XST + j * 16 + pr];
-#pragma unroll
-        for (int i = 0; i < RT; ++i)
-#pragma unroll
-          for (int j = 0; j < NT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][kk][s4], b[j], acc[i][j], 0, 0, 0);
-      }
-    }
-  };
-  auto stage = [&](int64_t r, const f32x4 (&cur)[RT][2], f32x4 (&nxt)[RT][2], int buf)
-      __attribute__((always_inline)) {
-    const bool more = r + BK < re;
-    if (more) {
-      load_x(r + BK);
-      load_a(r + BK, nxt);
-    }
-    compute(buf, cur);
-    if (more) store_x(buf ^ 1);
-    __syncthreads();
-  };
-  if (rb < re) {
-    load_x(rb);
-    load_a(rb, ra0);
-    store_x(0);
-    __syncthreads();
-    for (int64_t r = rb;;) {
-      stage(r, ra0, ra1, 0);
-      r += BK;
-      if (r >= re) break;
-      stage(r, ra1, ra0, 1);
-      r += BK;
-      if (r >= re) break;
-    }
-  }
-
-  // Epilogue: acc[i][j][e] is out[p][c] with p = p0 + 16 RT wave + 16 i + 4 g4 + e,
-  // c = c0 + 16 j + pr (the 16x16 MFMA output layout).
-  double rs = 0.0;
-#pragma unroll
-  for (int i = 0; i < RT; ++i) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t p = p0 + wave * 16 * RT + i * 16 + g4 * 4 + e;
-      if (p >= g.P) continue;
-      bool rowok = true;
-      if (epi == EPI_SUB && g.rowmask) rowok = g.rowmask[p] < 0;
-      if (!rowok) continue;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        if (DYN && j >= ntr) continue;
-        const int64_t c = c0 + j * 16 + pr;
-        if (c >= g.C) continue;
-        const float v = acc[i][j][e];
-        if (epi == EPI_STORE) {
-          g.out[p * g.ldo + c] = v;
-        } else if (epi == EPI_PART) {
-          g.out[(int64_t)split * g.part_stride + p * g.ldo + c] = v;
-        } else if (epi == EPI_SUB) {
-          g.out[p * g.ldo + c] -= v;
-        } else {
-          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + (int64_t)g.qidx[c] * g.aref_cs] - (double)v;
-          rs = fma(d, d, rs);
-        }
-      }
-    }
-  }
-  const int64_t wg = (int64_t)gr.by * gr.gx + gr.bx;
-  if (g.sumsq_part != nullptr && gr.by == 0) {
-    const double t = block_sum_double(ss, red);
-    if (tid == 0) g.sumsq_part[gr.bx] = t;
-  }
-  if (epi == EPI_RESID) {
-    const double t = block_sum_double(rs, red);
-    if (tid == 0) g.resid_part[wg] = t;
-  }
-}
-
-template <int NT, int EPI>
-__device__ void b_pass_direct(const GemmArgs& g, const Grid& gr) {
-  pass_direct_body<NT, EPI>(g, gr);
-}
-
 template <int MODE, int NT, int EPI>
 __device__ void b_pass(const GemmArgs& g, const Grid& gr) {
   pass_body<MODE, NT, EPI>(g, gr);
@@ -472,18 +283,6 @@ template <int EPI>
 __device__ void b_pass_any(const GemmArgs& g, const Grid& gr) {
   if (g.mode == 0) pass_body<0, 8, EPI, GEMM_BP / 64, GEMM_BK, true>(g, gr);
   else pass_body<1, 8, EPI, GEMM_BP / 64, GEMM_BK, true>(g, gr);
-}
-
-template <int EPI>
-hipError_t launch_direct_nt(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
-  switch (nt) {
-#define PLU_ND_CASE(N) \
-  case N: return dispatch<GemmArgs, b_pass_direct<N, EPI>, 256, 2>(a, grid, 0, s);
-    PLU_ND_CASE(1) PLU_ND_CASE(2) PLU_ND_CASE(3) PLU_ND_CASE(4)
-    PLU_ND_CASE(5) PLU_ND_CASE(6) PLU_ND_CASE(7) PLU_ND_CASE(8)
-#undef PLU_ND_CASE
-    default: return hipErrorInvalidValue;
-  }
 }
 
 template <int MODE, int EPI>
@@ -682,12 +481,6 @@ hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const Gem
   // column blocks of nt*16 columns each
   dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
   if ((int64_t)pl.cblocks * pl.nt * 16 < g.C) return hipErrorInvalidValue;
-  if (mode == 0 && pl.variant == 1 && !thread_recorder() && g.run_if == nullptr) {
-    switch (epi) {
-      case EPI_STORE: return launch_direct_nt<EPI_STORE>(pl.nt, grid, g, s);
-      case EPI_PART: return launch_direct_nt<EPI_PART>(pl.nt, grid, g, s);
-    }
-  }
   if (mode == 0) {
     switch (epi) {
       case EPI_STORE: return launch_nt<0, EPI_STORE>(pl.nt, grid, g, s);

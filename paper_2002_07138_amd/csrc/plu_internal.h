@@ -54,7 +54,6 @@ constexpr int GEMM_BK = 32;
 struct GemmPlan {
   int pblocks, cblocks, nt, nsplit;
   int64_t rsplit;
-  int variant = 0;   // direction N only: 1 reads A straight into registers (same bits)
 };
 // kalign: the split length is a multiple of it (the reduction depth of one
 // stage of the kernel that runs the plan).
