@@ -28,6 +28,10 @@ design notes of the repository):
   R8  When l columns are not enough, the rank-l result is returned with
       ``tol_reached = False`` (the Remark after Alg. 8 suggests a restart; that
       is not part of this oracle).
+  R15 Restart (the Remark after Alg. 8): when a round's l columns miss the
+      tolerance, a fresh Gaussian matrix is drawn and Alg. 7 runs on the
+      remainder A - A V V^T; the new block is projected out of V twice and
+      re-orthonormalized, and the indicator continues over all columns.
   R13 Precision form (not in the paper, which computes in float64): the v - 1
       passes of Alg. 7 take operands rounded to a narrower format (module
       ``lowp``) and accumulate exactly; the final product with A, the LU and
@@ -225,6 +229,7 @@ class Factorization:
     V: np.ndarray | None = None
     Y: np.ndarray | None = None
     Bt: np.ndarray | None = None
+    G: np.ndarray | None = None        # A V over all kept columns (fixed precision)
     normA2: float = 0.0
     E: np.ndarray | None = None        # running indicator E_j (fixed precision)
     tol_reached: bool = True
@@ -310,22 +315,49 @@ def rank_rule(normA2: float, colnorm2: np.ndarray, eps: float, b: int,
 
 def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
                column_mode: bool = True, pass_round=None,
-               exact_last: bool = False) -> Factorization:
+               exact_last: bool = False, restart_omegas=()) -> Factorization:
     """PowerLU_FP (Alg. 9) on top of Alg. 8 (block rule) or Alg. 11 (column
     rule).  l = Omega.shape[1] must be a multiple of b (Sec. 4.1, l = s b).
-    pass_round: precision form of the v - 1 range passes; G = A V is exact."""
+    pass_round: precision form of the v - 1 range passes; G = A V is exact.
+
+    restart_omegas (reading R15 of the Remark after Alg. 8): when the l
+    columns of a round do not reach the tolerance, the next round draws a
+    fresh Gaussian matrix (the next entry, same shape as Omega) and runs
+    Alg. 7 on the remainder R = A - A V V^T of the columns found so far.
+    The new block is orthogonalized against V (Range(R^T) is orthogonal to
+    V in exact arithmetic; projecting twice, then a thin QR, keeps that in
+    floating point), its G block is A times it, and the indicator of
+    Thm 4.3 continues over the concatenated columns, blocks of b included.
+    The rounds stop when the tolerance is met or the entries run out."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     l = Omega.shape[1]
-    if l % b != 0 or not (l < min(m, n)):
-        raise ValueError("need b | l and l < min(m, n)")
+    rounds = 1 + len(restart_omegas)
+    if l % b != 0 or not (l * rounds < min(m, n)):
+        raise ValueError("need b | l and (rounds * l) < min(m, n)")
     normA2 = float(np.sum(A * A))
     rec = RangeRecord()
     V = range_basis(A, Omega, v, rec, pass_round, exact_last)
     G = A @ V
     colnorm2 = np.sum(G * G, axis=0)
-    E = indicator(normA2, colnorm2)
     k, ok = rank_rule(normA2, colnorm2, eps, b, column_mode)
+    used = 1
+    for Om in restart_omegas:
+        if ok:
+            break
+        used += 1
+        R = A - G @ V.T                                  # remainder A (I - V V^T)
+        Vr = range_basis(R, np.asarray(Om, dtype=np.float64), v, RangeRecord(),
+                         pass_round, exact_last)
+        for _ in range(2):                               # against the columns kept so far
+            Vr = Vr - V @ (V.T @ Vr)
+        Vr = thin_qr(Vr)
+        Gr = A @ Vr
+        V = np.concatenate([V, Vr], axis=1)
+        G = np.concatenate([G, Gr], axis=1)
+        colnorm2 = np.sum(G * G, axis=0)
+        k, ok = rank_rule(normA2, colnorm2, eps, b, column_mode)
+    E = indicator(normA2, colnorm2)
     if k == 0:
         fac = Factorization(p=np.arange(m), q=np.arange(n), L=np.zeros((m, 0)),
                             U=np.zeros((0, n)), rank=0)
@@ -334,8 +366,9 @@ def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
     fac.normA2 = normA2
     fac.E = E
     fac.tol_reached = ok
-    fac.passes = rec.passes + 1
+    fac.passes = (rec.passes + 1) * used       # v passes over A (or its remainder) per round
     fac.V = V
+    fac.G = G
     return fac
 
 
