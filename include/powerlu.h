@@ -137,17 +137,26 @@ int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const flo
  *   eps    > 0 relative Frobenius tolerance.
  *   b      block size >= 1; l (sketch width) must be a multiple of b and
  *          < min(m, n); l = 0 selects min(50 b, b * floor((min(m,n)-1)/b)).
- *   L, U   device outputs with room for l columns / rows: L m x l (ldl >= l),
- *          U l x n (ldu >= n); only the leading rank columns/rows are written.
+ *   max_rounds >= 1, with l * max_rounds < min(m, n).  1 is Alg. 9 as
+ *          printed.  Above 1, a round whose l columns miss the tolerance is
+ *          followed by another (the restart of the Remark after Alg. 8):
+ *          a fresh Gaussian matrix, drawn on the device from seed + r for
+ *          round r (0-based; round 0 uses Omega when given), and Alg. 7 on
+ *          the remainder A - A V V^T of the columns kept so far; the
+ *          indicator continues over all columns.  One synchronization per
+ *          round.  Needs l * max_rounds columns of L and rows of U.
+ *   L, U   device outputs with room for l * max_rounds columns / rows:
+ *          L m x (l max_rounds) (ldl >= l max_rounds), U (l max_rounds) x n
+ *          (ldu >= n); only the leading rank columns/rows are written.
  *   rank_out host int32*, nullable: receives k (the call synchronizes to read
  *          it; the rank is also in info).
- * If eps is not met within l columns the rank-l factorization is returned
- * with PLU_TOL_NOT_REACHED.  A zero matrix gives rank 0.                  */
+ * If eps is not met within l * max_rounds columns, that factorization is
+ * returned with PLU_TOL_NOT_REACHED.  A zero matrix gives rank 0.         */
 int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
-                        int64_t lda, double eps, int32_t b, int32_t l, int32_t v, int32_t column_exact,
-                        int32_t prec, const float* Omega, uint64_t seed,
-                        int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
-                        int32_t* rank_out, plu_info* info);
+                        int64_t lda, double eps, int32_t b, int32_t l, int32_t v,
+                        int32_t column_exact, int32_t max_rounds, int32_t prec,
+                        const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                        int64_t ldl, float* U, int64_t ldu, int32_t* rank_out, plu_info* info);
 
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.

@@ -110,7 +110,8 @@ def _lib():
             "plu_status_string": [ctypes.c_int],
             "plu_fixed_rank": [vp, i32, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
                                vp, vp, vp, i64, vp, i64, pinfo],
-            "plu_fixed_precision": [vp, i32, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, vp, u64,
+            "plu_fixed_precision": [vp, i32, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, i32, vp,
+                                    u64,
                                     vp, vp, vp, i64, vp, i64, ctypes.POINTER(i32), pinfo],
             "plu_residual": [vp, i32, i64, i64, vp, i64, vp, vp, i32, vp, i64, vp, i64,
                              ctypes.POINTER(dbl)],
@@ -343,13 +344,13 @@ class Handle:
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
 
     def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,
-                        prec=PREC_FP32):
+                        prec=PREC_FP32, max_rounds=1):
         t = self._torch
         _check_mat(Omega, "Omega")
         lay, lda = _layout_of(A)
         m, n = A.shape
         dev = A.device
-        lcap = l if l else min(50 * b, b * ((min(m, n) - 1) // b))
+        lcap = (l if l else min(50 * b, b * ((min(m, n) - 1) // b))) * max(int(max_rounds), 1)
         p = t.empty(m, dtype=t.int32, device=dev)
         q = t.empty(n, dtype=t.int32, device=dev)
         L = t.empty((m, lcap), dtype=t.float32, device=dev)
@@ -357,7 +358,8 @@ class Handle:
         k = ctypes.c_int32()
         info = PluInfo()
         rc = _lib().plu_fixed_precision(self._h, lay, m, n, _ptr(A), lda, float(eps), b, l, v,
-                                        1 if column_exact else 0, prec, _ptr(Omega), seed,
+                                        1 if column_exact else 0, int(max_rounds), prec,
+                                        _ptr(Omega), seed,
                                         _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
                                         ctypes.byref(k), ctypes.byref(info))
         self._rc(rc, "plu_fixed_precision", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT, PLU_TOL_NOT_REACHED))

@@ -117,6 +117,8 @@ struct Ws {
   // matrix A^T, so A X is the transposed-direction pass over that storage
   // and A^T Y the direct one
   bool acol = false;
+  // restarted fixed precision: the kept basis V (n x lp) and G = A V (m x lp)
+  float *vall = nullptr, *gall = nullptr;
 };
 
 int64_t part_need(int64_t m, int64_t n, int64_t l) {
@@ -161,7 +163,8 @@ int64_t lowp_part_need(int64_t m, int64_t n, int64_t l, int prec) {
   return need;
 }
 
-Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32) {
+Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
+          bool basis_store = false) {
   prec &= PLU_PREC_FORMAT_MASK;
   Ws w{};
   const int64_t Mx = std::max(m, n);
@@ -226,13 +229,17 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32) 
     w.x8s = L.take<uint8_t>((size_t)w.x8_rows * (w.ldx8 / 32));
     w.sumsq_cap = std::max<int64_t>(w.sumsq_cap, 1);
   }
+  if (basis_store) {
+    w.vall = L.take<float>(n * lp);
+    w.gall = L.take<float>(m * lp);
+  }
   return w;
 }
 
 int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
-              int prec = PLU_PREC_FP32) {
+              int prec = PLU_PREC_FP32, bool basis_store = false) {
   Layout dry;
-  layout(dry, m, n, l, prec);
+  layout(dry, m, n, l, prec, basis_store);
   const size_t need = dry.off + 256;
   if (need > h->arena_bytes) {
     if (h->arena) {
@@ -251,7 +258,7 @@ int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
   }
   Layout L;
   L.base = h->arena;
-  *out = layout(L, m, n, l, prec);
+  *out = layout(L, m, n, l, prec, basis_store);
   if (h->tag_counter == 0) {
     if (launch_fill_u32(reinterpret_cast<uint32_t*>(out->msg), out->msg_words * 2, 0u, h->stream) !=
         hipSuccess)
@@ -537,11 +544,44 @@ hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t
                          h->stream);
 }
 
+// out -= B (C^T X) with C (rc x Ld), B (rb x Ld), both leading dimension
+// ldd; X rc x l (ldx); W (Ld x l, ldw) is scratch.  The small product C^T X
+// reduces over rc rows with split-K through the workspace partials.
+hipError_t project_out(plu_handle h, const Ws& w, const float* C, const float* B, int64_t ldd,
+                       int64_t Ld, int64_t rc, int64_t rb, const float* X, int64_t ldx, int64_t l,
+                       float* out, int64_t ldo, float* W, int64_t ldw) {
+  hipError_t e;
+  GemmArgs g;
+  g.A = C; g.lda = ldd; g.X = X; g.ldx = ldx;
+  g.P = Ld; g.R = rc; g.C = l;
+  int max_split = (int)std::min<int64_t>(64, w.part_cap / std::max<int64_t>(Ld * ldw, 1));
+  if (max_split < 1) max_split = 1;
+  const GemmPlan pl = plan_gemm(Ld, rc, l, max_split, 1024);
+  if (pl.nsplit > 1) {
+    g.out = w.part; g.ldo = ldw; g.part_stride = Ld * ldw;
+    if ((e = launch_gemm(1, EPI_PART, 0, g, pl, h->stream)) != hipSuccess) return e;
+    if ((e = launch_splitk_reduce(w.part, Ld * ldw, pl.nsplit, W, ldw, Ld, l, nullptr, 64,
+                                  h->stream)) != hipSuccess)
+      return e;
+  } else {
+    g.out = W; g.ldo = ldw;
+    if ((e = launch_gemm(1, EPI_STORE, 0, g, pl, h->stream)) != hipSuccess) return e;
+  }
+  GemmArgs u;
+  u.A = B; u.lda = ldd; u.X = W; u.ldx = ldw; u.out = out; u.ldo = ldo;
+  u.P = rb; u.R = Ld; u.C = l;
+  return launch_gemm(0, EPI_SUB, 0, u, plan_gemm(rb, Ld, l, 1, 1), h->stream);
+}
+
 // Alg. 7.  Leaves the orthonormal n x l basis in *Vout (one of the workspace
-// buffers, leading dimension w.lp); passes counted in *passes.
+// buffers, leading dimension w.lp); passes counted in *passes.  With Ld > 0
+// it runs on the remainder A (I - Vd Vd^T) of the kept basis Vd (n x Ld)
+// with Gd = A Vd (m x Ld), both of leading dimension w.lp: each pass A X
+// becomes A X - Gd (Vd^T X) and each A^T Y becomes A^T Y - Vd (Gd^T Y).
 hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A, int64_t lda,
                        int l, int v, const float* Omega, uint64_t seed, float** Vout,
-                       int* passes, int prec = PLU_PREC_FP32) {
+                       int* passes, int prec = PLU_PREC_FP32, const float* Vd = nullptr,
+                       const float* Gd = nullptr, int64_t Ld = 0) {
   const int64_t lp = w.lp;
   const int64_t rows = (v % 2 == 0) ? m : n;
   hipError_t e;
@@ -574,13 +614,20 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
   auto pass = [&](int trans, const float* X, float* out) -> hipError_t {
     const bool rounded = any_rounded && !(refine && pidx == v - 2);
     ++pidx;
-    if (rounded && fmt == PLU_PREC_BF16) return run_pass_bf16(h, w, trans, m, n, X, lp, l, out, lp);
-    if (rounded && fmt == PLU_PREC_FP8_E4M3)
-      return run_pass_fp8(h, w, trans, m, n, X, lp, l, out, lp);
-    hipError_t r = run_pass(h, w, trans, m, n, A, lda, X, lp, l, out, lp,
-                            first ? normA2 : nullptr, nullptr, nullptr);
-    first = false;
-    return r;
+    hipError_t r;
+    if (rounded && fmt == PLU_PREC_BF16) {
+      r = run_pass_bf16(h, w, trans, m, n, X, lp, l, out, lp);
+    } else if (rounded && fmt == PLU_PREC_FP8_E4M3) {
+      r = run_pass_fp8(h, w, trans, m, n, X, lp, l, out, lp);
+    } else {
+      r = run_pass(h, w, trans, m, n, A, lda, X, lp, l, out, lp, first ? normA2 : nullptr, nullptr,
+                   nullptr);
+      first = false;
+    }
+    if (r != hipSuccess || Ld == 0) return r;
+    // the remainder's pass (w.bt, n x lp, holds the small Ld x l product)
+    return trans == 0 ? project_out(h, w, Vd, Gd, lp, Ld, n, m, X, lp, l, out, lp, w.bt, lp)
+                      : project_out(h, w, Gd, Vd, lp, Ld, m, n, X, lp, l, out, lp, w.bt, lp);
   };
   if (v % 2 == 0) {
     if ((e = pass(1, w.om, w.zn)) != hipSuccess) return e;
@@ -620,15 +667,18 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
   return hipSuccess;
 }
 
-// Alg. 5 steps 4-8 given Y = A V(:, :k) in w.ym (leading dimension lp) and V.
+// Alg. 5 steps 4-8 given Y = A V(:, :k) (leading dimension lp; w.ym unless Yin
+// is given) and V.  Y is overwritten.
 hipError_t assemble(plu_handle h, const Ws& w, int64_t m, int64_t n, int k, const float* V,
-                    int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu) {
+                    int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                    float* Yin = nullptr) {
   const int64_t lp = w.lp;
+  float* const Y = Yin ? Yin : w.ym;
   hipError_t e;
   const GetrfWork g1 = getrf_work(h, w, 1);
   const GetrfWork g2 = getrf_work(h, w, 2);
-  // [L1, U1, P] = lu(Y): ym <- P^T L1, ut1 <- U1^T
-  if ((e = getrf_run(w.ym, lp, m, k, g1, p, w.ut1, lp, 1, h->stream)) != hipSuccess) return e;
+  // [L1, U1, P] = lu(Y): Y <- P^T L1, ut1 <- U1^T
+  if ((e = getrf_run(Y, lp, m, k, g1, p, w.ut1, lp, 1, h->stream)) != hipSuccess) return e;
   if ((e = trace_getrf(h, g1, k)) != hipSuccess) return e;
   // B^T = V(:, :k) U1^T  (n x k)
   {
@@ -644,7 +694,7 @@ hipError_t assemble(plu_handle h, const Ws& w, int64_t m, int64_t n, int k, cons
   // L = L1 U2^T with L1 = (P^T L1)[p]
   {
     GemmArgs g;
-    g.A = w.ym; g.lda = lp; g.arow = p; g.X = w.ut2; g.ldx = lp; g.out = L; g.ldo = ldl;
+    g.A = Y; g.lda = lp; g.arow = p; g.X = w.ut2; g.ldx = lp; g.out = L; g.ldo = ldl;
     g.P = m; g.R = k; g.C = k;
     if ((e = launch_gemm(0, EPI_STORE, 0, g, plan_gemm(m, k, k, 1, 1), h->stream)) != hipSuccess)
       return e;
@@ -1385,6 +1435,83 @@ void server_finisher(plu_server S, int idx) {
   }
 }
 
+
+// PowerLU_FP with restarts (the Remark after Alg. 8): when a round's l
+// columns miss the tolerance, the next round draws a fresh Gaussian matrix
+// (on the device, from seed + round) and runs Alg. 7 on the remainder
+// A (I - V V^T) of the basis V kept so far.  The new block is projected out
+// of V twice and re-orthonormalized, its G block is A times it, and the
+// Thm 4.3 indicator continues over the concatenated columns.  V and G
+// accumulate in w.vall and w.gall; the assembly (Alg. 9 steps 2-6) runs on
+// their first k columns.  One synchronization per round reads its rank.
+int fixed_precision_rounds(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A,
+                           int64_t lda, double eps, int b, int l, int v, int column_exact,
+                           int rounds, int prec, const float* Omega, uint64_t seed, int32_t* p,
+                           int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                           int32_t* rank_out, plu_info* info) {
+  const int64_t lp = w.lp;
+  const GetrfWork gw = getrf_work(h, w, 0);
+  const QrWork qw = qr_work(w, w.qb, lp);
+  const size_t rowb = (size_t)l * sizeof(float), pitch = (size_t)lp * sizeof(float);
+  int np = 0, k = 0;
+  bool tol_ok = false;
+  int64_t off = 0;
+  double sc[2] = {0.0, 0.0};
+  for (int r = 0; r < rounds; ++r) {
+    float* V = nullptr;
+    int npr = 0;
+    PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, r == 0 ? Omega : nullptr,
+                            seed + (uint64_t)r, &V, &npr, prec, w.vall, w.gall, off));
+    np += npr;
+    float* Vr = w.vall + off;
+    PLU_TRY_HIP(hipMemcpy2DAsync(Vr, pitch, V, pitch, rowb, n, hipMemcpyDeviceToDevice,
+                                 h->stream));
+    if (off > 0) {
+      for (int rep = 0; rep < 2; ++rep)
+        PLU_TRY_HIP(project_out(h, w, w.vall, w.vall, lp, off, n, n, Vr, lp, l, Vr, lp, w.bt, lp));
+      PLU_TRY_HIP(thin_qr_run(Vr, lp, n, l, gw, qw, h->stream));   // orthonormal block in w.qb
+      PLU_TRY_HIP(hipMemcpy2DAsync(Vr, pitch, w.qb, pitch, rowb, n, hipMemcpyDeviceToDevice,
+                                   h->stream));
+    }
+    // G block = A V_r with float64 column energies, and the basis columns' norms
+    int nblk = 0;
+    PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, Vr, lp, l, w.gall + off, lp, nullptr,
+                         w.colsq_part, &nblk));
+    ++np;
+    PLU_TRY_HIP(launch_splitk_reduce(Vr, 0, 1, nullptr, lp, n, l, w.vsq_part, 64, h->stream));
+    PLU_TRY_HIP(launch_rank_rule(w.colsq_part, nblk, l, w.vsq_part, (int)((n + 63) / 64),
+                                 w.scal + 0, eps, b, column_exact ? 1 : 0, w.iscal + 0, w.scal + 1,
+                                 w.iscal + 1, w.colnorm, h->stream, r == 0 ? nullptr : w.scal + 1));
+    PLU_TRY_HIP(hipStreamSynchronize(h->stream));
+    int32_t ks[2];
+    PLU_TRY_HIP(hipMemcpy(ks, w.iscal, sizeof(ks), hipMemcpyDeviceToHost));
+    PLU_TRY_HIP(hipMemcpy(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    if (!std::isfinite(sc[0])) {
+      if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = PLU_ERR_NONFINITE;
+        info->normA2 = sc[0];
+      }
+      return PLU_ERR_NONFINITE;
+    }
+    tol_ok = ks[1] != 0;
+    k = (int)off + ks[0];
+    if (tol_ok) break;
+    off += l;
+  }
+  if (rank_out) *rank_out = k;
+  const int status = tol_ok ? PLU_OK : PLU_TOL_NOT_REACHED;
+  if (k == 0) {
+    PLU_TRY_HIP(launch_iota(p, m, h->stream));
+    PLU_TRY_HIP(launch_iota(q, n, h->stream));
+  } else {
+    PLU_TRY_HIP(assemble(h, w, m, n, k, w.vall, p, q, L, ldl, U, ldu, w.gall));
+  }
+  int rs = finish_info(h, w, status, k, np, l, true, info);
+  if (info) info->tol_reached = tol_ok ? 1 : 0;
+  return info ? rs : status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1667,9 +1794,9 @@ int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const flo
 
 int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
                         int64_t lda, double eps, int32_t b, int32_t l, int32_t v,
-                        int32_t column_exact, int32_t prec, const float* Omega, uint64_t seed,
-                        int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
-                        int32_t* rank_out, plu_info* info) {
+                        int32_t column_exact, int32_t max_rounds, int32_t prec,
+                        const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                        int64_t ldl, float* U, int64_t ldu, int32_t* rank_out, plu_info* info) {
   if (!h) return -1;
   if (!valid_layout(layout)) return -2;
   if (m <= 0) return -3;
@@ -1682,15 +1809,24 @@ int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, cons
   if (l == 0) l = (int32_t)std::min<int64_t>(50LL * b, b * ((mn - 1) / b));
   if (l <= 0 || l % b != 0 || l >= mn) return -9;
   if (v < 2) return -10;
-  if (!valid_prec(prec)) return -12;
-  if (!p) return -15;
-  if (!q) return -16;
-  if (!L) return -17;
-  if (ldl < l) return -18;
-  if (!U) return -19;
-  if (ldu < n) return -20;
+  if (max_rounds < 1 || (int64_t)l * max_rounds >= mn) return -12;
+  if (!valid_prec(prec)) return -13;
+  if (!p) return -16;
+  if (!q) return -17;
+  if (!L) return -18;
+  if (ldl < (int64_t)l * max_rounds) return -19;
+  if (!U) return -20;
+  if (ldu < n) return -21;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
+  if (max_rounds > 1) {
+    int st = ensure_ws(h, m, n, (int64_t)l * max_rounds, &w, prec, true);
+    if (st) return st;
+    w.acol = layout == PLU_COL_MAJOR;
+    trace_reset(h);
+    return fixed_precision_rounds(h, w, m, n, A, lda, eps, b, l, v, column_exact, max_rounds, prec,
+                                  Omega, seed, p, q, L, ldl, U, ldu, rank_out, info);
+  }
   int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
   w.acol = layout == PLU_COL_MAJOR;

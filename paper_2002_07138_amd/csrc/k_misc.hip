@@ -111,6 +111,7 @@ struct RankArgs {
   const double* colsq_part; int nblk, l; const double* vsq_part; int nvblk;
   const double* normA2p; double eps; int b, col_mode; int32_t* kout; double* Eout;
   int32_t* tol; double* colnorm;
+  const double* E0p;   // nullable: indicator before these columns (default ||A||^2)
 };
 
 __device__ void b_rank_rule(const RankArgs& a, const Grid& gr) {
@@ -132,7 +133,7 @@ __device__ void b_rank_rule(const RankArgs& a, const Grid& gr) {
   if (threadIdx.x != 0) return;
   const double nA2 = *a.normA2p;
   int k = l, ok = 0;
-  double E = nA2;
+  double E = a.E0p ? *a.E0p : nA2;
   if (nA2 == 0.0) {
     k = 0;
     ok = 1;
@@ -210,11 +211,11 @@ hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* r
 hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,
                             int nvblk, const double* normA2, double eps, int b, int col_mode,
                             int32_t* kout, double* Eout, int32_t* tol, double* colnorm,
-                            hipStream_t s) {
+                            hipStream_t s, const double* E0) {
   if (l > 8192) return hipErrorInvalidValue;
   return dispatch<RankArgs, b_rank_rule, 256>(
       RankArgs{colsq_part, nblk, l, vsq_part, nvblk, normA2, eps, b, col_mode, kout, Eout, tol,
-               colnorm},
+               colnorm, E0},
       dim3(1), (size_t)l * sizeof(double), s);
 }
 

@@ -152,7 +152,7 @@ hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* r
 hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,
                             int nvblk, const double* normA2, double eps, int b, int col_mode,
                             int32_t* kout, double* Eout, int32_t* tol, double* colnorm,
-                            hipStream_t s);
+                            hipStream_t s, const double* E0 = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 
