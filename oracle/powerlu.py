@@ -32,6 +32,10 @@ design notes of the repository):
       tolerance, a fresh Gaussian matrix is drawn and Alg. 7 runs on the
       remainder A - A V V^T; the new block is projected out of V twice and
       re-orthonormalized, and the indicator continues over all columns.
+  R16 Single-pass LU (Alg. 10): Omega is m x k as the listing sizes it (the
+      text's n x k does not conform with A^T Omega); U = L2^T as the text
+      derives (the listing's last line reads L^T); pinv(G^T) is the
+      Moore-Penrose inverse of the full-row-rank k x n matrix G^T.
   R13 Precision form (not in the paper, which computes in float64): the v - 1
       passes of Alg. 7 take operands rounded to a narrower format (module
       ``lowp``) and accumulate exactly; the final product with A, the LU and
@@ -368,6 +372,36 @@ def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
     fac.tol_reached = ok
     fac.passes = (rec.passes + 1) * used       # v passes over A (or its remainder) per round
     fac.V = V
+    fac.G = G
+    return fac
+
+
+# ----------------------------------------------------------------------------
+# Sec. 5: single-pass randomized LU (Alg. 10).
+# ----------------------------------------------------------------------------
+def single_pass_lu(A: np.ndarray, k: int, Omega: np.ndarray) -> Factorization:
+    """Alg. 10.  Omega is m x k (the listing's size; reading R16).  G = A^T Omega
+    and H = A G are the two products the one pass over A yields (the Remark
+    after the derivation streams the columns of A once, forming G(i,:) and
+    the outer product A(:,i) G(i,:) together); here they are plain products.
+    [L1, U1, P] = lu(H); the pseudo-inverse of G^T (n x k, G of full column
+    rank) times U1^T is factored as [L2, U2, Q] = lu(.); L = L1 U2^T and
+    U = L2^T (the listing's last line reads U = L^T; the text's derivation
+    gives L2^T).  That is Alg. 5's assembly with V := pinv(G^T) and Y := H,
+    so the approximation L U equals A G pinv(G) = A V V^T for V an
+    orthonormal basis of Range(A^T Omega), in the row and column orders p, q."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    Omega = np.asarray(Omega, dtype=np.float64)
+    if Omega.shape != (m, k) or not (1 <= k < min(m, n)):
+        raise ValueError("need Omega m x k and 1 <= k < min(m, n)")
+    G = A.T @ Omega                      # n x k
+    H = A @ G                            # m x k
+    Gt_pinv = np.linalg.pinv(G.T)        # n x k
+    fac = assemble(A, Gt_pinv, Y=H)
+    fac.normA2 = float(np.sum(A * A))
+    fac.passes = 1
+    fac.V = Gt_pinv
     fac.G = G
     return fac
 
