@@ -158,6 +158,21 @@ int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, cons
                         const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
                         int64_t ldl, float* U, int64_t ldu, int32_t* rank_out, plu_info* info);
 
+/* ---- Single-pass randomized LU (Alg. 10, Sec. 5): G = A^T Omega and
+ * H = A G from one pass over A, [L1, U1, P] = lu(H), [L2, U2, Q] =
+ * lu(pinv(G^T) U1^T), L = L1 U2^T, U = L2^T.  The one-pass schedule needs
+ * the columns of A contiguous (layout PLU_COL_MAJOR, as the paper states):
+ * blocks of columns are read from HBM once, multiplied into G and, while
+ * still cached, into H.  With PLU_ROW_MAJOR the same result takes two
+ * passes.  pinv(G^T) = Q R^{-T} from a thin QR G = Q R.
+ *   k      1 <= k <= 128, k < min(m, n); no oversampling (as in Alg. 10).
+ *   Omega  device, nullable: m x k with leading dimension k (NULL: drawn
+ *          from seed as in plu_gaussian).
+ *   A, lda, p, q, L, ldl, U, ldu, info   as for plu_fixed_rank.           */
+int plu_single_pass(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                    int64_t lda, int32_t k, const float* Omega, uint64_t seed, int32_t* p,
+                    int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu, plu_info* info);
+
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
  *   all matrix/vector pointers device; rel_resid host; layout of A as in

@@ -544,29 +544,34 @@ hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t
                          h->stream);
 }
 
+// W (P x l, ldw) = C^T X for C rc x P (ldc) and X rc x l (ldx): a short wide
+// product whose reduction over the rc rows is split through the workspace
+// partials.
+hipError_t small_tn(plu_handle h, const Ws& w, const float* C, int64_t ldc, const float* X,
+                    int64_t ldx, int64_t P, int64_t rc, int64_t l, float* W, int64_t ldw) {
+  hipError_t e;
+  GemmArgs g;
+  g.A = C; g.lda = ldc; g.X = X; g.ldx = ldx;
+  g.P = P; g.R = rc; g.C = l;
+  int max_split = (int)std::min<int64_t>(64, w.part_cap / std::max<int64_t>(P * ldw, 1));
+  if (max_split < 1) max_split = 1;
+  const GemmPlan pl = plan_gemm(P, rc, l, max_split, 1024);
+  if (pl.nsplit > 1) {
+    g.out = w.part; g.ldo = ldw; g.part_stride = P * ldw;
+    if ((e = launch_gemm(1, EPI_PART, 0, g, pl, h->stream)) != hipSuccess) return e;
+    return launch_splitk_reduce(w.part, P * ldw, pl.nsplit, W, ldw, P, l, nullptr, 64, h->stream);
+  }
+  g.out = W; g.ldo = ldw;
+  return launch_gemm(1, EPI_STORE, 0, g, pl, h->stream);
+}
+
 // out -= B (C^T X) with C (rc x Ld), B (rb x Ld), both leading dimension
-// ldd; X rc x l (ldx); W (Ld x l, ldw) is scratch.  The small product C^T X
-// reduces over rc rows with split-K through the workspace partials.
+// ldd; X rc x l (ldx); W (Ld x l, ldw) is scratch.
 hipError_t project_out(plu_handle h, const Ws& w, const float* C, const float* B, int64_t ldd,
                        int64_t Ld, int64_t rc, int64_t rb, const float* X, int64_t ldx, int64_t l,
                        float* out, int64_t ldo, float* W, int64_t ldw) {
   hipError_t e;
-  GemmArgs g;
-  g.A = C; g.lda = ldd; g.X = X; g.ldx = ldx;
-  g.P = Ld; g.R = rc; g.C = l;
-  int max_split = (int)std::min<int64_t>(64, w.part_cap / std::max<int64_t>(Ld * ldw, 1));
-  if (max_split < 1) max_split = 1;
-  const GemmPlan pl = plan_gemm(Ld, rc, l, max_split, 1024);
-  if (pl.nsplit > 1) {
-    g.out = w.part; g.ldo = ldw; g.part_stride = Ld * ldw;
-    if ((e = launch_gemm(1, EPI_PART, 0, g, pl, h->stream)) != hipSuccess) return e;
-    if ((e = launch_splitk_reduce(w.part, Ld * ldw, pl.nsplit, W, ldw, Ld, l, nullptr, 64,
-                                  h->stream)) != hipSuccess)
-      return e;
-  } else {
-    g.out = W; g.ldo = ldw;
-    if ((e = launch_gemm(1, EPI_STORE, 0, g, pl, h->stream)) != hipSuccess) return e;
-  }
+  if ((e = small_tn(h, w, C, ldd, X, ldx, Ld, rc, l, W, ldw)) != hipSuccess) return e;
   GemmArgs u;
   u.A = B; u.lda = ldd; u.X = W; u.ldx = ldw; u.out = out; u.ldo = ldo;
   u.P = rb; u.R = Ld; u.C = l;
@@ -1871,6 +1876,97 @@ int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, cons
   int rs = finish_info(h, w, status, k, np, l, true, info);
   if (info) info->tol_reached = tol_ok ? 1 : 0;
   return info ? rs : status;
+}
+
+int plu_single_pass(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                    int64_t lda, int32_t k, const float* Omega, uint64_t seed, int32_t* p,
+                    int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu, plu_info* info) {
+  if (!h) return -1;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
+  const bool col = layout == PLU_COL_MAJOR;
+  if (lda < (col ? m : n)) return -6;
+  if (k < 1 || k > 128 || k >= std::min(m, n)) return -7;
+  if (!p) return -10;
+  if (!q) return -11;
+  if (!L) return -12;
+  if (ldl < k) return -13;
+  if (!U) return -14;
+  if (ldu < n) return -15;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  Ws w;
+  int st = ensure_ws(h, m, n, k, &w);
+  if (st) return st;
+  w.acol = col;
+  trace_reset(h);
+  hipStream_t s = h->stream;
+  const int64_t lp = w.lp;
+  // Alg. 10 step 1: Omega (m x k)
+  if (Omega) PLU_TRY_HIP(launch_copy_pad(Omega, k, w.om, lp, m, k, k, s));
+  else PLU_TRY_HIP(launch_gaussian(w.om, lp, m, k, seed, s));
+  // steps 2-3: G = A^T Omega (n x k, w.zn) and H = A G (m x k, w.ym)
+  if (!col) {
+    // rows of A are contiguous: G is complete only after every row, so
+    // these are two passes (the one-pass form needs the columns contiguous)
+    PLU_TRY_HIP(run_pass(h, w, 1, m, n, A, lda, w.om, lp, k, w.zn, lp, w.scal + 0, nullptr,
+                         nullptr));
+    PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, w.zn, lp, k, w.ym, lp, nullptr, nullptr,
+                         nullptr));
+  } else {
+    // one pass (the Remark after the derivation): column i of A is row i of
+    // the storage; for a block of storage rows, G's rows = block x Omega, then
+    // H -= block^T x G's rows, while the block is still in the caches (its
+    // bytes are read from HBM once); H is negated at the end
+    PLU_TRY_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(w.ym), (size_t)m * lp, 0u, s));
+    const int64_t blk = std::max<int64_t>(128, ((int64_t)(48 << 20) / (4 * m)) / 128 * 128);
+    int64_t sq_off = 0;
+    for (int64_t i0 = 0; i0 < n; i0 += blk) {
+      const int64_t b = std::min(blk, n - i0);
+      GemmArgs g;
+      g.A = A + i0 * lda; g.lda = lda; g.X = w.om; g.ldx = lp;
+      g.P = b; g.R = m; g.C = k;
+      int max_split = (int)std::min<int64_t>(64, w.part_cap / std::max<int64_t>(b * lp, 1));
+      if (max_split < 1) max_split = 1;
+      const GemmPlan pl = plan_gemm(b, m, k, max_split, 1024);
+      if (sq_off + (int64_t)pl.pblocks * pl.nsplit > w.sumsq_cap) return PLU_ERR_NOT_IMPLEMENTED;
+      g.sumsq_part = w.sumsq_part + sq_off;   // ||A||_F^2 partials of this block
+      sq_off += (int64_t)pl.pblocks * pl.nsplit;
+      float* Gb = w.zn + i0 * lp;
+      if (pl.nsplit > 1) {
+        g.out = w.part; g.ldo = lp; g.part_stride = b * lp;
+        PLU_TRY_HIP(launch_gemm(0, EPI_PART, 0, g, pl, s));
+        PLU_TRY_HIP(launch_splitk_reduce(w.part, b * lp, pl.nsplit, Gb, lp, b, k, nullptr, 64, s));
+      } else {
+        g.out = Gb; g.ldo = lp;
+        PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, pl, s));
+      }
+      GemmArgs u;
+      u.A = A + i0 * lda; u.lda = lda; u.X = Gb; u.ldx = lp; u.out = w.ym; u.ldo = lp;
+      u.P = m; u.R = b; u.C = k;
+      PLU_TRY_HIP(launch_gemm(1, EPI_SUB, 0, u, plan_gemm(m, b, k, 1, 1), s));
+    }
+    PLU_TRY_HIP(launch_sum_doubles(w.sumsq_part, sq_off, w.scal + 0, s));
+    PLU_TRY_HIP(launch_negate(w.ym, lp, m, k, s));
+  }
+  // pinv(G^T) = Q R^{-T} with G = Q R (thin QR of a copy of G, R = Q^T G)
+  const GetrfWork gw = getrf_work(h, w, 0);
+  const QrWork qw = qr_work(w, w.qb, lp);
+  PLU_TRY_HIP(hipMemcpy2DAsync(w.bt, lp * sizeof(float), w.zn, lp * sizeof(float),
+                               k * sizeof(float), n, hipMemcpyDeviceToDevice, s));
+  PLU_TRY_HIP(thin_qr_run(w.bt, lp, n, k, gw, qw, s));
+  PLU_TRY_HIP(small_tn(h, w, w.qb, lp, w.zn, lp, k, n, k, w.ut2, lp));   // R (k x k)
+  PLU_TRY_HIP(launch_tri_inv_t(w.ut2, lp, w.ut1, lp, k, s));              // (R^{-1})^T
+  {
+    GemmArgs g;
+    g.A = w.qb; g.lda = lp; g.X = w.ut1; g.ldx = lp; g.out = w.zn; g.ldo = lp;
+    g.P = n; g.R = k; g.C = k;
+    PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, plan_gemm(n, k, k, 1, 1), s));
+  }
+  // steps 4-7: lu(H), lu(pinv(G^T) U1^T), L = L1 U2^T, U = L2^T
+  PLU_TRY_HIP(assemble(h, w, m, n, k, w.zn, p, q, L, ldl, U, ldu, w.ym));
+  return finish_info(h, w, PLU_OK, k, 1, k, false, info);
 }
 
 int plu_rank_rule(plu_handle h, int64_t m, int32_t l, const float* G, int64_t ldg, double normA2,

@@ -184,6 +184,49 @@ __device__ void b_iota(const IotaArgs& a, const Grid& gr) {
   if (i < a.n) a.p[i] = (int32_t)i;
 }
 
+struct NegateArgs {
+  float* p; int64_t ld, rows, cols;
+};
+
+__device__ void b_negate(const NegateArgs& a, const Grid& gr) {
+  const int64_t e = (int64_t)gr.bx * 256 + threadIdx.x;
+  if (e >= a.rows * a.cols) return;
+  const int64_t r = e / a.cols, c = e % a.cols;
+  a.p[r * a.ld + c] = -a.p[r * a.ld + c];
+}
+
+// X = (R^{-1})^T for the upper triangular k x k factor R (k <= 128), by
+// back substitution, one column of R^{-1} per thread, float64 sums; X is
+// lower triangular.  One workgroup.
+struct TriInvArgs {
+  const float* R; int64_t ldr; float* X; int64_t ldx; int k;
+};
+
+__device__ void b_tri_inv_t(const TriInvArgs& a, const Grid& gr) {
+  (void)gr;
+  __shared__ float Rs[128][129];
+  __shared__ float Ys[128][129];   // Ys[i][c] = (R^{-1})[i][c]
+  const int k = a.k;
+  for (int e = threadIdx.x; e < k * k; e += 128) {
+    const int i = e / k, j = e % k;
+    Rs[i][j] = a.R[(int64_t)i * a.ldr + j];
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < k) {
+    for (int i = k - 1; i >= 0; --i) {
+      if (i > c) {
+        Ys[i][c] = 0.f;
+        continue;
+      }
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int j = i + 1; j <= c; ++j) s -= (double)Rs[i][j] * (double)Ys[j][c];
+      Ys[i][c] = (float)(s / (double)Rs[i][i]);
+    }
+    for (int i = 0; i < k; ++i) a.X[(int64_t)c * a.ldx + i] = Ys[i][c];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gaussian(float* out, int64_t ldo, int64_t rows, int64_t cols, uint64_t seed,
@@ -228,5 +271,19 @@ hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s) {
   return dispatch<IotaArgs, b_iota, 256>(IotaArgs{p, n}, dim3((unsigned)((n + 255) / 256)), 0,
                                          s);
 }
+
+hipError_t launch_negate(float* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t s) {
+  const int64_t tot = rows * cols;
+  if (tot == 0) return hipSuccess;
+  return dispatch<NegateArgs, b_negate, 256>(NegateArgs{p, ld, rows, cols},
+                                            dim3((unsigned)((tot + 255) / 256)), 0, s);
+}
+
+hipError_t launch_tri_inv_t(const float* R, int64_t ldr, float* X, int64_t ldx, int k,
+                            hipStream_t s) {
+  if (k < 1 || k > 128) return hipErrorInvalidValue;
+  return dispatch<TriInvArgs, b_tri_inv_t, 128>(TriInvArgs{R, ldr, X, ldx, k}, dim3(1), 0, s);
+}
+
 
 }  // namespace plu

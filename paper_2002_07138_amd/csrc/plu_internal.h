@@ -155,5 +155,10 @@ hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const dou
                             hipStream_t s, const double* E0 = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
+// p[r][c] = -p[r][c] over a rows x cols block (leading dimension ld)
+hipError_t launch_negate(float* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
+// X = (R^{-1})^T for an upper triangular k x k R, k <= 128 (one workgroup)
+hipError_t launch_tri_inv_t(const float* R, int64_t ldr, float* X, int64_t ldx, int k,
+                            hipStream_t s);
 
 }  // namespace plu
