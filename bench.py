@@ -64,6 +64,42 @@ def flops_fixed_precision(m: int, n: int, l: int, k: int, v: int) -> float:
 FORMS = {"bf16": 1, "fp8_e4m3": 2, "bf16+refine_last": 1 | 16, "fp8_e4m3+refine_last": 2 | 16}
 
 
+def single_pass_section(h, A, k, reps=5):
+    """Single-pass randomized LU (Alg. 10) at the workload shape: one pass over
+    a column-major copy of A (the storage order the paper's one-pass form
+    needs), two over the row-major A, against PowerLU at v = 2 without
+    oversampling (the same approximation); residuals from plu_residual."""
+    import torch
+    m, n = A.shape
+    Ac = A.t().contiguous().t()          # same matrix, columns contiguous
+    res = {}
+    for name, M in (("column_major_one_pass", Ac), ("row_major_two_passes", A)):
+        f = h.single_pass(M, k, seed=31, sync_info=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            h.single_pass(M, k, seed=31, sync_info=False)
+        e1.record()
+        e1.synchronize()
+        res[name] = {"ms": round(e0.elapsed_time(e1) / reps, 3),
+                     "residual": h.residual(M, f)}
+    g = h.fixed_rank(A, k, 0, 2, seed=31, sync_info=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.fixed_rank(A, k, 0, 2, seed=31, sync_info=False)
+    e1.record()
+    e1.synchronize()
+    res["powerlu_v2_p0"] = {"ms": round(e0.elapsed_time(e1) / reps, 3),
+                            "residual": h.residual(A, g)}
+    res["k"] = k
+    del Ac
+    torch.cuda.empty_cache()
+    return res
+
+
 def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
     """The precision form (rounded passes, fp32 refinement pass) on the same
     workload and seeds as the fp32 step; residuals against the fp32 path's."""
@@ -468,6 +504,7 @@ def main():
 
     if not args.no_forms:
         forms = precision_forms(h, A, outs, m, n, k, p_over, resid)
+        single = single_pass_section(h, A, k)
     traffic = load_traffic()
     roofline = {
         "bound": "mfma",
@@ -504,6 +541,7 @@ def main():
     }
     if not args.no_forms:
         result["precision_forms"] = forms
+        result["single_pass"] = single
 
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
