@@ -390,6 +390,33 @@ def profile_pass(m, n):
                       "copy_bytes_each_direction": 4 * 2 ** 28}))
 
 
+def profile_single_pass(m, n, k=100):
+    """HBM bytes of the single-pass LU: after a 1 GiB fill (the start mark),
+    one call on a column-major A (one pass), a 1 GiB copy (calibration, and
+    the boundary between the two), one call on the row-major A (two passes)."""
+    import torch
+    import paper_2002_07138_amd as plu
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    A = torch.randn((m, n), device=dev, generator=g)
+    Ac = A.t().contiguous().t()
+    h = plu.Handle(0)
+    src = torch.empty(2 ** 28, device=dev)
+    dst = torch.empty_like(src)
+    h.single_pass(Ac, k, seed=3, sync_info=True)      # workspace and plans
+    h.single_pass(A, k, seed=3, sync_info=True)
+    torch.cuda.synchronize()
+    src.fill_(1.0)                                    # marks the start of the counted calls
+    h.single_pass(Ac, k, seed=3, sync_info=False)
+    dst.copy_(src)
+    h.single_pass(A, k, seed=3, sync_info=False)
+    torch.cuda.synchronize()
+    h.close()
+    print(json.dumps({"profile_single_pass": True, "m": m, "n": n, "k": k,
+                      "bytes_of_A": 4.0 * m * n, "copy_bytes_each_direction": 4 * 2 ** 28}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,6 +430,9 @@ def main():
     ap.add_argument("--pool", type=int, default=16, help="distinct matrices of the serving replay")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the batched comparison and the serving replay")
+    ap.add_argument("--profile-single-pass", action="store_true",
+                    help="run only the single-pass LU on a column-major and a row-major A "
+                         "around a plain 1 GiB copy, for hardware-counter runs")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run only the pass kernels at the workload shape (3 launches per "
                          "direction) and a plain 1 GiB copy, for hardware-counter runs")
@@ -421,6 +451,9 @@ def main():
     m = n = args.size
     if args.profile_pass:
         profile_pass(m, n)
+        return
+    if args.profile_single_pass:
+        profile_single_pass(m, n)
         return
     if args.serving_only:
         pool = serving_pool(args.pool)
