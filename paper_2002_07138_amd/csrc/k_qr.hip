@@ -99,12 +99,9 @@ __device__ void b_gram_reduce(const GramReduceArgs& ga, const Grid& gr) {
   W[e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
-// Cholesky W = L L^T and X = L^{-1} in float64, both in one LDS tile: L in
-// the lower triangle (S[i][t], t <= i) and X transposed in the upper part
-// (X[i][c] at S[c][i+1], c <= i).  R^{-1} = X^T is written as float32
-// (upper triangular, bw x bw, leading dimension ldr) and, when Rinv64 is set,
-// as float64.  The column being eliminated is copied to its own array so the
-// trailing update reads and writes different LDS objects.
+// Cholesky W = L L^T and Y = L^{-1} in float64 inside one workgroup; R^{-1}
+// = Y^T is written as float32 (upper triangular, bw x bw, leading dimension
+// ldr) and, when Rinv64 is set, as float64.
 struct CholArgs {
   const double* W; int bw; float* Rinv; int64_t ldr; double* Rinv64; int32_t* status;
   int32_t* need_lu;   // nullable: set to 1 when the Cholesky factor shows X ill-conditioned
@@ -117,17 +114,34 @@ struct CholArgs {
 // cond(X) well below 1e7, and the ratio underestimates cond(X).
 constexpr double kCholRatioMin = 1e-4;
 
+constexpr int CHOL_NB = 16;    // block size of the blocked Cholesky
+constexpr int CHOL_QS = 17;    // row stride (doubles) of the block-column buffer
+
+// A lane's double from lane src of the wave (src is a constant after unrolling).
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
-  // Blocked (16 columns) right-looking Cholesky of the bw x bw Gram matrix,
-  // then X = L^{-1} by blocks of 16 rows, all in LDS (float64):
-  //   factor: the diagonal block by one wave (16 wave-synchronous steps), the
-  //           panel below by a row-parallel triangular solve, the trailing
-  //           matrix by a rank-16 update -- three barriers per block;
-  //   inverse: for each block I of rows, T = E_I - L(I, :I) X(:I, :) in
-  //           parallel, then X(I, :) = L_II^{-1} T column-parallel -- two
-  //           barriers per block.
-  // X is lower triangular; X[r][c] (c <= r) is stored at S[c][r + 1], the
-  // upper part that the factor does not use.
+  // Right-looking blocked Cholesky (blocks of 16) that carries the inverse
+  // along: Y = L^{-1} is the product of the elimination steps applied to I,
+  // so block row J of Y is X_JJ T(J, :) (X_JJ = L_JJ^{-1}, T the running
+  // right-hand side) and the rows below lose L(I, J) Y(J, :).  Per block:
+  //   (1) one wave factors the 16 x 16 diagonal block and inverts it in
+  //       registers (lane r holds row r of L_JJ and column r of X_JJ; the
+  //       pivot column is broadcast with readlane);
+  //   (2) the panel L(I, J) = A(I, J) X_JJ^T (a product, not a triangular
+  //       solve) and Y(J, :J) = X_JJ T(J, :J), one row or column per thread,
+  //       into a block-column buffer Q: Q[i] = L(i, J) for rows below the
+  //       block, Q[c] = Y(J, c)^T for columns up to the block;
+  //   (3) one symmetric rank-16 update out(r, c) -= Q[r] . Q[c] for every
+  //       row r below the block and c <= r: the trailing matrix for c below
+  //       the block, T for c up to it; 4 x 4 register tiles.
+  // S holds A / L in its lower triangle and Y transposed above it: Y[r][c]
+  // (c <= r) at S[c][r + 1].
   (void)gr;
   const double* W = ca.W;
   const int bw = ca.bw;
@@ -136,23 +150,50 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   double* Rinv64 = ca.Rinv64;
   int32_t* status = ca.status;
   if (ca.run_if && *ca.run_if == 0) return;
-  constexpr int NBk = 16;
+  constexpr int NB = CHOL_NB;
   __shared__ int bad;
   __shared__ double S[QB][QB + 1];
+  __shared__ double Q[QB][CHOL_QS];
+  __shared__ double Xd[NB][NB];     // X_JJ[r][c]
+  __shared__ double Dg[QB];         // diagonal of L
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int tx = t & 15, ty = t >> 4;
   if (t == 0) bad = 0;
-  for (int r = ty; r < bw; r += 16)
-    for (int c = tx; c <= r; c += 16) S[r][c] = W[r * bw + c];
+  {
+    // lower triangle of W; zero above it (the running T / Y storage)
+    const int n1 = bw + 1, tot = bw * n1;
+    for (int e0 = t; e0 < tot; e0 += 4 * 256) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        const int r = e / n1, c = e - r * n1;
+        v[u] = (e < tot && c <= r) ? W[r * bw + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        const int r = e / n1, c = e - r * n1;
+        if (e < tot) S[r][c] = v[u];
+      }
+    }
+  }
   __syncthreads();
-  for (int J = 0; J < bw; J += NBk) {
-    const int nb = (bw - J < NBk) ? bw - J : NBk;
-    // (1) diagonal block, one wave; LDS operations of a wave complete in order
+  const int nblk = (bw + NB - 1) / NB;
+  for (int J = 0; J < bw; J += NB) {
+    const int nb = (bw - J < NB) ? bw - J : NB;
+    // (1) diagonal block, padded to 16 x 16 with the identity
     if (wave == 0) {
-      for (int jj = 0; jj < nb; ++jj) {
-        const int j = J + jj;
-        double d = S[j][j];
+      const int r = lane;
+      double a[NB], x[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        a[c] = (r < nb && c <= r) ? S[J + r][J + c] : (r == c ? 1.0 : 0.0);
+        x[c] = (r == c) ? 1.0 : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double d = readlane_f64(a[j], j);
         if (!(d > 0.0)) {
           if (lane == 0) {
             status[2] = 1;
@@ -162,89 +203,134 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
         }
         const double sd = sqrt(d);
         const double rp = 1.0 / sd;
-        if (lane < nb - jj - 1) S[j + 1 + lane][j] *= rp;
-        if (lane == 0) S[j][j] = sd;
-        __builtin_amdgcn_wave_barrier();
-        // rank-1 update of the rest of the diagonal block
-        const int rem = nb - jj - 1;
-        for (int e = lane; e < rem * rem; e += 64) {
-          const int i = j + 1 + e / rem, c = j + 1 + e % rem;
-          if (c <= i) S[i][c] = fma(-S[i][j], S[c][j], S[i][c]);
+        a[j] = (r == j) ? sd : ((r > j) ? a[j] * rp : a[j]);
+        x[j] *= rp;
+#pragma unroll
+        for (int c = j + 1; c < NB; ++c) {
+          const double lc = readlane_f64(a[j], c);   // L(J + c, J + j)
+          a[c] = fma(-a[j], lc, a[c]);
+          x[c] = fma(-lc, x[j], x[c]);
         }
-        __builtin_amdgcn_wave_barrier();
+      }
+      if (r < NB) {
+#pragma unroll
+        for (int rr = 0; rr < NB; ++rr) Xd[rr][r] = x[rr];
+      }
+      if (r < nb) {
+        Dg[J + r] = a[r];
+#pragma unroll
+        for (int rr = 0; rr < NB; ++rr) {
+          Q[J + r][rr] = x[rr];                                 // Y(J + rr, J + r)
+          if (rr >= r && rr < nb) S[J + r][J + rr + 1] = x[rr];
+        }
       }
     }
     __syncthreads();
-    // (2) panel: rows below the block, L(i, J:J+nb) = A(i, J:J+nb) L_JJ^{-T}
-    {
-      const int i = J + nb + t;
-      if (i < bw) {
-        double v[NBk];
+    // (2) panel rows and block row J of Y
+    const int r0 = J + nb, nrow = bw - r0;
+    if (t < nrow) {
+      const int i = r0 + t;       // nrow > 0 implies nb == 16
+      double am[NB];
 #pragma unroll
-        for (int jj = 0; jj < NBk; ++jj) {
-          if (jj < nb) {
-            double a = S[i][J + jj];
+      for (int m = 0; m < NB; ++m) am[m] = S[i][J + m];
 #pragma unroll
-            for (int kk = 0; kk < jj; ++kk) a = fma(-v[kk], S[J + jj][J + kk], a);
-            v[jj] = a / S[J + jj][J + jj];
+      for (int c = 0; c < NB; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m <= c; ++m) s = fma(am[m], Xd[c][m], s);
+        Q[i][c] = s;
+      }
+    } else if (t - nrow < J) {
+      const int c = t - nrow;
+      double tm[NB];
+#pragma unroll
+      for (int m = 0; m < NB; ++m) tm[m] = (m < nb) ? S[c][J + 1 + m] : 0.0;
+#pragma unroll
+      for (int rr = 0; rr < NB; ++rr) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m <= rr; ++m) s = fma(Xd[rr][m], tm[m], s);
+        Q[c][rr] = s;
+        if (rr < nb) S[c][J + 1 + rr] = s;
+      }
+    }
+    __syncthreads();
+    if (nrow <= 0) break;
+    // (3) out(r, c) -= Q[r] . Q[c], r >= r0, c <= r, over 16 x 16 tiles
+    // (R, C), R the row block (below the diagonal one), C <= R, each tile by
+    // 16 threads of 4 x 4
+    const int Rb0 = J / NB + 1;
+    const int ntiles = (nblk * (nblk + 1) - Rb0 * (Rb0 + 1)) / 2;
+    for (int w = t; w < ntiles * 16; w += 256) {
+      int tile = w >> 4;
+      const int sub = w & 15;
+      int R = Rb0;
+      while (tile > R) {
+        tile -= R + 1;
+        ++R;
+      }
+      const int C = tile;
+      const bool tpart = C < Rb0;            // columns of T (transposed storage)
+      const int rb = R * NB + 4 * (sub >> 2), cb = C * NB + 4 * (sub & 3);
+      double acc[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = rb + i, c = cb + j;
+          acc[i][j] = (r < bw && c <= r) ? (tpart ? S[c][r + 1] : S[r][c]) : 0.0;
+        }
+#pragma unroll 4
+      for (int kk = 0; kk < NB; ++kk) {
+        double qa[4], qb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) qa[i] = Q[rb + i][kk];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) qb[j] = Q[cb + j][kk];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(-qa[i], qb[j], acc[i][j]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = rb + i, c = cb + j;
+          if (r < bw && c <= r) {
+            if (tpart) S[c][r + 1] = acc[i][j];
+            else S[r][c] = acc[i][j];
           }
         }
-#pragma unroll
-        for (int jj = 0; jj < NBk; ++jj)
-          if (jj < nb) S[i][J + jj] = v[jj];
-      }
-    }
-    __syncthreads();
-    // (3) trailing update, lower triangle
-    for (int i = J + nb + ty; i < bw; i += 16) {
-      for (int c = J + nb + tx; c <= i; c += 16) {
-        double a = S[i][c];
-#pragma unroll
-        for (int kk = 0; kk < NBk; ++kk)
-          if (kk < nb) a = fma(-S[i][J + kk], S[c][J + kk], a);
-        S[i][c] = a;
-      }
     }
     __syncthreads();
   }
   if (ca.need_lu && t == 0) {
-    double mn = S[0][0], mx = S[0][0];
+    double mn = Dg[0], mx = Dg[0];
     for (int j = 1; j < bw; ++j) {
-      mn = fmin(mn, S[j][j]);
-      mx = fmax(mx, S[j][j]);
+      mn = fmin(mn, Dg[j]);
+      mx = fmax(mx, Dg[j]);
     }
     *ca.need_lu = (bad || !(mn > kCholRatioMin * mx)) ? 1 : 0;
   }
-  // X = L^{-1}, block row by block row
-  for (int I0 = 0; I0 < bw; I0 += NBk) {
-    const int nb = (bw - I0 < NBk) ? bw - I0 : NBk;
-    // (a) T(r, c) = [r == c] - sum_{c <= m < I0} L[r][m] X[m][c], r in the block,
-    //     c <= r; stored in X's slots S[c][r + 1]
-    for (int e = t; e < nb * (I0 + nb); e += 256) {
-      const int r = I0 + e / (I0 + nb), c = e % (I0 + nb);
-      if (c > r) continue;
-      double a = (r == c) ? 1.0 : 0.0;
-      for (int m = c; m < I0; ++m) a = fma(-S[r][m], S[c][m + 1], a);
-      S[c][r + 1] = a;
+  // Rinv[r][c] = Y[c][r] = S[r][c + 1] for r <= c
+  const int tot = bw * bw;
+  for (int e0 = t; e0 < tot; e0 += 4 * 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + 256 * u;
+      const int r = e / bw, c = e - r * bw;
+      v[u] = (e < tot && r <= c) ? S[r][c + 1] : 0.0;
     }
-    __syncthreads();
-    // (b) X(I, c) = L_II^{-1} T(:, c), each column c by one thread
-    for (int c = t; c < I0 + nb; c += 256) {
-      for (int rr = 0; rr < nb; ++rr) {
-        const int r = I0 + rr;
-        if (c > r) continue;
-        double a = S[c][r + 1];
-        for (int m = (c > I0 ? c : I0); m < r; ++m) a = fma(-S[r][m], S[c][m + 1], a);
-        S[c][r + 1] = a / S[r][r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + 256 * u;
+      const int r = e / bw, c = e - r * bw;
+      if (e < tot) {
+        Rinv[(int64_t)r * ldr + c] = (float)v[u];
+        if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v[u];
       }
-    }
-    __syncthreads();
-  }
-  for (int r = ty; r < bw; r += 16) {
-    for (int c = tx; c < bw; c += 16) {   // Rinv[r][c] = X[c][r] = S[r][c+1] for r <= c
-      const double v = (r <= c) ? S[r][c + 1] : 0.0;
-      Rinv[(int64_t)r * ldr + c] = (float)v;
-      if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v;
     }
   }
 }
