@@ -116,6 +116,7 @@ constexpr double kCholRatioMin = 1e-4;
 
 constexpr int CHOL_NB = 16;    // block size of the blocked Cholesky
 constexpr int CHOL_QS = 17;    // row stride (doubles) of the block-column buffer
+constexpr int CHOL_T = 512;    // threads of the Cholesky workgroup (two waves per SIMD)
 
 // A lane's double from lane src of the wave (src is a constant after unrolling).
 __device__ __forceinline__ double readlane_f64(double v, int src) {
@@ -123,6 +124,19 @@ __device__ __forceinline__ double readlane_f64(double v, int src) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// 1/sqrt(d) for a positive normal d: the hardware estimate and two Newton
+// steps y <- y + y (1 - d y^2) / 2 (each squares the relative error, so the
+// estimate's ~2^-22 ends below double rounding).
+__device__ __forceinline__ double rsqrt_f64(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(d * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
 }
 
 __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
@@ -134,14 +148,17 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   //       registers (lane r holds row r of L_JJ and column r of X_JJ; the
   //       pivot column is broadcast with readlane);
   //   (2) the panel L(I, J) = A(I, J) X_JJ^T (a product, not a triangular
-  //       solve) and Y(J, :J) = X_JJ T(J, :J), one row or column per thread,
-  //       into a block-column buffer Q: Q[i] = L(i, J) for rows below the
-  //       block, Q[c] = Y(J, c)^T for columns up to the block;
+  //       solve) and Y(J, :J) = X_JJ T(J, :J), one row or column per thread
+  //       with the same arithmetic, into a block-column buffer Q:
+  //       Q[i] = L(i, J) for rows below the block, Q[c] = Y(J, c)^T for
+  //       columns up to it;
   //   (3) one symmetric rank-16 update out(r, c) -= Q[r] . Q[c] for every
   //       row r below the block and c <= r: the trailing matrix for c below
   //       the block, T for c up to it; 4 x 4 register tiles.
   // S holds A / L in its lower triangle and Y transposed above it: Y[r][c]
-  // (c <= r) at S[c][r + 1].
+  // (c <= r) at S[c][r + 1].  Entries of S that no later step reads (the
+  // factored block column, rows and columns past bw) take whatever the
+  // branch-free loads and stores put there; every access stays inside S.
   (void)gr;
   const double* W = ca.W;
   const int bw = ca.bw;
@@ -153,30 +170,36 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   constexpr int NB = CHOL_NB;
   __shared__ int bad;
   __shared__ double S[QB][QB + 1];
-  __shared__ double Q[QB][CHOL_QS];
-  __shared__ double Xd[NB][NB];     // X_JJ[r][c]
-  __shared__ double Dg[QB];         // diagonal of L
+  // Q rows QB .. QB + 15 hold the 16 x 16 identity (read as rows, so the
+  // per-lane unit vectors are reloaded each block instead of held live)
+  __shared__ double Q[QB + NB][CHOL_QS];
+  __shared__ __align__(16) double XdT[NB][NB];   // XdT[m][c] = X_JJ[c][m]
+  __shared__ double Dg[QB];                      // diagonal of L
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   if (t == 0) bad = 0;
+  if (t < NB * NB) Q[QB + t / NB][t % NB] = (t / NB == t % NB) ? 1.0 : 0.0;
   {
-    // lower triangle of W; zero above it (the running T / Y storage)
-    const int n1 = bw + 1, tot = bw * n1;
-    for (int e0 = t; e0 < tot; e0 += 4 * 256) {
-      double v[4];
+    // S[r][c] = W[r][c] for c <= r < bw, 0 elsewhere in rows and columns
+    // 0 .. 127 (the running T / Y above the diagonal); column 128 is zero.
+    // Thread (ry, cx) of 32 x 16 covers rows ry + 32 p and columns cx + 16 u;
+    // every load is issued before the first store (clamped addresses).
+    const int cx = t & 15, ry = t >> 4;
+    double v[4][8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + 256 * u;
-        const int r = e / n1, c = e - r * n1;
-        v[u] = (e < tot && c <= r) ? W[r * bw + c] : 0.0;
+    for (int p4 = 0; p4 < 4; ++p4)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = ry + 32 * p4, c = cx + 16 * u;
+        const int rr = (r < bw) ? r : bw - 1, cc = (c < rr) ? c : rr;
+        const double w = W[rr * bw + cc];
+        v[p4][u] = (r < bw && c <= r) ? w : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + 256 * u;
-        const int r = e / n1, c = e - r * n1;
-        if (e < tot) S[r][c] = v[u];
-      }
-    }
+    for (int p4 = 0; p4 < 4; ++p4)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) S[ry + 32 * p4][cx + 16 * u] = v[p4][u];
+    if (t < QB) S[t][QB] = 0.0;
   }
   __syncthreads();
   const int nblk = (bw + NB - 1) / NB;
@@ -184,12 +207,18 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
     const int nb = (bw - J < NB) ? bw - J : NB;
     // (1) diagonal block, padded to 16 x 16 with the identity
     if (wave == 0) {
+      // Lane r < nb holds row r of the block (entries above the diagonal are
+      // never combined with those below it, so they are left as they come);
+      // lanes nb .. 15 hold identity rows, other lanes row 0 of the identity.
       const int r = lane;
+      const int rs = (r < NB) ? r : 0;
+      const double* arow = (r < nb) ? &S[J + r][J] : &Q[QB + rs][0];
+      const double* irow = &Q[QB + rs][0];
       double a[NB], x[NB];
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        a[c] = (r < nb && c <= r) ? S[J + r][J + c] : (r == c ? 1.0 : 0.0);
-        x[c] = (r == c) ? 1.0 : 0.0;
+        a[c] = arow[c];
+        x[c] = irow[c];
       }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -200,10 +229,13 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
             bad = 1;
           }
           d = DBL_MIN;
+          a[j] = (r == j) ? d : a[j];
         }
-        const double sd = sqrt(d);
-        const double rp = 1.0 / sd;
-        a[j] = (r == j) ? sd : ((r > j) ? a[j] * rp : a[j]);
+        const double rp = rsqrt_f64(d);
+        // column j of L: the pivot lane gets d / sqrt(d) = sqrt(d), the rows
+        // below their multipliers
+        a[j] *= rp;
+        if (lane == 0) Dg[J + j] = d * rp;
         x[j] *= rp;
 #pragma unroll
         for (int c = j + 1; c < NB; ++c) {
@@ -211,57 +243,65 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
           a[c] = fma(-a[j], lc, a[c]);
           x[c] = fma(-lc, x[j], x[c]);
         }
+        // finish the step's updates here (an empty asm that takes the
+        // registers in and out; no instruction): the compiler would otherwise
+        // sink them to their next use and keep every broadcast multiplier of
+        // the block live in scalar registers
+#pragma unroll
+        for (int c = j + 1; c < NB; ++c) asm volatile("" : "+v"(a[c]), "+v"(x[c]));
       }
       if (r < NB) {
 #pragma unroll
-        for (int rr = 0; rr < NB; ++rr) Xd[rr][r] = x[rr];
+        for (int c = 0; c < NB; ++c) XdT[r][c] = x[c];
       }
       if (r < nb) {
-        Dg[J + r] = a[r];
+        // Y(J + rr, J + r) = x[rr]; for rr < r the slot is in the factored
+        // (dead) lower part and receives the zero x[rr]
 #pragma unroll
         for (int rr = 0; rr < NB; ++rr) {
-          Q[J + r][rr] = x[rr];                                 // Y(J + rr, J + r)
-          if (rr >= r && rr < nb) S[J + r][J + rr + 1] = x[rr];
+          Q[J + r][rr] = x[rr];
+          S[J + r][J + 1 + rr] = x[rr];
         }
       }
     }
     __syncthreads();
-    // (2) panel rows and block row J of Y
+    // (2) out = v X_JJ^T for a source vector v: the row of the panel
+    // (v = A(i, J:J+16), x = i, y0 = J) or the column of T (v = T(J:J+nb, c),
+    // x = c, y0 = J + 1), four threads per vector, each the outputs
+    // c' = q, q + 4, q + 8, q + 12; Q[x][c'] = S[x][y0 + c'] = out[c'].  In
+    // the last block (nb < 16) out[c'] = 0 for c' >= nb lands in columns past
+    // bw.
     const int r0 = J + nb, nrow = bw - r0;
-    if (t < nrow) {
-      const int i = r0 + t;       // nrow > 0 implies nb == 16
-      double am[NB];
+    if (t < 4 * (nrow + J)) {
+      const int src = t >> 2, q = t & 3;
+      const bool panel = src < nrow;
+      const int x0 = panel ? r0 + src : src - nrow;
+      const int y0 = panel ? J : J + 1;
+      double v[NB];
 #pragma unroll
-      for (int m = 0; m < NB; ++m) am[m] = S[i][J + m];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m <= c; ++m) s = fma(am[m], Xd[c][m], s);
-        Q[i][c] = s;
+      for (int m = 0; m < NB; ++m) {
+        const double sv = S[x0][y0 + m];
+        v[m] = (m < nb) ? sv : 0.0;
       }
-    } else if (t - nrow < J) {
-      const int c = t - nrow;
-      double tm[NB];
 #pragma unroll
-      for (int m = 0; m < NB; ++m) tm[m] = (m < nb) ? S[c][J + 1 + m] : 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const int c = q + 4 * k;
+        double o = 0.0;
 #pragma unroll
-      for (int rr = 0; rr < NB; ++rr) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m <= rr; ++m) s = fma(Xd[rr][m], tm[m], s);
-        Q[c][rr] = s;
-        if (rr < nb) S[c][J + 1 + rr] = s;
+        for (int m = 0; m < 4 * k + 4; ++m) o = fma(v[m], XdT[m][c], o);   // XdT[m][c] = 0 for m > c
+        Q[x0][c] = o;
+        S[x0][y0 + c] = o;
       }
     }
     __syncthreads();
     if (nrow <= 0) break;
     // (3) out(r, c) -= Q[r] . Q[c], r >= r0, c <= r, over 16 x 16 tiles
-    // (R, C), R the row block (below the diagonal one), C <= R, each tile by
-    // 16 threads of 4 x 4
+    // (R, C), R a row block below the diagonal one, C <= R, each tile by 16
+    // threads of 4 x 4.  Rows past bw and c > r in a diagonal tile are
+    // computed too and land in slots no later step reads.
     const int Rb0 = J / NB + 1;
     const int ntiles = (nblk * (nblk + 1) - Rb0 * (Rb0 + 1)) / 2;
-    for (int w = t; w < ntiles * 16; w += 256) {
+    for (int w = t; w < ntiles * 16; w += CHOL_T) {
       int tile = w >> 4;
       const int sub = w & 15;
       int R = Rb0;
@@ -272,36 +312,41 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
       const int C = tile;
       const bool tpart = C < Rb0;            // columns of T (transposed storage)
       const int rb = R * NB + 4 * (sub >> 2), cb = C * NB + 4 * (sub & 3);
+      double* dst[4][4];
       double acc[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int r = rb + i, c = cb + j;
-          acc[i][j] = (r < bw && c <= r) ? (tpart ? S[c][r + 1] : S[r][c]) : 0.0;
+          dst[i][j] = tpart ? &S[c][r + 1] : &S[r][c];
+          acc[i][j] = *dst[i][j];
         }
-#pragma unroll 4
+      double qa[2][4], qb[2][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        qa[0][i] = Q[rb + i][0];
+        qb[0][i] = Q[cb + i][0];
+      }
+#pragma unroll
       for (int kk = 0; kk < NB; ++kk) {
-        double qa[4], qb[4];
+        const int cur = kk & 1, nxt = cur ^ 1;
+        if (kk + 1 < NB) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) qa[i] = Q[rb + i][kk];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) qb[j] = Q[cb + j][kk];
+          for (int i = 0; i < 4; ++i) {
+            qa[nxt][i] = Q[rb + i][kk + 1];
+            qb[nxt][i] = Q[cb + i][kk + 1];
+          }
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fma(-qa[i], qb[j], acc[i][j]);
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(-qa[cur][i], qb[cur][j], acc[i][j]);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = rb + i, c = cb + j;
-          if (r < bw && c <= r) {
-            if (tpart) S[c][r + 1] = acc[i][j];
-            else S[r][c] = acc[i][j];
-          }
-        }
+        for (int j = 0; j < 4; ++j) *dst[i][j] = acc[i][j];
     }
     __syncthreads();
   }
@@ -313,23 +358,27 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
     }
     *ca.need_lu = (bad || !(mn > kCholRatioMin * mx)) ? 1 : 0;
   }
-  // Rinv[r][c] = Y[c][r] = S[r][c + 1] for r <= c
-  const int tot = bw * bw;
-  for (int e0 = t; e0 < tot; e0 += 4 * 256) {
-    double v[4];
+  // Rinv[r][c] = Y[c][r] = S[r][c + 1] for r <= c, 0 below the diagonal
+  {
+    const int cx = t & 15, ry = t >> 4;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + 256 * u;
-      const int r = e / bw, c = e - r * bw;
-      v[u] = (e < tot && r <= c) ? S[r][c + 1] : 0.0;
-    }
+    for (int p4 = 0; p4 < 4; ++p4) {
+      const int r = ry + 32 * p4;
+      if (r >= bw) break;
+      double v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + 256 * u;
-      const int r = e / bw, c = e - r * bw;
-      if (e < tot) {
-        Rinv[(int64_t)r * ldr + c] = (float)v[u];
-        if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v[u];
+      for (int u = 0; u < 8; ++u) {
+        const int c = cx + 16 * u;
+        const double sv = S[r][c + 1];
+        v[u] = (r <= c) ? sv : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = cx + 16 * u;
+        if (c < bw) {
+          Rinv[(int64_t)r * ldr + c] = (float)v[u];
+          if (Rinv64) Rinv64[(int64_t)r * ldr + c] = v[u];
+        }
       }
     }
   }
@@ -430,7 +479,7 @@ hipError_t cholqr_round(const float* src, int64_t lds, int64_t M, int bw, float*
            GramReduceArgs{qw.gram_part, nchunk, bw, qw.gram, factor_if},
            dim3((bw * bw + 255) / 256), 0, s)) != hipSuccess)
     return e;
-  if ((e = dispatch<CholArgs, b_chol_inv, 256>(
+  if ((e = dispatch<CholArgs, b_chol_inv, CHOL_T>(
            CholArgs{qw.gram, bw, qw.rinv, (int64_t)QB, fp64_apply ? qw.rinv64 : nullptr,
                     qw.status, nullptr, factor_if},
            dim3(1), 0, s)) != hipSuccess)
@@ -467,7 +516,7 @@ hipError_t cholqr_probe(const float* X, int64_t ldx, int64_t M, int bw, const Qr
     return e;
   // R^{-1} of X itself is kept in qw.rinv: the first CholeskyQR round reuses
   // it when the LU is skipped
-  return dispatch<CholArgs, b_chol_inv, 256>(
+  return dispatch<CholArgs, b_chol_inv, CHOL_T>(
       CholArgs{qw.gram, bw, qw.rinv, (int64_t)QB, nullptr, qw.status, qw.status + 4, nullptr},
       dim3(1), 0, s);
 }
