@@ -146,7 +146,9 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   // right-hand side) and the rows below lose L(I, J) Y(J, :).  Per block:
   //   (1) one wave factors the 16 x 16 diagonal block and inverts it in
   //       registers (lane r holds row r of L_JJ and column r of X_JJ; the
-  //       pivot column is broadcast with readlane);
+  //       pivot column is broadcast with readlane) -- for block J + 1 this
+  //       runs during step (3) of block J, right after that wave has updated
+  //       the block, while the other waves update the rest;
   //   (2) the panel L(I, J) = A(I, J) X_JJ^T (a product, not a triangular
   //       solve) and Y(J, :J) = X_JJ T(J, :J), one row or column per thread
   //       with the same arithmetic, into a block-column buffer Q:
@@ -174,6 +176,7 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   // per-lane unit vectors are reloaded each block instead of held live)
   __shared__ double Q[QB + NB][CHOL_QS];
   __shared__ __align__(16) double XdT[NB][NB];   // XdT[m][c] = X_JJ[c][m]
+  __shared__ double QD[NB][CHOL_QS];             // Q rows of the diagonal block
   __shared__ double Dg[QB];                      // diagonal of L
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -203,74 +206,79 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
   }
   __syncthreads();
   const int nblk = (bw + NB - 1) / NB;
-  for (int J = 0; J < bw; J += NB) {
+  // (1) for block J, by wave 0: the diagonal block, padded to 16 x 16 with
+  // the identity.  Lane r < nb holds row r of the block (entries above the
+  // diagonal are never combined with those below it, so they are left as they
+  // come); lanes nb .. 15 hold identity rows, other lanes row 0 of the
+  // identity.  Writes X_JJ to XdT and QD, Y_JJ into S, the pivots into Dg.
+  auto diag_block = [&](int J) {
     const int nb = (bw - J < NB) ? bw - J : NB;
-    // (1) diagonal block, padded to 16 x 16 with the identity
-    if (wave == 0) {
-      // Lane r < nb holds row r of the block (entries above the diagonal are
-      // never combined with those below it, so they are left as they come);
-      // lanes nb .. 15 hold identity rows, other lanes row 0 of the identity.
-      const int r = lane;
-      const int rs = (r < NB) ? r : 0;
-      const double* arow = (r < nb) ? &S[J + r][J] : &Q[QB + rs][0];
-      const double* irow = &Q[QB + rs][0];
-      double a[NB], x[NB];
+    const int r = lane;
+    const int rs = (r < NB) ? r : 0;
+    const double* arow = (r < nb) ? &S[J + r][J] : &Q[QB + rs][0];
+    const double* irow = &Q[QB + rs][0];
+    double a[NB], x[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      a[c] = arow[c];
+      x[c] = irow[c];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      double d = readlane_f64(a[j], j);
+      if (!(d > 0.0)) {
+        if (lane == 0) {
+          status[2] = 1;
+          bad = 1;
+        }
+        d = DBL_MIN;
+        a[j] = (r == j) ? d : a[j];
+      }
+      const double rp = rsqrt_f64(d);
+      // column j of L: the pivot lane gets d / sqrt(d) = sqrt(d), the rows
+      // below their multipliers
+      a[j] *= rp;
+      if (lane == 0) Dg[J + j] = d * rp;
+      x[j] *= rp;
+#pragma unroll
+      for (int c = j + 1; c < NB; ++c) {
+        const double lc = readlane_f64(a[j], c);   // L(J + c, J + j)
+        a[c] = fma(-a[j], lc, a[c]);
+        x[c] = fma(-lc, x[j], x[c]);
+      }
+      // finish the step's updates here (an empty asm that takes the
+      // registers in and out; no instruction): the compiler would otherwise
+      // sink them to their next use and keep every broadcast multiplier of
+      // the block live in scalar registers
+#pragma unroll
+      for (int c = j + 1; c < NB; ++c) asm volatile("" : "+v"(a[c]), "+v"(x[c]));
+    }
+    if (r < NB) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        a[c] = arow[c];
-        x[c] = irow[c];
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        double d = readlane_f64(a[j], j);
-        if (!(d > 0.0)) {
-          if (lane == 0) {
-            status[2] = 1;
-            bad = 1;
-          }
-          d = DBL_MIN;
-          a[j] = (r == j) ? d : a[j];
-        }
-        const double rp = rsqrt_f64(d);
-        // column j of L: the pivot lane gets d / sqrt(d) = sqrt(d), the rows
-        // below their multipliers
-        a[j] *= rp;
-        if (lane == 0) Dg[J + j] = d * rp;
-        x[j] *= rp;
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) {
-          const double lc = readlane_f64(a[j], c);   // L(J + c, J + j)
-          a[c] = fma(-a[j], lc, a[c]);
-          x[c] = fma(-lc, x[j], x[c]);
-        }
-        // finish the step's updates here (an empty asm that takes the
-        // registers in and out; no instruction): the compiler would otherwise
-        // sink them to their next use and keep every broadcast multiplier of
-        // the block live in scalar registers
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) asm volatile("" : "+v"(a[c]), "+v"(x[c]));
-      }
-      if (r < NB) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) XdT[r][c] = x[c];
-      }
-      if (r < nb) {
-        // Y(J + rr, J + r) = x[rr]; for rr < r the slot is in the factored
-        // (dead) lower part and receives the zero x[rr]
-#pragma unroll
-        for (int rr = 0; rr < NB; ++rr) {
-          Q[J + r][rr] = x[rr];
-          S[J + r][J + 1 + rr] = x[rr];
-        }
+        XdT[r][c] = x[c];
+        QD[r][c] = x[c];                              // Y(J + c, J + r)
       }
     }
-    __syncthreads();
+    if (r < nb) {
+      // Y(J + rr, J + r) = x[rr]; for rr < r the slot is in the factored
+      // (dead) lower part and receives the zero x[rr]
+#pragma unroll
+      for (int rr = 0; rr < NB; ++rr) S[J + r][J + 1 + rr] = x[rr];
+    }
+  };
+  if (wave == 0) diag_block(0);
+  __syncthreads();
+  for (int J = 0; J < bw; J += NB) {
+    const int nb = (bw - J < NB) ? bw - J : NB;
     // (2) out = v X_JJ^T for a source vector v: the row of the panel
     // (v = A(i, J:J+16), x = i, y0 = J) or the column of T (v = T(J:J+nb, c),
     // x = c, y0 = J + 1), four threads per vector, each the outputs
     // c' = q, q + 4, q + 8, q + 12; Q[x][c'] = S[x][y0 + c'] = out[c'].  In
     // the last block (nb < 16) out[c'] = 0 for c' >= nb lands in columns past
-    // bw.
+    // bw.  The four threads of a vector are lanes of one wave, which reads
+    // all of v before any of them stores.  The diagonal block's rows of Q
+    // come from QD.
     const int r0 = J + nb, nrow = bw - r0;
     if (t < 4 * (nrow + J)) {
       const int src = t >> 2, q = t & 3;
@@ -293,60 +301,92 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
         S[x0][y0 + c] = o;
       }
     }
+    if (t < NB * NB) Q[J + t / NB][t % NB] = QD[t / NB][t % NB];   // rows past bw are never read
     __syncthreads();
     if (nrow <= 0) break;
     // (3) out(r, c) -= Q[r] . Q[c], r >= r0, c <= r, over 16 x 16 tiles
-    // (R, C), R a row block below the diagonal one, C <= R, each tile by 16
-    // threads of 4 x 4.  Rows past bw and c > r in a diagonal tile are
-    // computed too and land in slots no later step reads.
+    // (R, C), R a row block below the diagonal one, C <= R.  Rows past bw and
+    // c > r in a diagonal tile are computed too and land in slots no later
+    // step reads.  Wave 0 takes the tile (Rb0, Rb0), the next diagonal block,
+    // in 2 x 2 pieces and then factors it (look-ahead); waves 1 .. 7 take
+    // the other tiles in 4 x 4 pieces.
     const int Rb0 = J / NB + 1;
-    const int ntiles = (nblk * (nblk + 1) - Rb0 * (Rb0 + 1)) / 2;
-    for (int w = t; w < ntiles * 16; w += CHOL_T) {
-      int tile = w >> 4;
-      const int sub = w & 15;
-      int R = Rb0;
-      while (tile > R) {
-        tile -= R + 1;
-        ++R;
-      }
-      const int C = tile;
-      const bool tpart = C < Rb0;            // columns of T (transposed storage)
-      const int rb = R * NB + 4 * (sub >> 2), cb = C * NB + 4 * (sub & 3);
-      double* dst[4][4];
-      double acc[4][4];
+    if (wave == 0) {
+      const int rb = Rb0 * NB + 2 * (lane >> 3), cb = Rb0 * NB + 2 * (lane & 7);
+      double acc[2][2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = rb + i, c = cb + j;
-          dst[i][j] = tpart ? &S[c][r + 1] : &S[r][c];
-          acc[i][j] = *dst[i][j];
-        }
-      double qa[2][4], qb[2][4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        qa[0][i] = Q[rb + i][0];
-        qb[0][i] = Q[cb + i][0];
-      }
+        for (int j = 0; j < 2; ++j) acc[i][j] = S[rb + i][cb + j];
 #pragma unroll
       for (int kk = 0; kk < NB; ++kk) {
-        const int cur = kk & 1, nxt = cur ^ 1;
-        if (kk + 1 < NB) {
+        const double qa0 = Q[rb][kk], qa1 = Q[rb + 1][kk];
+        const double qb0 = Q[cb][kk], qb1 = Q[cb + 1][kk];
+        acc[0][0] = fma(-qa0, qb0, acc[0][0]);
+        acc[0][1] = fma(-qa0, qb1, acc[0][1]);
+        acc[1][0] = fma(-qa1, qb0, acc[1][0]);
+        acc[1][1] = fma(-qa1, qb1, acc[1][1]);
+      }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            qa[nxt][i] = Q[rb + i][kk + 1];
-            qb[nxt][i] = Q[cb + i][kk + 1];
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) S[rb + i][cb + j] = acc[i][j];
+      // a wave's LDS operations complete in issue order; keep the compiler
+      // from moving the block's loads above these stores
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      diag_block(Rb0 * NB);
+    } else {
+      const int ntiles = (nblk * (nblk + 1) - Rb0 * (Rb0 + 1)) / 2 - 1;   // without (Rb0, Rb0)
+      for (int w = t - 64; w < ntiles * 16; w += CHOL_T - 64) {
+        int tile = w >> 4;
+        const int sub = w & 15;
+        if (tile >= Rb0) ++tile;             // skip (Rb0, Rb0), the Rb0-th tile
+        int R = Rb0;
+        while (tile > R) {
+          tile -= R + 1;
+          ++R;
+        }
+        const int C = tile;
+        const bool tpart = C < Rb0;          // columns of T (transposed storage)
+        const int rb = R * NB + 4 * (sub >> 2), cb = C * NB + 4 * (sub & 3);
+        double* dst[4][4];
+        double acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int r = rb + i, c = cb + j;
+            dst[i][j] = tpart ? &S[c][r + 1] : &S[r][c];
+            acc[i][j] = *dst[i][j];
           }
+        double qa[2][4], qb[2][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          qa[0][i] = Q[rb + i][0];
+          qb[0][i] = Q[cb + i][0];
+        }
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) {
+          const int cur = kk & 1, nxt = cur ^ 1;
+          if (kk + 1 < NB) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              qa[nxt][i] = Q[rb + i][kk + 1];
+              qb[nxt][i] = Q[cb + i][kk + 1];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = fma(-qa[cur][i], qb[cur][j], acc[i][j]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fma(-qa[cur][i], qb[cur][j], acc[i][j]);
+          for (int j = 0; j < 4; ++j) *dst[i][j] = acc[i][j];
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) *dst[i][j] = acc[i][j];
     }
     __syncthreads();
   }
