@@ -100,6 +100,42 @@ def single_pass_section(h, A, k, reps=5):
     return res
 
 
+def _time_calls(fn, reps):
+    """One synchronized call (its result kept), then reps timed calls."""
+    import torch
+    f = fn(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn(False)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps, f
+
+
+def baselines_section(h, A, k, p_over, reps=3):
+    """The paper's fixed-rank timing comparison (Sec. 6.1, Fig. 1) at the
+    workload shape: PowerLU at v = 2p + 2 against RandLU (Alg. 3 + Alg. 4)
+    at power exponent p -- the same 2p + 2 passes over A -- for p = 0 and 1;
+    milliseconds per call and relative residuals (plu_residual)."""
+    out = {}
+    for pw in (0, 1):
+        v = 2 * pw + 2
+        t_pl, f_pl = _time_calls(
+            lambda sync: h.fixed_rank(A, k, p_over, v, seed=71, sync_info=sync), reps)
+        t_rl, f_rl = _time_calls(
+            lambda sync: h.randlu(A, k, p_over, pw, seed=71, sync_info=sync), reps)
+        out[f"p{pw}"] = {
+            "passes": v,
+            "powerlu_ms": round(t_pl, 3), "randlu_ms": round(t_rl, 3),
+            "speedup_powerlu_over_randlu": round(t_rl / t_pl, 3),
+            "residual_powerlu": h.residual(A, f_pl), "residual_randlu": h.residual(A, f_rl),
+        }
+    out["paper_cpu_speedup_powerlu_over_randlu"] = {"p0": 1.80, "p1": 1.44}
+    return out
+
+
 def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
     """The precision form (rounded passes, fp32 refinement pass) on the same
     workload and seeds as the fp32 step; residuals against the fp32 path's."""
@@ -425,6 +461,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=20000, help="reduced sizes for quick checks")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision forms")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the RandLU / RandSVD comparison")
     ap.add_argument("--serving-count", type=int, default=1024,
                     help="requests of the serving replay (0 skips it and the batch comparison)")
     ap.add_argument("--pool", type=int, default=16, help="distinct matrices of the serving replay")
@@ -575,6 +613,8 @@ def main():
     if not args.no_forms:
         result["precision_forms"] = forms
         result["single_pass"] = single
+    if not args.no_baselines:
+        result["baselines"] = baselines_section(h, A, k, p_over)
 
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()

@@ -173,6 +173,29 @@ int plu_single_pass(plu_handle h, int32_t layout, int64_t m, int64_t n, const fl
                     int64_t lda, int32_t k, const float* Omega, uint64_t seed, int32_t* p,
                     int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu, plu_info* info);
 
+/* ---- RandLU (Alg. 3 with its steps 1-3 replaced by the LU power iteration
+ * of Alg. 4, Sec. 2.2): the comparison algorithm the paper measures PowerLU
+ * against.  P Y = L_y U_y for Y = A (A^T A)^pw Omega with an LU
+ * reorthogonalization after every product; L_y = L_y(:, 1:k);
+ * B = L_y^+ P A with L_y^+ = (L_y^T L_y)^{-1} L_y^T (the Remark after
+ * Alg. 4; the Gram matrix and its Cholesky factor in float64);
+ * [L2, U2, Q] = lu(B^T) (B Q = L_b U_b with L_b = U2^T, U_b = L2^T);
+ * L = L_y U2^T, U = L2^T.  2 pw + 2 passes over A.
+ *   k       1 <= k <= 128.
+ *   p_over  oversampling >= 0; l = k + p_over < min(m, n).
+ *   pw      power exponent p >= 0 of Alg. 3 / Alg. 4.
+ *   Omega   device, nullable: n x l with leading dimension l (NULL: drawn
+ *           from seed as in plu_gaussian).
+ *   layout, A, lda, p, q, L, ldl, U, ldu, info   as for plu_fixed_rank
+ *           (A[p][:, q] ~ L U; L is lower trapezoidal in the row order p,
+ *           U unit upper trapezoidal).
+ * Errors: -(argument index) for invalid arguments; PLU_ERR_OOM,
+ * PLU_ERR_HIP, PLU_ERR_TIMEOUT as for plu_fixed_rank.                      */
+int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
+               int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
+               int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+               plu_info* info);
+
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
  *   all matrix/vector pointers device; rel_resid host; layout of A as in

@@ -36,7 +36,7 @@ _ENTRY_POINTS = [
     "plu_fixed_rank", "plu_fixed_precision", "plu_residual", "plu_gaussian", "plu_pass",
     "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule", "plu_quantize",
     "plu_batched", "plu_set_pivot_trace", "plu_pivot_trace", "plu_single_pass",
-    "plu_server_create",
+    "plu_randlu", "plu_server_create",
     "plu_server_submit", "plu_server_poll",
     "plu_server_wait", "plu_server_destroy",
 ]
@@ -128,6 +128,8 @@ def _lib():
             "plu_set_pivot_trace": [vp, i64],
             "plu_single_pass": [vp, i32, i64, i64, vp, i64, i32, vp, u64, vp, vp, vp, i64, vp, i64,
                                 pinfo],
+            "plu_randlu": [vp, i32, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, vp, vp, i64, vp,
+                           i64, pinfo],
             "plu_pivot_trace": [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32,
                                 ctypes.POINTER(i32)],
             "plu_server_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, i32],
@@ -363,6 +365,25 @@ class Handle:
                                     _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
                                     ctypes.byref(info) if sync_info else None)
         self._rc(rc, "plu_single_pass", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
+        return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
+
+    def randlu(self, A, k, p_over, pw, Omega=None, seed=0, sync_info=True):
+        """RandLU (Alg. 3 with the Alg. 4 power iteration, exponent pw):
+        2 pw + 2 passes over A; Omega is n x (k + p_over)."""
+        t = self._torch
+        _check_mat(Omega, "Omega")
+        lay, lda = _layout_of(A)
+        m, n = A.shape
+        dev = A.device
+        p = t.empty(m, dtype=t.int32, device=dev)
+        q = t.empty(n, dtype=t.int32, device=dev)
+        L = t.empty((m, k), dtype=t.float32, device=dev)
+        U = t.empty((k, n), dtype=t.float32, device=dev)
+        info = PluInfo()
+        rc = _lib().plu_randlu(self._h, lay, m, n, _ptr(A), lda, k, p_over, pw, _ptr(Omega), seed,
+                               _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
+                               ctypes.byref(info) if sync_info else None)
+        self._rc(rc, "plu_randlu", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
 
     def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,

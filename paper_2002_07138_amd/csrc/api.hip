@@ -1972,6 +1972,93 @@ int plu_single_pass(plu_handle h, int32_t layout, int64_t m, int64_t n, const fl
   return finish_info(h, w, PLU_OK, k, 1, k, false, info);
 }
 
+int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
+               int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
+               int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+               plu_info* info) {
+  if (!h) return -1;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
+  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (k < 1 || k > 128) return -7;
+  if (p_over < 0) return -8;
+  const int64_t l = (int64_t)k + p_over;
+  if (l >= std::min(m, n)) return -8;
+  if (pw < 0) return -9;
+  if (!p) return -12;
+  if (!q) return -13;
+  if (!L) return -14;
+  if (ldl < k) return -15;
+  if (!U) return -16;
+  if (ldu < n) return -17;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  Ws w;
+  int st = ensure_ws(h, m, n, l, &w);
+  if (st) return st;
+  w.acol = layout == PLU_COL_MAJOR;
+  trace_reset(h);
+  hipStream_t s = h->stream;
+  const int64_t lp = w.lp;
+  const GetrfWork g0 = getrf_work(h, w, 0);
+  const GetrfWork g1 = getrf_work(h, w, 1);
+  const GetrfWork g2 = getrf_work(h, w, 2);
+  // Alg. 4 (in place of Alg. 3 steps 1-3): Omega (n x l)
+  if (Omega) PLU_TRY_HIP(launch_copy_pad(Omega, l, w.om, lp, n, l, l, s));
+  else PLU_TRY_HIP(launch_gaussian(w.om, lp, n, l, seed, s));
+  // Y = A Omega (the first pass also yields ||A||_F^2)
+  PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, w.om, lp, (int)l, w.ym, lp, w.scal + 0, nullptr,
+                       nullptr));
+  int np = 1;
+  for (int i = 1; i <= pw; ++i) {
+    // L = P^T L of the previous product, then L = P^T L of lu(A^T L)
+    PLU_TRY_HIP(getrf_run(w.ym, lp, m, (int)l, g0, nullptr, nullptr, 0, 0, s));
+    PLU_TRY_HIP(trace_getrf(h, g0, (int)l));
+    PLU_TRY_HIP(run_pass(h, w, 1, m, n, A, lda, w.ym, lp, (int)l, w.zn, lp, nullptr, nullptr,
+                         nullptr));
+    PLU_TRY_HIP(getrf_run(w.zn, lp, n, (int)l, g0, nullptr, nullptr, 0, 0, s));
+    PLU_TRY_HIP(trace_getrf(h, g0, (int)l));
+    PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, w.zn, lp, (int)l, w.ym, lp, nullptr, nullptr,
+                         nullptr));
+    np += 2;
+  }
+  // [L_y, U_y, P] = lu(Y): w.ym <- P^T L_y (A's row order), p <- P's order
+  PLU_TRY_HIP(getrf_run(w.ym, lp, m, (int)l, g1, p, nullptr, 0, 0, s));
+  PLU_TRY_HIP(trace_getrf(h, g1, (int)l));
+  // Alg. 3 steps 4-5 with V = P^T L_y(:, :k): B = (V^T V)^{-1} V^T A, as
+  // B^T = C R^{-1} R^{-T} with C = A^T V (the last pass) and V^T V = R^T R
+  PLU_TRY_HIP(run_pass(h, w, 1, m, n, A, lda, w.ym, lp, k, w.zn, lp, nullptr, nullptr, nullptr));
+  ++np;
+  const QrWork qw = qr_work(w, w.qb, lp);
+  PLU_TRY_HIP(gram_inverse_run(w.ym, lp, m, k, qw, s));
+  {
+    GemmArgs g;
+    g.A = w.zn; g.lda = lp; g.X = w.rinv; g.ldx = kQB; g.out = w.bt; g.ldo = lp;
+    g.P = n; g.R = k; g.C = k;
+    PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, plan_gemm(n, k, k, 1, 1), s));
+  }
+  PLU_TRY_HIP(launch_iota(w.pos, k, s));
+  PLU_TRY_HIP(launch_transpose_gather(w.rinv, kQB, w.pos, k, k, w.ut1, lp, s));   // R^{-T}
+  {
+    GemmArgs g;
+    g.A = w.bt; g.lda = lp; g.X = w.ut1; g.ldx = lp; g.out = w.zn; g.ldo = lp;
+    g.P = n; g.R = k; g.C = k;
+    PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, plan_gemm(n, k, k, 1, 1), s));
+  }
+  // steps 6-8: [L2, U2, Q] = lu(B^T), L = L_y U2^T, U = L2^T
+  PLU_TRY_HIP(getrf_run(w.zn, lp, n, k, g2, q, w.ut2, lp, 1, s));
+  PLU_TRY_HIP(trace_getrf(h, g2, k));
+  {
+    GemmArgs g;
+    g.A = w.ym; g.lda = lp; g.arow = p; g.X = w.ut2; g.ldx = lp; g.out = L; g.ldo = ldl;
+    g.P = m; g.R = k; g.C = k;
+    PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, plan_gemm(m, k, k, 1, 1), s));
+  }
+  PLU_TRY_HIP(launch_transpose_gather(w.zn, lp, q, n, k, U, ldu, s));
+  return finish_info(h, w, PLU_OK, k, np, (int)l, false, info);
+}
+
 int plu_rank_rule(plu_handle h, int64_t m, int32_t l, const float* G, int64_t ldg, double normA2,
                   double eps, int32_t b, int32_t column_exact, int32_t* k_out, double* E_out,
                   double* colnorm2) {

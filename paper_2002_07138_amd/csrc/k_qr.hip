@@ -608,4 +608,11 @@ hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork&
   return hipSuccess;
 }
 
+hipError_t gram_inverse_run(const float* X, int64_t ldx, int64_t M, int c, const QrWork& qw,
+                            hipStream_t s) {
+  if (c < 1 || c > QB || M < c) return hipErrorInvalidValue;
+  // the Cholesky factor's diagonal test (qw.status[4]) is not used here
+  return cholqr_probe(X, ldx, M, c, qw, s);
+}
+
 }  // namespace plu

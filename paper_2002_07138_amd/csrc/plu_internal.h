@@ -139,6 +139,11 @@ struct QrWork {
 };
 hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw,
                        const QrWork& qw, hipStream_t s);
+// (X^T X)^{-1} = R^{-1} R^{-T} for an M x c X, c <= 128: the float64 Gram
+// and its Cholesky factor X^T X = R^T R; R^{-1} (upper triangular, float32,
+// leading dimension 128) is left in qw.rinv.
+hipError_t gram_inverse_run(const float* X, int64_t ldx, int64_t M, int c, const QrWork& qw,
+                            hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Misc kernels.
