@@ -117,8 +117,10 @@ def _time_calls(fn, reps):
 def baselines_section(h, A, k, p_over, reps=3):
     """The paper's fixed-rank timing comparison (Sec. 6.1, Fig. 1) at the
     workload shape: PowerLU at v = 2p + 2 against RandLU (Alg. 3 + Alg. 4)
-    at power exponent p -- the same 2p + 2 passes over A -- for p = 0 and 1;
-    milliseconds per call and relative residuals (plu_residual)."""
+    and RandSVD (Alg. 1 + Alg. 2) at power exponent p -- the same 2p + 2
+    passes over A -- for p = 0 and 1; milliseconds per call and relative
+    residuals (plu_residual for the LU forms; the RandSVD residual is
+    sqrt(1 - sum s_i^2 / ||A||_F^2), exact for its orthonormal factors)."""
     out = {}
     for pw in (0, 1):
         v = 2 * pw + 2
@@ -126,11 +128,19 @@ def baselines_section(h, A, k, p_over, reps=3):
             lambda sync: h.fixed_rank(A, k, p_over, v, seed=71, sync_info=sync), reps)
         t_rl, f_rl = _time_calls(
             lambda sync: h.randlu(A, k, p_over, pw, seed=71, sync_info=sync), reps)
+        t_sv, f_sv = _time_calls(
+            lambda sync: h.randsvd(A, k, p_over, pw, seed=71, sync_info=sync), reps)
+        s_sv = f_sv[1].double()
+        nA2 = f_sv[3]["normA2"]
+        r_sv = float(max(0.0, 1.0 - float((s_sv * s_sv).sum()) / nA2)) ** 0.5
         out[f"p{pw}"] = {
             "passes": v,
             "powerlu_ms": round(t_pl, 3), "randlu_ms": round(t_rl, 3),
+            "randsvd_ms": round(t_sv, 3),
             "speedup_powerlu_over_randlu": round(t_rl / t_pl, 3),
+            "speedup_powerlu_over_randsvd": round(t_sv / t_pl, 3),
             "residual_powerlu": h.residual(A, f_pl), "residual_randlu": h.residual(A, f_rl),
+            "residual_randsvd": r_sv,
         }
     out["paper_cpu_speedup_powerlu_over_randlu"] = {"p0": 1.80, "p1": 1.44}
     return out

@@ -196,6 +196,25 @@ int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* 
                int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
                plu_info* info);
 
+/* ---- RandSVD (Alg. 1 with the QR power iteration of Alg. 2, Sec. 2): the
+ * other comparison algorithm.  Q = qr(A Omega), then pw times Q = qr(A^T Q),
+ * Q = qr(A Q); B = Q^T A (l x n); B = U_hat S V^T; U = Q U_hat.  The SVD of
+ * B is taken as B^T = Q_b R (thin QR) and R = U_r S V_r^T by one-sided
+ * Jacobi in one workgroup (U_hat = V_r, V = Q_b U_r).  The k leading
+ * singular triplets are returned.  2 pw + 2 passes over A.
+ *   k, p_over  l = k + p_over <= 128, l < min(m, n).
+ *   pw         power exponent p >= 0 of Alg. 1 / Alg. 2.
+ *   Omega      device, nullable: n x l (leading dimension l).
+ *   U          device m x k (ldu >= k), orthonormal columns.
+ *   S          device k float32, non-increasing.
+ *   V          device n x k (ldv >= k), orthonormal columns.
+ *   info       as for plu_fixed_rank (rank = k; no pivot fields).
+ * Errors: -(argument index) for invalid arguments; PLU_ERR_OOM, PLU_ERR_HIP,
+ * PLU_ERR_TIMEOUT.                                                          */
+int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
+                int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
+                float* U, int64_t ldu, float* S, float* V, int64_t ldv, plu_info* info);
+
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
  *   all matrix/vector pointers device; rel_resid host; layout of A as in

@@ -36,7 +36,7 @@ _ENTRY_POINTS = [
     "plu_fixed_rank", "plu_fixed_precision", "plu_residual", "plu_gaussian", "plu_pass",
     "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule", "plu_quantize",
     "plu_batched", "plu_set_pivot_trace", "plu_pivot_trace", "plu_single_pass",
-    "plu_randlu", "plu_server_create",
+    "plu_randlu", "plu_randsvd", "plu_server_create",
     "plu_server_submit", "plu_server_poll",
     "plu_server_wait", "plu_server_destroy",
 ]
@@ -130,6 +130,8 @@ def _lib():
                                 pinfo],
             "plu_randlu": [vp, i32, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, vp, vp, i64, vp,
                            i64, pinfo],
+            "plu_randsvd": [vp, i32, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, i64, vp, vp,
+                            i64, pinfo],
             "plu_pivot_trace": [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32,
                                 ctypes.POINTER(i32)],
             "plu_server_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, i32],
@@ -385,6 +387,24 @@ class Handle:
                                ctypes.byref(info) if sync_info else None)
         self._rc(rc, "plu_randlu", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
+
+    def randsvd(self, A, k, p_over, pw, Omega=None, seed=0, sync_info=True):
+        """RandSVD (Alg. 1 with the Alg. 2 power iteration, exponent pw):
+        returns (U m x k, S (k,), V n x k, info); 2 pw + 2 passes over A."""
+        t = self._torch
+        _check_mat(Omega, "Omega")
+        lay, lda = _layout_of(A)
+        m, n = A.shape
+        dev = A.device
+        U = t.empty((m, k), dtype=t.float32, device=dev)
+        S = t.empty(k, dtype=t.float32, device=dev)
+        V = t.empty((n, k), dtype=t.float32, device=dev)
+        info = PluInfo()
+        rc = _lib().plu_randsvd(self._h, lay, m, n, _ptr(A), lda, k, p_over, pw, _ptr(Omega), seed,
+                                _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V),
+                                ctypes.byref(info) if sync_info else None)
+        self._rc(rc, "plu_randsvd")
+        return U, S, V, (info.as_dict() if sync_info else {})
 
     def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,
                         prec=PREC_FP32, max_rounds=1):

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpowerlu.so")
-SOURCES = ["k_gemm.hip", "k_getrf.hip", "k_qr.hip", "k_misc.hip", "k_lowp.hip", "batch.hip", "api.hip"]
+SOURCES = ["k_gemm.hip", "k_getrf.hip", "k_qr.hip", "k_misc.hip", "k_lowp.hip", "k_svd.hip",
+           "batch.hip", "api.hip"]
 ARCH = os.environ.get("PLU_OFFLOAD_ARCH", "gfx950")
 
 CXXFLAGS = [

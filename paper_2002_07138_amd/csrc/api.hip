@@ -2059,6 +2059,79 @@ int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* 
   return finish_info(h, w, PLU_OK, k, np, (int)l, false, info);
 }
 
+int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
+                int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
+                float* Uo, int64_t ldu, float* S, float* Vo, int64_t ldv, plu_info* info) {
+  if (!h) return -1;
+  if (!valid_layout(layout)) return -2;
+  if (m <= 0) return -3;
+  if (n <= 0) return -4;
+  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
+  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (k < 1) return -7;
+  if (p_over < 0) return -8;
+  const int64_t l = (int64_t)k + p_over;
+  if (l > 128 || l >= std::min(m, n)) return -8;
+  if (pw < 0) return -9;
+  if (!Uo) return -12;
+  if (ldu < k) return -13;
+  if (!S) return -14;
+  if (!Vo) return -15;
+  if (ldv < k) return -16;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  Ws w;
+  int st = ensure_ws(h, m, n, l, &w);
+  if (st) return st;
+  w.acol = layout == PLU_COL_MAJOR;
+  trace_reset(h);
+  hipStream_t s = h->stream;
+  const int64_t lp = w.lp;
+  const int c = (int)l;
+  const GetrfWork gw = getrf_work(h, w, 0);
+  const QrWork qw = qr_work(w, w.qb, lp);     // Q of Alg. 2 in w.qb
+  const QrWork qwb = qr_work(w, w.bt, lp);    // Q_b of B^T in w.bt
+  // Alg. 2: Q = qr(A Omega); p times Q = qr(A^T Q), Q = qr(A Q)
+  if (Omega) PLU_TRY_HIP(launch_copy_pad(Omega, l, w.om, lp, n, l, l, s));
+  else PLU_TRY_HIP(launch_gaussian(w.om, lp, n, l, seed, s));
+  PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, w.om, lp, c, w.ym, lp, w.scal + 0, nullptr,
+                       nullptr));
+  PLU_TRY_HIP(thin_qr_run(w.ym, lp, m, c, gw, qw, s));
+  int np = 1;
+  for (int i = 1; i <= pw; ++i) {
+    PLU_TRY_HIP(run_pass(h, w, 1, m, n, A, lda, w.qb, lp, c, w.zn, lp, nullptr, nullptr,
+                         nullptr));
+    PLU_TRY_HIP(thin_qr_run(w.zn, lp, n, c, gw, qw, s));
+    PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, w.qb, lp, c, w.ym, lp, nullptr, nullptr,
+                         nullptr));
+    PLU_TRY_HIP(thin_qr_run(w.ym, lp, m, c, gw, qw, s));
+    np += 2;
+  }
+  // Alg. 1 steps 4-6: B^T = A^T Q (n x l); B^T = Q_b R (thin QR, R = Q_b^T B^T);
+  // R = U_r S V_r^T (Jacobi); U = Q V_r, V = Q_b U_r, the k leading columns
+  PLU_TRY_HIP(run_pass(h, w, 1, m, n, A, lda, w.qb, lp, c, w.zn, lp, nullptr, nullptr, nullptr));
+  ++np;
+  PLU_TRY_HIP(hipMemcpy2DAsync(w.om, lp * sizeof(float), w.zn, lp * sizeof(float),
+                               c * sizeof(float), n, hipMemcpyDeviceToDevice, s));
+  PLU_TRY_HIP(thin_qr_run(w.zn, lp, n, c, gw, qwb, s));
+  PLU_TRY_HIP(small_tn(h, w, w.bt, lp, w.om, lp, c, n, c, w.ut1, lp));
+  PLU_TRY_HIP(launch_jacobi_svd(w.ut1, lp, c, w.ut2, lp, w.wproj, kQB, S, k, w.iscal + 2, s));
+  {
+    GemmArgs g;
+    g.A = w.qb; g.lda = lp; g.X = w.wproj; g.ldx = kQB; g.out = Uo; g.ldo = ldu;
+    g.P = m; g.R = c; g.C = k;
+    PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, plan_gemm(m, c, k, 1, 1), s));
+  }
+  {
+    GemmArgs g;
+    g.A = w.bt; g.lda = lp; g.X = w.ut2; g.ldx = lp; g.out = Vo; g.ldo = ldv;
+    g.P = n; g.R = c; g.C = k;
+    PLU_TRY_HIP(launch_gemm(0, EPI_STORE, 0, g, plan_gemm(n, c, k, 1, 1), s));
+  }
+  const int rs = finish_info(h, w, PLU_OK, 0, np, c, false, info);
+  if (info) info->rank = k;
+  return rs;
+}
+
 int plu_rank_rule(plu_handle h, int64_t m, int32_t l, const float* G, int64_t ldg, double normA2,
                   double eps, int32_t b, int32_t column_exact, int32_t* k_out, double* E_out,
                   double* colnorm2) {

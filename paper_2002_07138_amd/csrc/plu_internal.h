@@ -162,6 +162,12 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 // p[r][c] = -p[r][c] over a rows x cols block (leading dimension ld)
 hipError_t launch_negate(float* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
+// R = U_r diag(S) V_r^T for a square l x l R, l <= 128 (one-sided Jacobi in
+// one workgroup): Ur, Vr l x l with columns in non-increasing order of the
+// singular values, the kout largest of which go to S; sweeps_out nullable.
+hipError_t launch_jacobi_svd(const float* R, int64_t ldr, int l, float* Ur, int64_t ldur,
+                             float* Vr, int64_t ldvr, float* S, int kout, int32_t* sweeps_out,
+                             hipStream_t s);
 // X = (R^{-1})^T for an upper triangular k x k R, k <= 128 (one workgroup)
 hipError_t launch_tri_inv_t(const float* R, int64_t ldr, float* X, int64_t ldx, int k,
                             hipStream_t s);
