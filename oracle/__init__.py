@@ -19,6 +19,8 @@ lowp      bfloat16 and block-scaled FP8 E4M3 operand rounding for the
           precision form of the passes.
 philox    Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
           Box-Muller transform, for the seeded Gaussian test matrix.
+baselines RandLU (Alg. 3 with Alg. 4) and RandSVD (Alg. 1 with Alg. 2), the
+          paper's fixed-rank comparison algorithms.
 
 Every function states the passage it follows.  Parity status of each function
 is listed in the module docstrings; none is "parity unpinned" except where a
