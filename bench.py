@@ -146,6 +146,55 @@ def baselines_section(h, A, k, p_over, reps=3):
     return out
 
 
+def sparse_section(h, n=20000, density=0.003, k=100, p_over=10, reps=3):
+    """The paper's sparse experiment (Sec. 6.1, Fig. 2) at one size: a
+    sprand-like n x n matrix (uniform values, density 0.3%) in compressed
+    rows.  The SpMM passes (ms and the rate of X rows gathered), then
+    PowerLU at v = 2p + 2 against RandLU and RandSVD at p (2p + 2 passes),
+    p = 0 and 1, and PowerLU on the same matrix stored dense.  Residuals of
+    the LU forms by plu_residual on the dense copy; RandSVD's from its
+    singular values."""
+    import torch
+    from synth import sprand_csr
+    ip, ix, d = sprand_csr(n, n, density, 4242)
+    dev = torch.device("cuda", 0)
+    rp, ci, vv = (torch.from_numpy(x).to(dev) for x in (ip, ix, d))
+    S = h.sparse_matrix(rp, ci, vv, (n, n))
+    nnz = int(d.size)
+    l = k + p_over
+    X = torch.randn(n, l, device=dev)
+    res = {"n": n, "density": density, "nnz": nnz, "k": k, "p_over": p_over}
+    for name, trans in (("spmm_N_ms", False), ("spmm_T_ms", True)):
+        t, _ = _time_calls(lambda sync: h.sparse_pass(S, X, trans=trans), 10)
+        res[name] = round(t, 4)
+        res[name.replace("_ms", "_gather_GBps")] = round(nnz * l * 4 / (t * 1e-3) / 1e9, 1)
+    Ad = torch.sparse_csr_tensor(rp, ci, vv, size=(n, n)).to_dense()
+    nA2 = float((Ad.double() ** 2).sum())
+    for pw in (0, 1):
+        v = 2 * pw + 2
+        t_pl, f_pl = _time_calls(
+            lambda sync: h.fixed_rank(S, k, p_over, v, seed=81, sync_info=sync), reps)
+        t_rl, f_rl = _time_calls(
+            lambda sync: h.randlu(S, k, p_over, pw, seed=81, sync_info=sync), reps)
+        t_sv, f_sv = _time_calls(
+            lambda sync: h.randsvd(S, k, p_over, pw, seed=81, sync_info=sync), reps)
+        t_dn, f_dn = _time_calls(
+            lambda sync: h.fixed_rank(Ad, k, p_over, v, seed=81, sync_info=sync), reps)
+        s_sv = f_sv[1].double()
+        res[f"p{pw}"] = {
+            "passes": v,
+            "powerlu_ms": round(t_pl, 3), "randlu_ms": round(t_rl, 3),
+            "randsvd_ms": round(t_sv, 3), "powerlu_dense_storage_ms": round(t_dn, 3),
+            "residual_powerlu": h.residual(Ad, f_pl), "residual_randlu": h.residual(Ad, f_rl),
+            "residual_randsvd": float(max(0.0, 1.0 - float((s_sv * s_sv).sum()) / nA2)) ** 0.5,
+            "residual_powerlu_dense_storage": h.residual(Ad, f_dn),
+        }
+    del Ad
+    S.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
     """The precision form (rounded passes, fp32 refinement pass) on the same
     workload and seeds as the fp32 step; residuals against the fp32 path's."""
@@ -625,6 +674,7 @@ def main():
         result["single_pass"] = single
     if not args.no_baselines:
         result["baselines"] = baselines_section(h, A, k, p_over)
+        result["sparse"] = sparse_section(h)
 
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()

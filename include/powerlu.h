@@ -215,6 +215,55 @@ int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float*
                 int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
                 float* U, int64_t ldu, float* S, float* V, int64_t ldv, plu_info* info);
 
+/* ---- Sparse A (the sprand inputs of Sec. 6.1's second experiment).  A
+ * matrix in compressed rows is bound to the handle's device once; the
+ * drivers then run their passes A X and A^T Y as row-parallel gathers over
+ * the compressed rows and over compressed columns built on the device (with
+ * each column's entries in ascending row order, so results do not depend on
+ * scheduling).  The rest of every algorithm (LU, QR, assembly, indicator) is
+ * the dense path's.
+ *   plu_sparse_create: m, n in [1, 2^31); nnz >= 0 stored entries;
+ *     rowptr device int64 (m + 1), rowptr[0] = 0, non-decreasing,
+ *     rowptr[m] = nnz; colidx device int32 (nnz), each in [0, n); vals
+ *     device float32 (nnz).  Entries need not be sorted within a row;
+ *     repeated (i, j) entries act as their sum (in an unspecified order).
+ *     The arrays are borrowed: they must stay valid and unchanged until
+ *     plu_sparse_destroy.  The object owns about 8 (n + nnz) more bytes of
+ *     device memory (compressed columns, ||A||_F^2).  The structure is
+ *     checked on the device first; a violation returns -5 (rowptr) or -6
+ *     (colidx) and no object.  Synchronizes the handle's stream.
+ *   plu_sparse_destroy: waits for the device, frees the object (NULL is a
+ *     no-op).
+ *   plu_sparse_pass: out = A X (trans 0; X n x l, out m x l) or A^T X
+ *     (trans 1; X m x l, out n x l), row-major, float32, on the handle's
+ *     stream.
+ *   plu_sparse_fixed_rank, plu_sparse_fixed_precision, plu_sparse_randlu,
+ *   plu_sparse_randsvd: as plu_fixed_rank, plu_fixed_precision, plu_randlu
+ *     and plu_randsvd with (layout, m, n, A, lda) replaced by sp; m and n
+ *     are the matrix's; prec must be PLU_PREC_FP32.  Argument errors are
+ *     -(index in this signature): the dense index minus 4 for every argument
+ *     after sp.                                                            */
+typedef struct plu_sparse_s* plu_sparse;
+int plu_sparse_create(plu_handle h, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                      const int32_t* colidx, const float* vals, plu_sparse* out);
+int plu_sparse_destroy(plu_sparse sp);
+int plu_sparse_pass(plu_handle h, plu_sparse sp, int32_t trans, const float* X, int64_t ldx,
+                    int32_t l, float* out, int64_t ldo);
+int plu_sparse_fixed_rank(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t v,
+                          int32_t prec, const float* Omega, uint64_t seed, int32_t* p, int32_t* q,
+                          float* L, int64_t ldl, float* U, int64_t ldu, plu_info* info);
+int plu_sparse_fixed_precision(plu_handle h, plu_sparse sp, double eps, int32_t b, int32_t l,
+                               int32_t v, int32_t column_exact, int32_t max_rounds, int32_t prec,
+                               const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                               int64_t ldl, float* U, int64_t ldu, int32_t* rank_out,
+                               plu_info* info);
+int plu_sparse_randlu(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t pw,
+                      const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                      int64_t ldl, float* U, int64_t ldu, plu_info* info);
+int plu_sparse_randsvd(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t pw,
+                       const float* Omega, uint64_t seed, float* U, int64_t ldu, float* S,
+                       float* V, int64_t ldv, plu_info* info);
+
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
  *   all matrix/vector pointers device; rel_resid host; layout of A as in

@@ -36,7 +36,9 @@ _ENTRY_POINTS = [
     "plu_fixed_rank", "plu_fixed_precision", "plu_residual", "plu_gaussian", "plu_pass",
     "plu_getrf", "plu_thin_qr", "plu_range_basis", "plu_rank_rule", "plu_quantize",
     "plu_batched", "plu_set_pivot_trace", "plu_pivot_trace", "plu_single_pass",
-    "plu_randlu", "plu_randsvd", "plu_server_create",
+    "plu_randlu", "plu_randsvd", "plu_sparse_create", "plu_sparse_destroy", "plu_sparse_pass",
+    "plu_sparse_fixed_rank", "plu_sparse_fixed_precision", "plu_sparse_randlu",
+    "plu_sparse_randsvd", "plu_server_create",
     "plu_server_submit", "plu_server_poll",
     "plu_server_wait", "plu_server_destroy",
 ]
@@ -132,6 +134,15 @@ def _lib():
                            i64, pinfo],
             "plu_randsvd": [vp, i32, i64, i64, vp, i64, i32, i32, i32, vp, u64, vp, i64, vp, vp,
                             i64, pinfo],
+            "plu_sparse_create": [vp, i64, i64, i64, vp, vp, vp, ctypes.POINTER(vp)],
+            "plu_sparse_destroy": [vp],
+            "plu_sparse_pass": [vp, vp, i32, vp, i64, i32, vp, i64],
+            "plu_sparse_fixed_rank": [vp, vp, i32, i32, i32, i32, vp, u64, vp, vp, vp, i64, vp, i64,
+                                      pinfo],
+            "plu_sparse_fixed_precision": [vp, vp, dbl, i32, i32, i32, i32, i32, i32, vp, u64, vp,
+                                           vp, vp, i64, vp, i64, ctypes.POINTER(i32), pinfo],
+            "plu_sparse_randlu": [vp, vp, i32, i32, i32, vp, u64, vp, vp, vp, i64, vp, i64, pinfo],
+            "plu_sparse_randsvd": [vp, vp, i32, i32, i32, vp, u64, vp, i64, vp, vp, i64, pinfo],
             "plu_pivot_trace": [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32,
                                 ctypes.POINTER(i32)],
             "plu_server_create": [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, i32],
@@ -201,6 +212,45 @@ class Factors:
     U: "object"
     rank: int
     info: dict
+
+
+class SparseMatrix:
+    """A sparse matrix in compressed rows bound to a handle's device
+    (plu_sparse_create).  rowptr (int64, m + 1), colidx (int32) and vals
+    (float32) are device tensors; they are kept referenced (the library
+    borrows them) until close()."""
+
+    def __init__(self, handle, rowptr, colidx, vals, shape):
+        t = handle._torch
+        m, n = (int(shape[0]), int(shape[1]))
+        for x, name, dt in ((rowptr, "rowptr", t.int64), (colidx, "colidx", t.int32),
+                            (vals, "vals", t.float32)):
+            if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == dt and x.dim() == 1
+                    and x.is_contiguous()):
+                raise TypeError(f"{name}: a contiguous 1-D {dt} device tensor is needed")
+        if rowptr.numel() != m + 1 or colidx.numel() != vals.numel():
+            raise ValueError("rowptr needs m + 1 entries and colidx, vals one per stored entry")
+        self.shape = (m, n)
+        self.nnz = int(vals.numel())
+        self.device = vals.device
+        self._keep = (rowptr, colidx, vals)
+        sp = ctypes.c_void_p()
+        rc = _lib().plu_sparse_create(handle._h, m, n, self.nnz, _ptr(rowptr), _ptr(colidx),
+                                      _ptr(vals), ctypes.byref(sp))
+        if rc != PLU_OK:
+            raise PowerLUError(rc, "plu_sparse_create")
+        self._sp = sp
+
+    def close(self):
+        if getattr(self, "_sp", None):
+            _lib().plu_sparse_destroy(self._sp)
+            self._sp = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Handle:
@@ -328,12 +378,32 @@ class Handle:
         self._rc(rc, "plu_rank_rule", ok=(PLU_OK, PLU_TOL_NOT_REACHED))
         return k.value, E.value, list(cn), rc == PLU_OK
 
+    # ------------------------------------------------------------- sparse A
+    def sparse_matrix(self, rowptr, colidx, vals, shape):
+        """Bind a device matrix in compressed rows (see SparseMatrix)."""
+        return SparseMatrix(self, rowptr, colidx, vals, shape)
+
+    def sparse_pass(self, S, X, trans=False, out=None):
+        """out = S X (trans False) or S^T X (trans True) for a SparseMatrix S."""
+        _check_mat(X, "X")
+        m, n = S.shape
+        rows = n if trans else m
+        l = X.shape[1]
+        if out is None:
+            out = self._torch.empty((rows, l), dtype=self._torch.float32, device=X.device)
+        rc = _lib().plu_sparse_pass(self._h, S._sp, 1 if trans else 0, _ptr(X), _ld(X), l,
+                                    _ptr(out), _ld(out))
+        self._rc(rc, "plu_sparse_pass")
+        return out
+
     # ------------------------------------------------------------- problems
     def fixed_rank(self, A, k, p_over, v, Omega=None, seed=0, prec=PREC_FP32, sync_info=True,
                    out=None):
+        """PowerLU (Alg. 5 with Alg. 7); A is a device tensor or a SparseMatrix."""
         t = self._torch
         _check_mat(Omega, "Omega")
-        lay, lda = _layout_of(A)
+        sparse = isinstance(A, SparseMatrix)
+        lay, lda = (0, 0) if sparse else _layout_of(A)
         m, n = A.shape
         dev = A.device
         if out is None:
@@ -344,9 +414,15 @@ class Handle:
         else:
             p, q, L, U = out
         info = PluInfo()
-        rc = _lib().plu_fixed_rank(self._h, lay, m, n, _ptr(A), lda, k, p_over, v, prec,
-                                   _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U),
-                                   _ld(U), ctypes.byref(info) if sync_info else None)
+        pinfo = ctypes.byref(info) if sync_info else None
+        if sparse:
+            rc = _lib().plu_sparse_fixed_rank(self._h, A._sp, k, p_over, v, prec, _ptr(Omega),
+                                              seed, _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U),
+                                              _ld(U), pinfo)
+        else:
+            rc = _lib().plu_fixed_rank(self._h, lay, m, n, _ptr(A), lda, k, p_over, v, prec,
+                                       _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L), _ld(L),
+                                       _ptr(U), _ld(U), pinfo)
         self._rc(rc, "plu_fixed_rank", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
 
@@ -374,7 +450,8 @@ class Handle:
         2 pw + 2 passes over A; Omega is n x (k + p_over)."""
         t = self._torch
         _check_mat(Omega, "Omega")
-        lay, lda = _layout_of(A)
+        sparse = isinstance(A, SparseMatrix)
+        lay, lda = (0, 0) if sparse else _layout_of(A)
         m, n = A.shape
         dev = A.device
         p = t.empty(m, dtype=t.int32, device=dev)
@@ -382,9 +459,15 @@ class Handle:
         L = t.empty((m, k), dtype=t.float32, device=dev)
         U = t.empty((k, n), dtype=t.float32, device=dev)
         info = PluInfo()
-        rc = _lib().plu_randlu(self._h, lay, m, n, _ptr(A), lda, k, p_over, pw, _ptr(Omega), seed,
-                               _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
-                               ctypes.byref(info) if sync_info else None)
+        pinfo = ctypes.byref(info) if sync_info else None
+        if sparse:
+            rc = _lib().plu_sparse_randlu(self._h, A._sp, k, p_over, pw, _ptr(Omega), seed,
+                                          _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
+                                          pinfo)
+        else:
+            rc = _lib().plu_randlu(self._h, lay, m, n, _ptr(A), lda, k, p_over, pw, _ptr(Omega),
+                                   seed, _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
+                                   pinfo)
         self._rc(rc, "plu_randlu", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
 
@@ -393,24 +476,31 @@ class Handle:
         returns (U m x k, S (k,), V n x k, info); 2 pw + 2 passes over A."""
         t = self._torch
         _check_mat(Omega, "Omega")
-        lay, lda = _layout_of(A)
+        sparse = isinstance(A, SparseMatrix)
+        lay, lda = (0, 0) if sparse else _layout_of(A)
         m, n = A.shape
         dev = A.device
         U = t.empty((m, k), dtype=t.float32, device=dev)
         S = t.empty(k, dtype=t.float32, device=dev)
         V = t.empty((n, k), dtype=t.float32, device=dev)
         info = PluInfo()
-        rc = _lib().plu_randsvd(self._h, lay, m, n, _ptr(A), lda, k, p_over, pw, _ptr(Omega), seed,
-                                _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V),
-                                ctypes.byref(info) if sync_info else None)
+        pinfo = ctypes.byref(info) if sync_info else None
+        if sparse:
+            rc = _lib().plu_sparse_randsvd(self._h, A._sp, k, p_over, pw, _ptr(Omega), seed,
+                                           _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V), pinfo)
+        else:
+            rc = _lib().plu_randsvd(self._h, lay, m, n, _ptr(A), lda, k, p_over, pw, _ptr(Omega),
+                                    seed, _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V), pinfo)
         self._rc(rc, "plu_randsvd")
         return U, S, V, (info.as_dict() if sync_info else {})
 
     def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,
                         prec=PREC_FP32, max_rounds=1):
+        """PowerLU_FP (Alg. 9); A is a device tensor or a SparseMatrix."""
         t = self._torch
         _check_mat(Omega, "Omega")
-        lay, lda = _layout_of(A)
+        sparse = isinstance(A, SparseMatrix)
+        lay, lda = (0, 0) if sparse else _layout_of(A)
         m, n = A.shape
         dev = A.device
         lcap = (l if l else min(50 * b, b * ((min(m, n) - 1) // b))) * max(int(max_rounds), 1)
@@ -420,11 +510,18 @@ class Handle:
         U = t.empty((lcap, n), dtype=t.float32, device=dev)
         k = ctypes.c_int32()
         info = PluInfo()
-        rc = _lib().plu_fixed_precision(self._h, lay, m, n, _ptr(A), lda, float(eps), b, l, v,
-                                        1 if column_exact else 0, int(max_rounds), prec,
-                                        _ptr(Omega), seed,
-                                        _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
-                                        ctypes.byref(k), ctypes.byref(info))
+        if sparse:
+            rc = _lib().plu_sparse_fixed_precision(self._h, A._sp, float(eps), b, l, v,
+                                                   1 if column_exact else 0, int(max_rounds), prec,
+                                                   _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L),
+                                                   _ld(L), _ptr(U), _ld(U), ctypes.byref(k),
+                                                   ctypes.byref(info))
+        else:
+            rc = _lib().plu_fixed_precision(self._h, lay, m, n, _ptr(A), lda, float(eps), b, l, v,
+                                            1 if column_exact else 0, int(max_rounds), prec,
+                                            _ptr(Omega), seed,
+                                            _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
+                                            ctypes.byref(k), ctypes.byref(info))
         self._rc(rc, "plu_fixed_precision", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT, PLU_TOL_NOT_REACHED))
         kk = k.value
         return Factors(p, q, L[:, :kk], U[:kk], kk, info.as_dict())

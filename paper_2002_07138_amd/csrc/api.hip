@@ -119,6 +119,8 @@ struct Ws {
   bool acol = false;
   // restarted fixed precision: the kept basis V (n x lp) and G = A V (m x lp)
   float *vall = nullptr, *gall = nullptr;
+  // sparse A: the passes run on its compressed rows / columns instead
+  const SparseMat* sp = nullptr;
 };
 
 int64_t part_need(int64_t m, int64_t n, int64_t l) {
@@ -424,6 +426,23 @@ hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0,
 hipError_t run_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, const float* A,
                     int64_t lda, const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo,
                     double* normA2_dev, double* colsq, int* colsq_blocks) {
+  if (w.sp) {   // sparse A: a gather over the compressed rows (A X) or columns (A^T Y)
+    const SparseMat& S = *w.sp;
+    const int64_t P = trans ? S.n : S.m;
+    hipError_t e = trans ? launch_spmm(S.colptr, S.rowidx, S.valsT, S.n, X, ldx, (int)l, out, ldo,
+                                       h->stream)
+                         : launch_spmm(S.rowptr, S.colidx, S.vals, S.m, X, ldx, (int)l, out, ldo,
+                                       h->stream);
+    if (e != hipSuccess) return e;
+    if (colsq && (e = launch_splitk_reduce(out, 0, 1, nullptr, ldo, P, l, colsq, 64, h->stream)) !=
+                     hipSuccess)
+      return e;
+    if (colsq_blocks) *colsq_blocks = (int)((P + 63) / 64);
+    if (normA2_dev)
+      return hipMemcpyAsync(normA2_dev, S.normA2, sizeof(double), hipMemcpyDeviceToDevice,
+                            h->stream);
+    return hipSuccess;
+  }
   if (w.acol) {   // the storage is A^T, row-major
     trans ^= 1;
     std::swap(m, n);
@@ -994,6 +1013,14 @@ size_t server_footprint(const plu_request& r, int64_t l, int64_t cap, size_t* ws
 }
 
 }  // namespace
+
+// A sparse matrix bound to a device: the caller's compressed rows and the
+// compressed columns and ||A||_F^2 built from them.
+struct plu_sparse_s {
+  int device = 0;
+  SparseMat mat;
+  void* mem = nullptr;
+};
 
 struct plu_server_s {
   plu_handle h = nullptr;
@@ -1759,33 +1786,36 @@ int plu_range_basis(plu_handle h, int32_t layout, int64_t m, int64_t n, const fl
   return PLU_OK;
 }
 
-int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
-                   int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
-                   const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
-                   int64_t ldl, float* U, int64_t ldu, plu_info* info) {
+static int fixed_rank_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                           int64_t lda, const SparseMat* sp, int off, int32_t k, int32_t p_over,
+                           int32_t v, int32_t prec, const float* Omega, uint64_t seed, int32_t* p,
+                           int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                           plu_info* info) {
   if (!h) return -1;
-  if (!valid_layout(layout)) return -2;
-  if (m <= 0) return -3;
-  if (n <= 0) return -4;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
-  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
-  if (k < 1) return -7;
-  if (p_over < 0) return -8;
+  if (!sp && !valid_layout(layout)) return -2;
+  if (!sp && m <= 0) return -3;
+  if (!sp && n <= 0) return -4;
+  if (!sp && (!A || (reinterpret_cast<uintptr_t>(A) & 3u))) return -5;
+  if (!sp && lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (k < 1) return -(7 - off);
+  if (p_over < 0) return -(8 - off);
   const int64_t l = (int64_t)k + p_over;
-  if (l >= std::min(m, n)) return -8;
-  if (v < 2) return -9;
-  if (!valid_prec(prec)) return -10;
-  if (!p) return -13;
-  if (!q) return -14;
-  if (!L) return -15;
-  if (ldl < k) return -16;
-  if (!U) return -17;
-  if (ldu < n) return -18;
+  if (l >= std::min(m, n)) return -(8 - off);
+  if (v < 2) return -(9 - off);
+  if (!valid_prec(prec)) return -(10 - off);
+  if (sp && prec != PLU_PREC_FP32) return -(10 - off);   // sparse passes are float32
+  if (!p) return -(13 - off);
+  if (!q) return -(14 - off);
+  if (!L) return -(15 - off);
+  if (ldl < k) return -(16 - off);
+  if (!U) return -(17 - off);
+  if (ldu < n) return -(18 - off);
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
   w.acol = layout == PLU_COL_MAJOR;
+  w.sp = sp;
   trace_reset(h);
   float* V = nullptr;
   int np = 0;
@@ -1797,37 +1827,48 @@ int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const flo
   return finish_info(h, w, PLU_OK, k, np, (int)l, false, info);
 }
 
-int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
-                        int64_t lda, double eps, int32_t b, int32_t l, int32_t v,
-                        int32_t column_exact, int32_t max_rounds, int32_t prec,
-                        const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
-                        int64_t ldl, float* U, int64_t ldu, int32_t* rank_out, plu_info* info) {
+int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                   int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
+                   const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                   int64_t ldl, float* U, int64_t ldu, plu_info* info) {
+  return fixed_rank_impl(h, layout, m, n, A, lda, nullptr, 0, k, p_over, v, prec, Omega, seed, p, q,
+                         L, ldl, U, ldu, info);
+}
+
+static int fixed_precision_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                                int64_t lda, const SparseMat* sp, int off, double eps, int32_t b,
+                                int32_t l, int32_t v, int32_t column_exact, int32_t max_rounds,
+                                int32_t prec, const float* Omega, uint64_t seed, int32_t* p,
+                                int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+                                int32_t* rank_out, plu_info* info) {
   if (!h) return -1;
-  if (!valid_layout(layout)) return -2;
-  if (m <= 0) return -3;
-  if (n <= 0) return -4;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
-  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
-  if (!(eps > 0.0)) return -7;
-  if (b < 1) return -8;
+  if (!sp && !valid_layout(layout)) return -2;
+  if (!sp && m <= 0) return -3;
+  if (!sp && n <= 0) return -4;
+  if (!sp && (!A || (reinterpret_cast<uintptr_t>(A) & 3u))) return -5;
+  if (!sp && lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (!(eps > 0.0)) return -(7 - off);
+  if (b < 1) return -(8 - off);
   const int64_t mn = std::min(m, n);
   if (l == 0) l = (int32_t)std::min<int64_t>(50LL * b, b * ((mn - 1) / b));
-  if (l <= 0 || l % b != 0 || l >= mn) return -9;
-  if (v < 2) return -10;
-  if (max_rounds < 1 || (int64_t)l * max_rounds >= mn) return -12;
-  if (!valid_prec(prec)) return -13;
-  if (!p) return -16;
-  if (!q) return -17;
-  if (!L) return -18;
-  if (ldl < (int64_t)l * max_rounds) return -19;
-  if (!U) return -20;
-  if (ldu < n) return -21;
+  if (l <= 0 || l % b != 0 || l >= mn) return -(9 - off);
+  if (v < 2) return -(10 - off);
+  if (max_rounds < 1 || (int64_t)l * max_rounds >= mn) return -(12 - off);
+  if (!valid_prec(prec)) return -(13 - off);
+  if (sp && prec != PLU_PREC_FP32) return -(13 - off);   // sparse passes are float32
+  if (!p) return -(16 - off);
+  if (!q) return -(17 - off);
+  if (!L) return -(18 - off);
+  if (ldl < (int64_t)l * max_rounds) return -(19 - off);
+  if (!U) return -(20 - off);
+  if (ldu < n) return -(21 - off);
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   if (max_rounds > 1) {
     int st = ensure_ws(h, m, n, (int64_t)l * max_rounds, &w, prec, true);
     if (st) return st;
     w.acol = layout == PLU_COL_MAJOR;
+    w.sp = sp;
     trace_reset(h);
     return fixed_precision_rounds(h, w, m, n, A, lda, eps, b, l, v, column_exact, max_rounds, prec,
                                   Omega, seed, p, q, L, ldl, U, ldu, rank_out, info);
@@ -1835,6 +1876,7 @@ int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, cons
   int st = ensure_ws(h, m, n, l, &w, prec);
   if (st) return st;
   w.acol = layout == PLU_COL_MAJOR;
+  w.sp = sp;
   trace_reset(h);
   float* V = nullptr;
   int np = 0;
@@ -1876,6 +1918,15 @@ int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, cons
   int rs = finish_info(h, w, status, k, np, l, true, info);
   if (info) info->tol_reached = tol_ok ? 1 : 0;
   return info ? rs : status;
+}
+
+int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                        int64_t lda, double eps, int32_t b, int32_t l, int32_t v,
+                        int32_t column_exact, int32_t max_rounds, int32_t prec,
+                        const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                        int64_t ldl, float* U, int64_t ldu, int32_t* rank_out, plu_info* info) {
+  return fixed_precision_impl(h, layout, m, n, A, lda, nullptr, 0, eps, b, l, v, column_exact,
+                              max_rounds, prec, Omega, seed, p, q, L, ldl, U, ldu, rank_out, info);
 }
 
 int plu_single_pass(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
@@ -1972,32 +2023,33 @@ int plu_single_pass(plu_handle h, int32_t layout, int64_t m, int64_t n, const fl
   return finish_info(h, w, PLU_OK, k, 1, k, false, info);
 }
 
-int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
-               int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
-               int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
-               plu_info* info) {
+static int randlu_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                       int64_t lda, const SparseMat* sp, int off, int32_t k, int32_t p_over,
+                       int32_t pw, const float* Omega, uint64_t seed, int32_t* p, int32_t* q,
+                       float* L, int64_t ldl, float* U, int64_t ldu, plu_info* info) {
   if (!h) return -1;
-  if (!valid_layout(layout)) return -2;
-  if (m <= 0) return -3;
-  if (n <= 0) return -4;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
-  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
-  if (k < 1 || k > 128) return -7;
-  if (p_over < 0) return -8;
+  if (!sp && !valid_layout(layout)) return -2;
+  if (!sp && m <= 0) return -3;
+  if (!sp && n <= 0) return -4;
+  if (!sp && (!A || (reinterpret_cast<uintptr_t>(A) & 3u))) return -5;
+  if (!sp && lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (k < 1 || k > 128) return -(7 - off);
+  if (p_over < 0) return -(8 - off);
   const int64_t l = (int64_t)k + p_over;
-  if (l >= std::min(m, n)) return -8;
-  if (pw < 0) return -9;
-  if (!p) return -12;
-  if (!q) return -13;
-  if (!L) return -14;
-  if (ldl < k) return -15;
-  if (!U) return -16;
-  if (ldu < n) return -17;
+  if (l >= std::min(m, n)) return -(8 - off);
+  if (pw < 0) return -(9 - off);
+  if (!p) return -(12 - off);
+  if (!q) return -(13 - off);
+  if (!L) return -(14 - off);
+  if (ldl < k) return -(15 - off);
+  if (!U) return -(16 - off);
+  if (ldu < n) return -(17 - off);
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   int st = ensure_ws(h, m, n, l, &w);
   if (st) return st;
   w.acol = layout == PLU_COL_MAJOR;
+  w.sp = sp;
   trace_reset(h);
   hipStream_t s = h->stream;
   const int64_t lp = w.lp;
@@ -2059,30 +2111,40 @@ int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* 
   return finish_info(h, w, PLU_OK, k, np, (int)l, false, info);
 }
 
-int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
-                int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
-                float* Uo, int64_t ldu, float* S, float* Vo, int64_t ldv, plu_info* info) {
+int plu_randlu(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
+               int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
+               int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
+               plu_info* info) {
+  return randlu_impl(h, layout, m, n, A, lda, nullptr, 0, k, p_over, pw, Omega, seed, p, q, L, ldl,
+                     U, ldu, info);
+}
+
+static int randsvd_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                        int64_t lda, const SparseMat* sp, int off, int32_t k, int32_t p_over,
+                        int32_t pw, const float* Omega, uint64_t seed, float* Uo, int64_t ldu,
+                        float* S, float* Vo, int64_t ldv, plu_info* info) {
   if (!h) return -1;
-  if (!valid_layout(layout)) return -2;
-  if (m <= 0) return -3;
-  if (n <= 0) return -4;
-  if (!A || (reinterpret_cast<uintptr_t>(A) & 3u)) return -5;
-  if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
-  if (k < 1) return -7;
-  if (p_over < 0) return -8;
+  if (!sp && !valid_layout(layout)) return -2;
+  if (!sp && m <= 0) return -3;
+  if (!sp && n <= 0) return -4;
+  if (!sp && (!A || (reinterpret_cast<uintptr_t>(A) & 3u))) return -5;
+  if (!sp && lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
+  if (k < 1) return -(7 - off);
+  if (p_over < 0) return -(8 - off);
   const int64_t l = (int64_t)k + p_over;
-  if (l > 128 || l >= std::min(m, n)) return -8;
-  if (pw < 0) return -9;
-  if (!Uo) return -12;
-  if (ldu < k) return -13;
-  if (!S) return -14;
-  if (!Vo) return -15;
-  if (ldv < k) return -16;
+  if (l > 128 || l >= std::min(m, n)) return -(8 - off);
+  if (pw < 0) return -(9 - off);
+  if (!Uo) return -(12 - off);
+  if (ldu < k) return -(13 - off);
+  if (!S) return -(14 - off);
+  if (!Vo) return -(15 - off);
+  if (ldv < k) return -(16 - off);
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
   int st = ensure_ws(h, m, n, l, &w);
   if (st) return st;
   w.acol = layout == PLU_COL_MAJOR;
+  w.sp = sp;
   trace_reset(h);
   hipStream_t s = h->stream;
   const int64_t lp = w.lp;
@@ -2130,6 +2192,123 @@ int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float*
   const int rs = finish_info(h, w, PLU_OK, 0, np, c, false, info);
   if (info) info->rank = k;
   return rs;
+}
+
+int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A, int64_t lda,
+                int32_t k, int32_t p_over, int32_t pw, const float* Omega, uint64_t seed,
+                float* Uo, int64_t ldu, float* S, float* Vo, int64_t ldv, plu_info* info) {
+  return randsvd_impl(h, layout, m, n, A, lda, nullptr, 0, k, p_over, pw, Omega, seed, Uo, ldu, S,
+                      Vo, ldv, info);
+}
+
+int plu_sparse_create(plu_handle h, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                      const int32_t* colidx, const float* vals, plu_sparse* out) {
+  if (!h) return -1;
+  if (m <= 0 || m > INT32_MAX) return -2;
+  if (n <= 0 || n > INT32_MAX) return -3;
+  if (nnz < 0) return -4;
+  if (!rowptr || (reinterpret_cast<uintptr_t>(rowptr) & 7u)) return -5;
+  if (nnz > 0 && (!colidx || (reinterpret_cast<uintptr_t>(colidx) & 3u))) return -6;
+  if (nnz > 0 && (!vals || (reinterpret_cast<uintptr_t>(vals) & 3u))) return -7;
+  if (!out) return -8;
+  *out = nullptr;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  plu_sparse sp = new (std::nothrow) plu_sparse_s;
+  if (!sp) return PLU_ERR_OOM;
+  sp->device = h->device;
+  sp->mat.m = m;
+  sp->mat.n = n;
+  sp->mat.nnz = nnz;
+  sp->mat.rowptr = rowptr;
+  sp->mat.colidx = colidx;
+  sp->mat.vals = vals;
+  if (hipMalloc(&sp->mem, sparse_scratch_bytes(m, n, nnz) + 4096) != hipSuccess) {
+    hipGetLastError();
+    delete sp;
+    return PLU_ERR_OOM;
+  }
+  int32_t bad = 0;
+  if (sparse_build(sp->mat, sp->mem, &bad, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    hipFree(sp->mem);
+    delete sp;
+    return PLU_ERR_HIP;
+  }
+  if (bad) {   // malformed compressed rows: the offending argument's index
+    hipFree(sp->mem);
+    delete sp;
+    return (bad & 1) ? -5 : -6;
+  }
+  *out = sp;
+  return PLU_OK;
+}
+
+int plu_sparse_destroy(plu_sparse sp) {
+  if (!sp) return PLU_OK;
+  if (hipSetDevice(sp->device) == hipSuccess) {
+    hipDeviceSynchronize();
+    hipFree(sp->mem);
+  }
+  delete sp;
+  return PLU_OK;
+}
+
+int plu_sparse_pass(plu_handle h, plu_sparse sp, int32_t trans, const float* X, int64_t ldx,
+                    int32_t l, float* out, int64_t ldo) {
+  if (!h) return -1;
+  if (!sp || sp->device != h->device) return -2;
+  if (trans != 0 && trans != 1) return -3;
+  if (!X || (reinterpret_cast<uintptr_t>(X) & 3u)) return -4;
+  if (l < 1) return -6;
+  if (ldx < l) return -5;
+  if (!out || (reinterpret_cast<uintptr_t>(out) & 3u)) return -7;
+  if (ldo < l) return -8;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  const SparseMat& S = sp->mat;
+  PLU_TRY_HIP(trans ? launch_spmm(S.colptr, S.rowidx, S.valsT, S.n, X, ldx, l, out, ldo, h->stream)
+                    : launch_spmm(S.rowptr, S.colidx, S.vals, S.m, X, ldx, l, out, ldo, h->stream));
+  return PLU_OK;
+}
+
+// The sparse forms of the drivers: the dense argument list without layout,
+// m, n, A and lda (so every later argument's index is 4 lower).
+int plu_sparse_fixed_rank(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t v,
+                          int32_t prec, const float* Omega, uint64_t seed, int32_t* p, int32_t* q,
+                          float* L, int64_t ldl, float* U, int64_t ldu, plu_info* info) {
+  if (!h) return -1;
+  if (!sp || sp->device != h->device) return -2;
+  return fixed_rank_impl(h, PLU_ROW_MAJOR, sp->mat.m, sp->mat.n, nullptr, 0, &sp->mat, 4, k, p_over,
+                         v, prec, Omega, seed, p, q, L, ldl, U, ldu, info);
+}
+
+int plu_sparse_fixed_precision(plu_handle h, plu_sparse sp, double eps, int32_t b, int32_t l,
+                               int32_t v, int32_t column_exact, int32_t max_rounds, int32_t prec,
+                               const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                               int64_t ldl, float* U, int64_t ldu, int32_t* rank_out,
+                               plu_info* info) {
+  if (!h) return -1;
+  if (!sp || sp->device != h->device) return -2;
+  return fixed_precision_impl(h, PLU_ROW_MAJOR, sp->mat.m, sp->mat.n, nullptr, 0, &sp->mat, 4, eps,
+                              b, l, v, column_exact, max_rounds, prec, Omega, seed, p, q, L, ldl,
+                              U, ldu, rank_out, info);
+}
+
+int plu_sparse_randlu(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t pw,
+                      const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                      int64_t ldl, float* U, int64_t ldu, plu_info* info) {
+  if (!h) return -1;
+  if (!sp || sp->device != h->device) return -2;
+  return randlu_impl(h, PLU_ROW_MAJOR, sp->mat.m, sp->mat.n, nullptr, 0, &sp->mat, 4, k, p_over, pw,
+                     Omega, seed, p, q, L, ldl, U, ldu, info);
+}
+
+int plu_sparse_randsvd(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t pw,
+                       const float* Omega, uint64_t seed, float* Uo, int64_t ldu, float* S,
+                       float* Vo, int64_t ldv, plu_info* info) {
+  if (!h) return -1;
+  if (!sp || sp->device != h->device) return -2;
+  return randsvd_impl(h, PLU_ROW_MAJOR, sp->mat.m, sp->mat.n, nullptr, 0, &sp->mat, 4, k, p_over,
+                      pw, Omega, seed, Uo, ldu, S, Vo, ldv, info);
 }
 
 int plu_rank_rule(plu_handle h, int64_t m, int32_t l, const float* G, int64_t ldg, double normA2,

@@ -162,6 +162,32 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t s);
 // p[r][c] = -p[r][c] over a rows x cols block (leading dimension ld)
 hipError_t launch_negate(float* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
+// ---------------------------------------------------------------------------
+// Sparse A (compressed rows, with the compressed columns built once).
+// ---------------------------------------------------------------------------
+struct SparseMat {
+  int64_t m = 0, n = 0, nnz = 0;
+  const int64_t* rowptr = nullptr;   // m + 1 (caller's)
+  const int32_t* colidx = nullptr;   // nnz (caller's)
+  const float* vals = nullptr;       // nnz (caller's)
+  int64_t* colptr = nullptr;         // n + 1 (built)
+  int32_t* rowidx = nullptr;         // nnz, rows ascending within a column (built)
+  float* valsT = nullptr;            // nnz (built)
+  double* normA2 = nullptr;          // ||A||_F^2 (built)
+};
+// Bytes of device memory sparse_build needs for an m x n matrix with nnz
+// stored entries.
+size_t sparse_scratch_bytes(int64_t m, int64_t n, int64_t nnz);
+// Checks the compressed rows of S (when malformed, sets *bad_host -- bit 1 for
+// the row pointers, bit 2 for the column indices -- and returns hipSuccess;
+// synchronizes on s), then builds the compressed columns and ||A||_F^2 in
+// mem (sparse_scratch_bytes long).
+hipError_t sparse_build(SparseMat& S, void* mem, int32_t* bad_host, hipStream_t s);
+// out (rows x l, ldo) = S X for S given by (ptr, idx, val) in compressed
+// rows and X with at least max(idx) + 1 rows (ldx).
+hipError_t launch_spmm(const int64_t* ptr, const int32_t* idx, const float* val, int64_t rows,
+                       const float* X, int64_t ldx, int l, float* out, int64_t ldo, hipStream_t s);
+
 // R = U_r diag(S) V_r^T for a square l x l R, l <= 128 (one-sided Jacobi in
 // one workgroup): Ur, Vr l x l with columns in non-increasing order of the
 // singular values, the kout largest of which go to S; sweeps_out nullable.

@@ -16,6 +16,9 @@ Matrix families
   of seeded Gaussian matrices, the workload shapes used for measurement
   (square 2000, 20000, 32768; 30000 x 20000; mixed request sizes).
 * ``gaussian_omega``: the N(0,1) test matrix (Sec. 1, Alg. 7).
+* ``sprand_csr``: sparse matrices like MATLAB's sprand (uniform values at
+  random positions, Sec. 6.1's sparse experiment), in compressed rows;
+  ``csr_dense`` expands them.
 
 Seed scheme: ``seed = 1000 * workload + role`` with role 0 the left factor,
 1 the right factor, 2 the noise, 3 + s the Gaussian test matrix of run s.
@@ -28,6 +31,8 @@ from .generators import (  # noqa: F401
     lowrank_factors,
     lowrank_plus_noise,
     gaussian_omega,
+    sprand_csr,
+    csr_dense,
     WORKLOADS,
     workload_matrix_factors,
     workload_matrix,

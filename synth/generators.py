@@ -201,3 +201,31 @@ def request_stream(count: int = 1024, rate_per_s: float = 200.0, seed: int = 500
         else:
             out.append(Request(i, t, m, n, r, 1, 0, 0, 4, 1e-3, 16, seed + 1 + i))
     return out
+
+
+def sprand_csr(m: int, n: int, density: float, seed: int):
+    """A sparse m x n matrix like MATLAB's ``sprand(m, n, density)`` (the
+    sparse inputs of Sec. 6.1): uniform (0, 1) values at about
+    density * m * n distinct positions drawn uniformly.  Returns compressed
+    rows (indptr int64 m + 1, indices int32 ascending within each row, data
+    float32)."""
+    rng = np.random.default_rng(seed)
+    target = int(round(density * m * n))
+    # draw a few extra positions, drop repeats, keep the first target of them
+    draw = rng.integers(0, m * n, size=int(target * 1.01) + 16, dtype=np.int64)
+    _, first = np.unique(draw, return_index=True)
+    lin = np.sort(draw[np.sort(first)][:target])
+    rows = lin // n
+    cols = (lin % n).astype(np.int32)
+    indptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=indptr[1:])
+    data = rng.random(lin.size).astype(np.float32)
+    return indptr, cols, data
+
+
+def csr_dense(m: int, n: int, indptr, indices, data, dtype=np.float64) -> np.ndarray:
+    """The dense matrix of compressed rows (repeated entries summed)."""
+    A = np.zeros((m, n), dtype=dtype)
+    rows = np.repeat(np.arange(m), np.diff(indptr))
+    np.add.at(A, (rows, indices), data.astype(dtype))
+    return A
