@@ -313,7 +313,13 @@ struct ReduceArgs {
   double* colsq_part; int rb;
 };
 
+constexpr int RED_T = 1024;   // threads of the split-K reduction workgroup
+
 __device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
+  // One workgroup per block of rb rows and 64 float4 column groups; each
+  // thread sums its rows' partials over the splits in split order (up to
+  // sixteen splits in flight), so the sums do not depend on the thread
+  // layout.
   const float* __restrict__ part = ra.part;
   const int64_t part_stride = ra.part_stride;
   const int nsplit = ra.nsplit;
@@ -323,7 +329,7 @@ __device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
   const int rb = ra.rb;
   const int64_t c4n = (C + 3) / 4;                 // float4 groups per row
   const int lanes_per_row = (int)((c4n < 64) ? c4n : 64);
-  const int rows_per_pass = 256 / lanes_per_row;
+  const int rows_per_pass = RED_T / lanes_per_row;
   const int tid = threadIdx.x;
   const int rsub = tid / lanes_per_row, cl = tid % lanes_per_row;
   const int64_t pb = gr.bx;
@@ -339,17 +345,27 @@ __device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
       float s[4] = {0.f, 0.f, 0.f, 0.f};
       const float* src0 = part + p * ldo + c0;
       if (v4ok) {
-        // four splits in flight at a time, summed in split order
         int k = 0;
-        for (; k + 4 <= nsplit; k += 4) {
-          f32x4 v[4];
+        for (; k + 16 <= nsplit; k += 16) {
+          f32x4 v[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 16; ++u)
             v[u] = *reinterpret_cast<const f32x4*>(src0 + (int64_t)(k + u) * part_stride);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 16; ++u) {
             s[0] += v[u].x; s[1] += v[u].y; s[2] += v[u].z; s[3] += v[u].w;
           }
+        }
+        if (k + 8 <= nsplit) {
+          f32x4 v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            v[u] = *reinterpret_cast<const f32x4*>(src0 + (int64_t)(k + u) * part_stride);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            s[0] += v[u].x; s[1] += v[u].y; s[2] += v[u].z; s[3] += v[u].w;
+          }
+          k += 8;
         }
         for (; k < nsplit; ++k) {
           const f32x4 v = *reinterpret_cast<const f32x4*>(src0 + (int64_t)k * part_stride);
@@ -375,7 +391,7 @@ __device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
   }
   if (!colsq_part) return;
   // combine the rows_per_pass partial sums of each column group in a fixed order
-  __shared__ double acc[256][4];
+  __shared__ double acc[RED_T][4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) acc[tid][e] = cs[e];
   __syncthreads();
@@ -503,7 +519,7 @@ hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nspl
                                 int rows_per_block, hipStream_t s) {
   dim3 grid((unsigned)((P + rows_per_block - 1) / rows_per_block),
             (unsigned)(((C + 3) / 4 + 63) / 64));
-  return dispatch<ReduceArgs, b_splitk_reduce, 256>(
+  return dispatch<ReduceArgs, b_splitk_reduce, RED_T>(
       ReduceArgs{part, part_stride, nsplit, out, ldo, P, C, colsq_part, rows_per_block}, grid, 0,
       s);
 }
