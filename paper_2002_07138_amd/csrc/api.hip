@@ -333,10 +333,12 @@ QrWork qr_work(const Ws& w, float* q, int64_t ldq) {
 // *colsq_blocks receives the number of row blocks).
 // Autotuned split of the passes over A.  The first pass of a shape (direction,
 // P, R, C, leading dimension of the output) on a device times the candidate
-// plans -- the split that fills whole rounds of 512, 768, 1024, 1280, 1536 or
-// 2048 resident workgroups -- with events on the handle's stream and keeps
-// the fastest for the process, so every later pass of that shape (single
-// calls and batches alike) runs the same plan and gives the same bits.
+// plans -- 128 or 64 rows per workgroup, each with the split that fills whole
+// rounds of 512, 768, 1024, 1280, 1536 or 2048 resident workgroups -- with
+// events on the handle's stream and keeps the fastest for the process, so
+// every later pass of that shape (single calls and batches alike) runs the
+// same plan and gives the same bits.  The row-block size leaves every output
+// element's summation order unchanged; the split does not.
 struct TuneKey {
   int device, trans;
   int64_t P, R, C, ldo;
@@ -362,7 +364,8 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   const int64_t P = g.P, R = g.R, C = g.C;
   const GemmPlan def = plan_gemm(P, R, C, kMaxSplit, kTargetWgs);
   auto fits = [&](const GemmPlan& p) {
-    return p.nsplit == 1 || (int64_t)p.nsplit * P * ldo <= w.part_cap;
+    return (p.nsplit == 1 || (int64_t)p.nsplit * P * ldo <= w.part_cap) &&
+           (int64_t)p.pblocks * p.nsplit <= w.sumsq_cap;
   };
   const TuneKey key{h->device, trans, P, R, C, ldo};
   {
@@ -373,34 +376,56 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   // small passes and recorded (batched) launches use the default plan
   if (!tune_enabled() || thread_recorder() || 2.0 * P * R * C < 2e10) return fits(def) ? def : plan_gemm(P, R, C, 1, 1);
   std::vector<GemmPlan> cands;
-  for (int slots : {512, 768, 1024, 1280, 1536, 2048}) {
-    GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots);
-    if (!fits(p)) continue;
-    bool dup = false;
-    for (auto& c : cands) dup |= c.nsplit == p.nsplit;
-    if (dup) continue;
-    cands.push_back(p);
+  for (int bp : {GEMM_BP, 64}) {
+    for (int slots : {512, 768, 1024, 1280, 1536, 2048}) {
+      GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots, GEMM_BK, bp);
+      if (!fits(p)) continue;
+      bool dup = false;
+      for (auto& c : cands) dup |= c.nsplit == p.nsplit && c.bp == p.bp;
+      if (dup) continue;
+      cands.push_back(p);
+    }
   }
   if (cands.empty()) return plan_gemm(P, R, C, 1, 1);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return cands[0];
+  // every candidate once to warm up (clocks, caches, code), then three rounds
+  // over all candidates in turn, keeping each one's fastest round, so that a
+  // clock still rising during the first launches favours none of them
+  std::vector<float> cand_ms(cands.size(), 1e30f);
+  std::vector<char> cand_ok(cands.size(), 1);
+  for (size_t c = 0; c < cands.size(); ++c)
+    cand_ok[c] = pass_launch(h, w, trans, g, cands[c], out, ldo, nullptr, h->stream) == hipSuccess;
+  for (int round = 0; round < 3; ++round) {
+    for (size_t c = 0; c < cands.size(); ++c) {
+      if (!cand_ok[c]) continue;
+      float ms = 0.f;
+      bool ok = hipEventRecord(e0, h->stream) == hipSuccess;
+      for (int r = 0; r < 2 && ok; ++r)
+        ok = pass_launch(h, w, trans, g, cands[c], out, ldo, nullptr, h->stream) == hipSuccess;
+      ok = ok && hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (!ok) cand_ok[c] = 0;
+      else cand_ms[c] = std::min(cand_ms[c], ms);
+    }
+  }
   GemmPlan best = cands[0];
   float best_ms = 1e30f;
-  for (const GemmPlan& p : cands) {
-    float ms = 0.f;
-    bool ok = pass_launch(h, w, trans, g, p, out, ldo, nullptr, h->stream) == hipSuccess;   // warm
-    ok = ok && hipEventRecord(e0, h->stream) == hipSuccess;
-    for (int r = 0; r < 3 && ok; ++r)
-      ok = pass_launch(h, w, trans, g, p, out, ldo, nullptr, h->stream) == hipSuccess;
-    ok = ok && hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    if (ok && ms < best_ms) {
-      best_ms = ms;
-      best = p;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    if (cand_ok[c] && cand_ms[c] < best_ms) {
+      best_ms = cand_ms[c];
+      best = cands[c];
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (const char* lg = std::getenv("PLU_AUTOTUNE_LOG"); lg && lg[0] == '1') {
+    for (size_t c = 0; c < cands.size(); ++c)
+      std::fprintf(stderr, "plu autotune: %s P %lld R %lld C %lld ldo %lld: rows %d split %d: %.4f ms%s\n",
+                   trans ? "T" : "N", (long long)P, (long long)R, (long long)C, (long long)ldo,
+                   cands[c].bp, cands[c].nsplit, cand_ms[c] / 2, (cands[c].bp == best.bp &&
+                   cands[c].nsplit == best.nsplit) ? "  <- kept" : "");
+  }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[key] = best;
   return best;

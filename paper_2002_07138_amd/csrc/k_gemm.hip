@@ -271,6 +271,13 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
   }
 }
 
+// The one-tile-per-wave variant (64 rows per workgroup): half the registers,
+// so more workgroups share a CU; the autotuner tries it beside the default.
+template <int MODE, int NT, int EPI>
+__device__ void b_pass64(const GemmArgs& g, const Grid& gr) {
+  pass_body<MODE, NT, EPI, 1>(g, gr);
+}
+
 template <int MODE, int NT, int EPI>
 __device__ void b_pass(const GemmArgs& g, const Grid& gr) {
   pass_body<MODE, NT, EPI>(g, gr);
@@ -280,9 +287,33 @@ __device__ void b_pass(const GemmArgs& g, const Grid& gr) {
 // problem's arguments, so one launch serves every pass of a batch that has
 // the same epilogue.
 template <int EPI>
+__device__ void b_pass_any64(const GemmArgs& g, const Grid& gr) {
+  if (g.mode == 0) pass_body<0, 8, EPI, 1, GEMM_BK, true>(g, gr);
+  else pass_body<1, 8, EPI, 1, GEMM_BK, true>(g, gr);
+}
+
+template <int EPI>
 __device__ void b_pass_any(const GemmArgs& g, const Grid& gr) {
   if (g.mode == 0) pass_body<0, 8, EPI, GEMM_BP / 64, GEMM_BK, true>(g, gr);
   else pass_body<1, 8, EPI, GEMM_BP / 64, GEMM_BK, true>(g, gr);
+}
+
+template <int MODE, int EPI>
+hipError_t launch_nt64(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
+  if (thread_recorder()) {
+    GemmArgs b = a;
+    b.mode = MODE;
+    b.nt = nt;
+    return dispatch<GemmArgs, b_pass_any64<EPI>, 256, 2>(b, grid, 0, s);
+  }
+  switch (nt) {
+#define PLU_NT_CASE(N) \
+  case N: return dispatch<GemmArgs, b_pass64<MODE, N, EPI>, 256, 2>(a, grid, 0, s);
+    PLU_NT_CASE(1) PLU_NT_CASE(2) PLU_NT_CASE(3) PLU_NT_CASE(4)
+    PLU_NT_CASE(5) PLU_NT_CASE(6) PLU_NT_CASE(7) PLU_NT_CASE(8)
+#undef PLU_NT_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int MODE, int EPI>
@@ -450,12 +481,15 @@ __device__ void b_sumsq_matrix(const SumsqArgs& a, const Grid& gr) {
 
 }  // namespace
 
-GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int slots, int kalign) {
+GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int slots, int kalign,
+                   int bp) {
   // slots: workgroups the device runs at once.  The split of R is chosen so
   // that the grid fills whole rounds of slots (the last round nearly full),
-  // with at least 256 of R per split.
+  // with at least 256 of R per split.  bp: rows per workgroup (GEMM_BP, or
+  // 64 for the one-tile-per-wave variant of the direct passes).
   GemmPlan pl;
-  pl.pblocks = (int)((P + BP - 1) / BP);
+  pl.bp = (bp == 64) ? 64 : BP;
+  pl.pblocks = (int)((P + pl.bp - 1) / pl.bp);
   const int64_t cb = (C + 127) / 128;
   pl.cblocks = (int)cb;
   const int64_t cpb = (C + cb - 1) / cb;          // columns per block, balanced
@@ -497,6 +531,15 @@ hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const Gem
   // column blocks of nt*16 columns each
   dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
   if ((int64_t)pl.cblocks * pl.nt * 16 < g.C) return hipErrorInvalidValue;
+  if (pl.bp == 64) {
+    // planned for the one-tile-per-wave kernels: the direct passes only
+    if (epi != EPI_STORE && epi != EPI_PART) return hipErrorInvalidValue;
+    if (mode == 0)
+      return epi == EPI_STORE ? launch_nt64<0, EPI_STORE>(pl.nt, grid, g, s)
+                              : launch_nt64<0, EPI_PART>(pl.nt, grid, g, s);
+    return epi == EPI_STORE ? launch_nt64<1, EPI_STORE>(pl.nt, grid, g, s)
+                            : launch_nt64<1, EPI_PART>(pl.nt, grid, g, s);
+  }
   if (mode == 0) {
     switch (epi) {
       case EPI_STORE: return launch_nt<0, EPI_STORE>(pl.nt, grid, g, s);

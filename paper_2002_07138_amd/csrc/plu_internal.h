@@ -16,11 +16,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Pass GEMM (one pass over A): out = op(A) X, FP32 MFMA 16x16x4, fp32 accumulate.
 //   mode 0 ("N"): out[p][c] = sum_r A[p][r] X[r][c]   (A is P x R, row-major)
 //   mode 1 ("T"): out[p][c] = sum_r A[r][p] X[r][c]   (A is R x P, row-major)
-// The kept dimension P is tiled by 256 rows, the columns c by NT*16 (NT<=8),
+// The kept dimension P is tiled by 128 (or 64) rows, the columns c by NT*16 (NT<=8),
 // the reduced dimension R by 32 per LDS stage and optionally split across
 // workgroups (partials reduced afterwards in a fixed order).
 // ---------------------------------------------------------------------------
 enum Epi { EPI_STORE = 0, EPI_PART = 1, EPI_SUB = 2, EPI_RESID = 3 };
+
+constexpr int GEMM_BP = 128;   // rows of the kept dimension per pass workgroup (2 tiles per wave)
+constexpr int GEMM_BK = 32;
 
 struct GemmArgs {
   const float* A = nullptr; int64_t lda = 0;
@@ -45,8 +48,6 @@ struct GemmArgs {
   const int32_t* run_if = nullptr;   // device flag: the launch does nothing when it reads 0
 };
 
-constexpr int GEMM_BP = 128;   // rows of the kept dimension per pass workgroup (2 tiles per wave)
-constexpr int GEMM_BK = 32;
 
 // Plans the split of R and launches; part must hold nsplit*P*ldo floats when
 // the plan splits.  Returns the number of sumsq partials written (grid size)
@@ -54,11 +55,12 @@ constexpr int GEMM_BK = 32;
 struct GemmPlan {
   int pblocks, cblocks, nt, nsplit;
   int64_t rsplit;
+  int bp = GEMM_BP;   // rows per workgroup: GEMM_BP, or 64 (one MFMA row tile per wave)
 };
 // kalign: the split length is a multiple of it (the reduction depth of one
 // stage of the kernel that runs the plan).
 GemmPlan plan_gemm(int64_t P, int64_t R, int64_t C, int max_split, int target_wgs,
-                   int kalign = GEMM_BK);
+                   int kalign = GEMM_BK, int bp = GEMM_BP);
 hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const GemmPlan& pl,
                        hipStream_t s);
 hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit,
