@@ -271,16 +271,27 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
   }
 }
 
+// The direct passes (store or split partials) stage 16 of the reduced
+// dimension per LDS step: fewer registers in flight per thread, so 4
+// workgroups of 128 rows (or 6 of 64 rows) share a CU, and the waiting on
+// the streamed tiles of one is covered by the multiplies of the others.  The
+// summation order of each output element is that of 32 per step (two steps
+// of 16 are the same MFMA sequence), so the bits do not change.
+constexpr int PASS_BK_DIRECT = 16;
+
+template <int EPI>
+constexpr int pass_bk() { return (EPI == EPI_STORE || EPI == EPI_PART) ? PASS_BK_DIRECT : GEMM_BK; }
+
 // The one-tile-per-wave variant (64 rows per workgroup): half the registers,
 // so more workgroups share a CU; the autotuner tries it beside the default.
 template <int MODE, int NT, int EPI>
 __device__ void b_pass64(const GemmArgs& g, const Grid& gr) {
-  pass_body<MODE, NT, EPI, 1>(g, gr);
+  pass_body<MODE, NT, EPI, 1, pass_bk<EPI>()>(g, gr);
 }
 
 template <int MODE, int NT, int EPI>
 __device__ void b_pass(const GemmArgs& g, const Grid& gr) {
-  pass_body<MODE, NT, EPI>(g, gr);
+  pass_body<MODE, NT, EPI, GEMM_BP / 64, pass_bk<EPI>()>(g, gr);
 }
 
 // The grouped pass: either direction and up to 8 column tiles, read from the
@@ -308,7 +319,7 @@ hipError_t launch_nt64(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
   }
   switch (nt) {
 #define PLU_NT_CASE(N) \
-  case N: return dispatch<GemmArgs, b_pass64<MODE, N, EPI>, 256, 2>(a, grid, 0, s);
+  case N: return dispatch<GemmArgs, b_pass64<MODE, N, EPI>, 256, 4>(a, grid, 0, s);
     PLU_NT_CASE(1) PLU_NT_CASE(2) PLU_NT_CASE(3) PLU_NT_CASE(4)
     PLU_NT_CASE(5) PLU_NT_CASE(6) PLU_NT_CASE(7) PLU_NT_CASE(8)
 #undef PLU_NT_CASE
@@ -328,7 +339,9 @@ hipError_t launch_nt(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
   }
   switch (nt) {
 #define PLU_NT_CASE(N) \
-  case N: return dispatch<GemmArgs, b_pass<MODE, N, EPI>, 256, (N * 2 >= 32) ? 1 : 2>(a, grid, 0, s);
+  case N:                                                                         \
+    return dispatch<GemmArgs, b_pass<MODE, N, EPI>, 256,                          \
+                    (pass_bk<EPI>() == PASS_BK_DIRECT && N < 8) ? 4 : 2>(a, grid, 0, s);
     PLU_NT_CASE(1) PLU_NT_CASE(2) PLU_NT_CASE(3) PLU_NT_CASE(4)
     PLU_NT_CASE(5) PLU_NT_CASE(6) PLU_NT_CASE(7) PLU_NT_CASE(8)
 #undef PLU_NT_CASE

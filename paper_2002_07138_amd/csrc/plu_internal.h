@@ -17,7 +17,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 //   mode 0 ("N"): out[p][c] = sum_r A[p][r] X[r][c]   (A is P x R, row-major)
 //   mode 1 ("T"): out[p][c] = sum_r A[r][p] X[r][c]   (A is R x P, row-major)
 // The kept dimension P is tiled by 128 (or 64) rows, the columns c by NT*16 (NT<=8),
-// the reduced dimension R by 32 per LDS stage and optionally split across
+// the reduced dimension R by 16 (direct passes) or 32 per LDS stage and split across
 // workgroups (partials reduced afterwards in a fixed order).
 // ---------------------------------------------------------------------------
 enum Epi { EPI_STORE = 0, EPI_PART = 1, EPI_SUB = 2, EPI_RESID = 3 };
