@@ -349,6 +349,9 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, GemmPlan> g_tuned;
 
+// row stride of the split partials of a pass whose output has row stride ldo
+int64_t part_ld(int64_t ldo) { return (ldo + 3) & ~int64_t(3); }
+
 hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0, const GemmPlan& pl,
                        float* out, int64_t ldo, double* colsq, hipStream_t s);
 
@@ -364,7 +367,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   const int64_t P = g.P, R = g.R, C = g.C;
   const GemmPlan def = plan_gemm(P, R, C, kMaxSplit, kTargetWgs);
   auto fits = [&](const GemmPlan& p) {
-    return (p.nsplit == 1 || (int64_t)p.nsplit * P * ldo <= w.part_cap) &&
+    return (p.nsplit == 1 || (int64_t)p.nsplit * P * part_ld(ldo) <= w.part_cap) &&
            (int64_t)p.pblocks * p.nsplit <= w.sumsq_cap;
   };
   const TuneKey key{h->device, trans, P, R, C, ldo};
@@ -438,9 +441,13 @@ hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0,
   const int rb = 64;
   hipError_t e;
   if (pl.nsplit > 1) {
-    g.out = w.part; g.ldo = ldo; g.part_stride = P * ldo;
+    // the partials' rows padded to whole float4s, so the reduction reads
+    // every column group, the last one too, as whole float4s
+    const int64_t pld = part_ld(ldo);
+    if ((int64_t)pl.nsplit * P * pld > w.part_cap) return hipErrorInvalidValue;
+    g.out = w.part; g.ldo = pld; g.part_stride = P * pld;
     if ((e = launch_gemm(trans, EPI_PART, 0, g, pl, s)) != hipSuccess) return e;
-    return launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, g.C, colsq, rb, s);
+    return launch_splitk_reduce_ld(w.part, pld, P * pld, pl.nsplit, out, ldo, P, g.C, colsq, rb, s);
   }
   g.out = out; g.ldo = ldo;
   if ((e = launch_gemm(trans, EPI_STORE, 0, g, pl, s)) != hipSuccess) return e;

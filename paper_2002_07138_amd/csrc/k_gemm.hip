@@ -353,7 +353,7 @@ hipError_t launch_nt(int nt, dim3 grid, const GemmArgs& a, hipStream_t s) {
 // consecutive columns of a row; optional per-column float64 sums of squares
 // over each block of rows_per_block rows (deterministic: fixed order).
 struct ReduceArgs {
-  const float* part; int64_t part_stride; int nsplit; float* out; int64_t ldo, P, C;
+  const float* part; int64_t pld, part_stride; int nsplit; float* out; int64_t ldo, P, C;
   double* colsq_part; int rb;
 };
 
@@ -365,6 +365,7 @@ __device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
   // sixteen splits in flight), so the sums do not depend on the thread
   // layout.
   const float* __restrict__ part = ra.part;
+  const int64_t pld = ra.pld;                      // row stride of the partials
   const int64_t part_stride = ra.part_stride;
   const int nsplit = ra.nsplit;
   float* out = ra.out;
@@ -383,11 +384,13 @@ __device__ void b_splitk_reduce(const ReduceArgs& ra, const Grid& gr) {
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
   if (active && cgi < c4n) {
     const int64_t c0 = cgi * 4;
-    const bool v4ok = ((reinterpret_cast<uintptr_t>(part) & 15u) == 0) && ((ldo & 3) == 0) &&
-                      ((part_stride & 3) == 0) && (c0 + 3 < C);
+    // whole float4 reads wherever they stay inside a row of the partials;
+    // entries at columns >= C are read but not used
+    const bool v4ok = ((reinterpret_cast<uintptr_t>(part) & 15u) == 0) && ((pld & 3) == 0) &&
+                      ((part_stride & 3) == 0) && (c0 + 3 < pld);
     for (int64_t p = pb * rb + rsub; p < pe; p += rows_per_pass) {
       float s[4] = {0.f, 0.f, 0.f, 0.f};
-      const float* src0 = part + p * ldo + c0;
+      const float* src0 = part + p * pld + c0;
       if (v4ok) {
         int k = 0;
         for (; k + 16 <= nsplit; k += 16) {
@@ -570,14 +573,22 @@ hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const Gem
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit, float* out,
-                                int64_t ldo, int64_t P, int64_t C, double* colsq_part,
-                                int rows_per_block, hipStream_t s) {
+hipError_t launch_splitk_reduce_ld(const float* part, int64_t pld, int64_t part_stride,
+                                   int nsplit, float* out, int64_t ldo, int64_t P, int64_t C,
+                                   double* colsq_part, int rows_per_block, hipStream_t s) {
+  if (pld < C || (nsplit > 1 && part_stride < P * pld)) return hipErrorInvalidValue;
   dim3 grid((unsigned)((P + rows_per_block - 1) / rows_per_block),
             (unsigned)(((C + 3) / 4 + 63) / 64));
   return dispatch<ReduceArgs, b_splitk_reduce, RED_T>(
-      ReduceArgs{part, part_stride, nsplit, out, ldo, P, C, colsq_part, rows_per_block}, grid, 0,
-      s);
+      ReduceArgs{part, pld, part_stride, nsplit, out, ldo, P, C, colsq_part, rows_per_block},
+      grid, 0, s);
+}
+
+hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit, float* out,
+                                int64_t ldo, int64_t P, int64_t C, double* colsq_part,
+                                int rows_per_block, hipStream_t s) {
+  return launch_splitk_reduce_ld(part, ldo, part_stride, nsplit, out, ldo, P, C, colsq_part,
+                                 rows_per_block, s);
 }
 
 hipError_t launch_sum_doubles(const double* in, int64_t n, double* out, hipStream_t s) {

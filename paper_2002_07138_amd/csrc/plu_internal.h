@@ -66,6 +66,11 @@ hipError_t launch_gemm(int mode, int epi, int bf16, const GemmArgs& a, const Gem
 hipError_t launch_splitk_reduce(const float* part, int64_t part_stride, int nsplit,
                                 float* out, int64_t ldo, int64_t P, int64_t C,
                                 double* colsq_part, int rows_per_block, hipStream_t s);
+// The same with the partials at their own row stride pld (>= C; a multiple of
+// 4 lets every column group, the last one too, be read as whole float4s).
+hipError_t launch_splitk_reduce_ld(const float* part, int64_t pld, int64_t part_stride,
+                                   int nsplit, float* out, int64_t ldo, int64_t P, int64_t C,
+                                   double* colsq_part, int rows_per_block, hipStream_t s);
 hipError_t launch_sum_doubles(const double* in, int64_t n, double* out, hipStream_t s);
 hipError_t launch_sumsq_matrix(const float* A, int64_t lda, int64_t m, int64_t n,
                                double* part, int nblocks, hipStream_t s);
