@@ -379,7 +379,7 @@ int plu_server_destroy(plu_server s);
 
 /* ================= Building blocks (one call per step of the path) ======= */
 
-/* Gaussian test matrix (Sec. 1; Alg. 7 lines 2 and 9): out (device,
+/* Gaussian test matrix (Sec. 1; Alg. 7): out (device,
  * rows x cols, ldo) filled with N(0,1) values.  Element e = i*cols + j is
  * word e%4 of Philox4x32-10 block e/4 (Salmon et al., SC'11) with counter
  * (e/4 mod 2^32, e/4 div 2^32, 0, 0) and key (seed mod 2^32, seed div 2^32);
@@ -391,7 +391,7 @@ int plu_gaussian(plu_handle h, int64_t rows, int64_t cols, uint64_t seed,
 /* One pass over A (the matrix products of Alg. 7 and Alg. 5 step 3):
  * trans = 0: out (m x l) = A X with X n x l;  trans = 1: out (n x l) = A^T X
  * with X m x l.  All device.  normA2_out: device double*, nullable; receives
- * ||A||_F^2 accumulated in float64 while A streams through (Alg. 8 line 1).
+ * ||A||_F^2 accumulated in float64 while A streams through (Alg. 8).
  * prec: PLU_PREC_FP32 or PLU_PREC_BF16 (operands rounded to bf16).       */
 int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, int64_t lda,
              int32_t l, const float* X, int64_t ldx, float* out, int64_t ldo,
@@ -427,9 +427,9 @@ int plu_quantize(plu_handle h, int32_t fmt, int64_t rows, int64_t cols, const fl
 int plu_getrf(plu_handle h, int64_t M, int32_t c, float* F, int64_t ldf,
               int32_t* perm, float* Ufac, int64_t ldu, plu_info* info);
 
-/* Thin QR basis (the paper's [V, ~] = qr(X), Alg. 6 line 5 / Alg. 7 lines 6
- * and 15): X (device, M x c, ldx, M > c) is replaced by an orthonormal Q
- * with Range(Q(:,1:j)) = Range(X(:,1:j)) for every j (column signs are
+/* Thin QR basis (the paper's [V, ~] = qr(X) in Alg. 6 and Alg. 7): X
+ * (device, M x c, ldx, M > c) is replaced by an orthonormal Q with
+ * Range(Q(:,1:j)) = Range(X(:,1:j)) for every j (column signs are
  * unspecified).                                                           */
 int plu_thin_qr(plu_handle h, int64_t M, int32_t c, float* X, int64_t ldx);
 

@@ -86,7 +86,7 @@ def lowrank_plus_noise(m: int, n: int, sigma: np.ndarray, seed_left: int,
 
 
 def gaussian_omega(rows: int, cols: int, seed: int, dtype=np.float32) -> np.ndarray:
-    """N(0,1) test matrix (Sec. 1; Alg. 7 lines 2 and 9)."""
+    """N(0,1) test matrix (Sec. 1; Alg. 7)."""
     return np.random.default_rng(seed).standard_normal((rows, cols)).astype(dtype)
 
 
