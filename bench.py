@@ -535,7 +535,7 @@ def main():
                          "direction) and a plain 1 GiB copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU design is "
+        print("bench.py: this library runs on one GPU only (the multi-GPU design is "
               "described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
