@@ -378,8 +378,14 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   }
   // small passes and recorded (batched) launches use the default plan
   if (!tune_enabled() || thread_recorder() || 2.0 * P * R * C < 2e10) return fits(def) ? def : plan_gemm(P, R, C, 1, 1);
+  // PLU_AUTOTUNE_ROWS=64 or 128 holds the tuner to one row-block size
+  int only_bp = 0;
+  if (const char* rows = std::getenv("PLU_AUTOTUNE_ROWS")) only_bp = std::atoi(rows);
   std::vector<GemmPlan> cands;
   for (int bp : {GEMM_BP, 64}) {
+    if (only_bp == 64 || only_bp == GEMM_BP) {
+      if (bp != only_bp) continue;
+    }
     for (int slots : {512, 768, 1024, 1280, 1536, 2048}) {
       GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots, GEMM_BK, bp);
       if (!fits(p)) continue;
@@ -527,8 +533,9 @@ hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_
   const int64_t P = trans ? n : m, Kl = trans ? m : n, K = ru(Kl, 64);
   const uint16_t* M = trans ? w.abt : w.ab;
   const int64_t ldm = trans ? w.ldabt : w.ldab;
+  const int64_t pld = part_ld(ldo);
   GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, 64);
-  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * ldo > w.part_cap)
+  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * pld > w.part_cap)
     pl = plan_gemm(P, K, l, 1, 1, 64);
   const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
   if (ct > w.xt_rows || K > w.ldxt) return hipErrorInvalidValue;
@@ -537,11 +544,11 @@ hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_
                            h->stream)) != hipSuccess)
     return e;
   if (pl.nsplit > 1) {
-    if ((e = launch_pass_bf16(EPI_PART, M, ldm, w.xt, K, w.part, ldo, P * ldo, P, K, l, pl,
+    if ((e = launch_pass_bf16(EPI_PART, M, ldm, w.xt, K, w.part, pld, P * pld, P, K, l, pl,
                               h->stream)) != hipSuccess)
       return e;
-    return launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, l, nullptr, 64,
-                                h->stream);
+    return launch_splitk_reduce_ld(w.part, pld, P * pld, pl.nsplit, out, ldo, P, l, nullptr, 64,
+                                   h->stream);
   }
   return launch_pass_bf16(EPI_STORE, M, ldm, w.xt, K, out, ldo, 0, P, K, l, pl, h->stream);
 }
@@ -575,8 +582,9 @@ hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t
   const uint8_t* M = trans ? w.a8t : w.a8;
   const uint8_t* Ms = trans ? w.a8ts : w.a8s;
   const int64_t ldm = trans ? w.lda8t : w.lda8;
+  const int64_t pld = part_ld(ldo);
   GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, 128);
-  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * ldo > w.part_cap)
+  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * pld > w.part_cap)
     pl = plan_gemm(P, K, l, 1, 1, 128);
   const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
   if (ct > w.x8_rows || K > w.ldx8) return hipErrorInvalidValue;
@@ -585,11 +593,11 @@ hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t
       hipSuccess)
     return e;
   if (pl.nsplit > 1) {
-    if ((e = launch_pass_fp8(EPI_PART, M, Ms, ldm, w.x8, w.x8s, K, w.part, ldo, P * ldo, P, K, l,
-                             pl, h->stream)) != hipSuccess)
+    if ((e = launch_pass_fp8(EPI_PART, M, Ms, ldm, w.x8, w.x8s, K, w.part, pld, P * pld, P, K,
+                             l, pl, h->stream)) != hipSuccess)
       return e;
-    return launch_splitk_reduce(w.part, P * ldo, pl.nsplit, out, ldo, P, l, nullptr, 64,
-                                h->stream);
+    return launch_splitk_reduce_ld(w.part, pld, P * pld, pl.nsplit, out, ldo, P, l, nullptr, 64,
+                                   h->stream);
   }
   return launch_pass_fp8(EPI_STORE, M, Ms, ldm, w.x8, w.x8s, K, out, ldo, 0, P, K, l, pl,
                          h->stream);

@@ -112,3 +112,27 @@ def test_batch_rejects_invalid_request(h):
     A = dev(np.ones((100, 80), dtype=np.float32))
     with pytest.raises(plu.PowerLUError):
         h.batched([dict(A=A, mode=0, k=70, p_over=20, v=3)])
+
+
+@pytest.mark.parametrize("rows", [64, 128])
+def test_batch_tuned_plans_match_single_calls(h, rows, monkeypatch):
+    """Passes large enough for the split tuner (2 m n l >= 2e10 flops), with
+    the tuner held to one row-block size: the plan tuned on the single calls
+    also runs the batch's grouped launches (the 64- or 128-row grouped
+    kernel), so the batch still equals the single calls bitwise."""
+    monkeypatch.setenv("PLU_AUTOTUNE_ROWS", str(rows))
+    m, n = 9611 + rows, 9600
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(rows)
+    U = torch.randn(m, 80, device="cuda:0", generator=gen)
+    V = torch.randn(80, n, device="cuda:0", generator=gen)
+    A = (U @ V) / 80.0 + 1e-3 * torch.randn(m, n, device="cuda:0", generator=gen)
+    assert 2.0 * m * n * 110 >= 2e10
+    probs = [dict(A=A, mode=0, k=100, p_over=10, v=3, seed=1),
+             dict(A=A, mode=0, k=100, p_over=10, v=4, seed=2)]
+    singles = [_single(h, pr) for pr in probs]
+    outs = h.batched(probs)
+    for f, g in zip(outs, singles):
+        _same(f, g)
+    del A, U, V
+    torch.cuda.empty_cache()
