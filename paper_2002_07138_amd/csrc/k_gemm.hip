@@ -223,8 +223,10 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
     for (int64_t r = rb; r < re; r += BK) {
       __syncthreads();
       sstore();
-      __syncthreads();
+      // the next stage's loads go out before the barrier: its wait then
+      // overlaps them too
       if (r + BK < re) gload(r + BK);
+      __syncthreads();
       compute();
     }
   }
