@@ -2,12 +2,15 @@
 // products of Alg. 7 and of Alg. 5 step 3 / Alg. 8 step 3), on FP32 MFMA.
 //
 // Work decomposition (per workgroup of 256 threads = 4 waves):
-//   * 128 rows of the kept dimension P (32 per wave, 2 MFMA row tiles; the
-//     small register footprint lets 4 workgroups share a CU, which is what
-//     hides the HBM latency of the streamed A tiles),
+//   * 128 rows of the kept dimension P (32 per wave, 2 MFMA row tiles), or
+//     64 rows (1 tile per wave) in the variant the autotuner may pick; the
+//     small register footprint lets 4 (or 6) workgroups share a CU, which is
+//     what hides the HBM latency of the streamed A tiles,
 //   * NT*16 columns of the sketch (NT <= 8 MFMA column tiles),
-//   * a contiguous range of the reduced dimension R, walked 32 at a time
-//     through LDS with the next stage prefetched into registers.
+//   * a contiguous range of the reduced dimension R, walked 16 (direct
+//     passes) or 32 at a time through LDS with the next stage prefetched into
+//     registers; the prefetch is issued before the barrier that follows the
+//     LDS store.
 // v_mfma_f32_16x16x4f32 is fed with a permuted reduction order: lane (r, g)
 // of a 16x16x4 step s uses reduction index 4g + s inside a 16-wide group, so
 // one 16-byte LDS read of A gives a lane its operands for four consecutive
