@@ -566,15 +566,14 @@ hipError_t cholqr_probe(const float* X, int64_t ldx, int64_t M, int bw, const Qr
 hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork& gw0,
                        const QrWork& qw, hipStream_t s) {
   hipError_t e;
-  // LU reorthogonalization X <- P^T L first -- for a single block only when
-  // the Cholesky factor of X's Gram shows it ill-conditioned (the LU kernels
-  // then read the flag on the device and run or return at once)
+  // Block classical Gram-Schmidt with reorthogonalization over blocks of QB
+  // columns.  Each block, once projected off the earlier ones, is probed:
+  // the Cholesky factor of its float64 Gram decides whether it first takes
+  // the LU reorthogonalization V_J <- P^T L (the LU kernels read the flag on
+  // the device and run or return at once).  Both steps multiply the block by
+  // upper triangular matrices, so Range(Q(:,1:j)) = Range(X(:,1:j)).
   GetrfWork gw = gw0;
-  if (c <= QB) {
-    if ((e = cholqr_probe(X, ldx, M, c, qw, s)) != hipSuccess) return e;
-    gw.run_if = qw.status + 4;
-  }
-  if ((e = getrf_run(X, ldx, M, c, gw, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
+  gw.run_if = qw.status + 4;
   for (int j0 = 0; j0 < c; j0 += QB) {
     const int bw = (c - j0 < QB) ? c - j0 : QB;
     float* VJ = X + j0;
@@ -596,11 +595,13 @@ hipError_t thin_qr_run(float* X, int64_t ldx, int64_t M, int c, const GetrfWork&
         if ((e = gemm_any(0, EPI_SUB, h, qw, s)) != hipSuccess) return e;
       }
     }
+    if ((e = cholqr_probe(VJ, ldx, M, bw, qw, s)) != hipSuccess) return e;
+    if ((e = getrf_run(VJ, ldx, M, bw, gw, nullptr, nullptr, 0, 0, s)) != hipSuccess) return e;
     // first round on the MFMA pass kernel; the second (R nearly I) in float64
-    // so that the stored basis is orthonormal to about one fp32 rounding.  A
-    // single block reuses the probe's factor unless the LU changed X.
-    if ((e = cholqr_round(VJ, ldx, M, bw, qw.tmp, QB, qw, false, s,
-                          c <= QB ? qw.status + 4 : nullptr)) != hipSuccess)
+    // so that the stored basis is orthonormal to about one fp32 rounding.  The
+    // first round reuses the probe's factor unless the LU changed the block.
+    if ((e = cholqr_round(VJ, ldx, M, bw, qw.tmp, QB, qw, false, s, qw.status + 4)) !=
+        hipSuccess)
       return e;
     if ((e = cholqr_round(qw.tmp, QB, M, bw, qw.q + j0, qw.ldq, qw, true, s)) != hipSuccess)
       return e;

@@ -96,10 +96,15 @@ def test_getrf_zero_column_reports_step(h):
 
 
 # ---------------------------------------------------------------- a5: thin QR
-@pytest.mark.parametrize("M,c,seed", [(2000, 30, 1), (5000, 110, 2), (3000, 200, 3), (600, 300, 4)])
-def test_thin_qr_orthonormal_and_same_range(h, M, c, seed):
+@pytest.mark.parametrize("M,c,seed,tau", [(2000, 30, 1, 40.0), (5000, 110, 2, 40.0),
+                                          (3000, 200, 3, 40.0), (600, 300, 4, 40.0),
+                                          # column scales down to e^-25 and e^-32: the
+                                          # float64 Gram of every block is far beyond
+                                          # the probe's limit, so each block takes the LU
+                                          (3000, 200, 5, 8.0), (2500, 260, 6, 8.0)])
+def test_thin_qr_orthonormal_and_same_range(h, M, c, seed, tau):
     rng = np.random.default_rng(seed)
-    X = (rng.standard_normal((M, c)) @ np.diag(np.exp(-np.arange(c) / 40.0))).astype(np.float32)
+    X = (rng.standard_normal((M, c)) @ np.diag(np.exp(-np.arange(c) / tau))).astype(np.float32)
     Q = host(h.thin_qr(dev(X)))
     eta = np.max(np.abs(Q.T.astype(np.float64) @ Q - np.eye(c)))
     print(f"M {M} c {c}: max |Q^T Q - I| = {eta:.2e}")
