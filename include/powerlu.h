@@ -57,10 +57,17 @@ typedef enum {
                               the contraction index: the smallest 2^e, e >= -127, with
                               max|x| / 2^e <= 448 */
   PLU_PREC_FORMAT_MASK = 15,
-  PLU_PREC_REFINE_LAST = 16 /* flag, OR-ed with BF16 or FP8_E4M3: the last of the v-1
+  PLU_PREC_REFINE_LAST = 16, /* flag, OR-ed with BF16 or FP8_E4M3: the last of the v-1
                               passes of Alg. 7 (the one whose result the final QR
                               orthonormalizes) also runs on the fp32 A, re-projecting the
                               rounded iterate; for v = 2 nothing is then rounded */
+  PLU_PREC_REFINE_TWO = 32  /* flag, OR-ed with BF16 or FP8_E4M3 (instead of REFINE_LAST):
+                              the last two of the v-1 passes of Alg. 7 -- the A X and
+                              A^T Y of its final loop iteration -- run on the fp32 A, one
+                              full fp32 power step on the basis the rounded passes
+                              found; for v <= 3 nothing is then rounded.  The E4M3 form
+                              needs it to stay within 1.05x of the exact residual when
+                              the rounding error of A exceeds sigma_{k+1} */
 } plu_prec;
 
 /* Storage order of the input matrix A (the paper's A is m x n, Def. 1.1).
@@ -112,7 +119,7 @@ const char* plu_status_string(int status);
  *   prec   arithmetic of the v-1 passes inside Alg. 7: FP32 (MFMA fp32),
  *          BF16 or FP8_E4M3 (A and the iterate rounded to that format, see
  *          plu_prec; exact products on the matrix cores with fp32
- *          accumulation), optionally | PLU_PREC_REFINE_LAST.  The final pass
+ *          accumulation), optionally | PLU_PREC_REFINE_LAST or | PLU_PREC_REFINE_TWO.  The final pass
  *          Y = A V(:,1:k) always runs in FP32 on the fp32 A: it is the
  *          refinement pass of the precision form.
  *          The rounded copies of A cost 4 m n (BF16) or 2 m n (FP8) bytes

@@ -42,6 +42,12 @@ design notes of the repository):
       QR steps and the indicator stay exact.  With exact_last, the last of
       the v - 1 passes (the one feeding the final QR) is exact too: a
       refinement pass that re-projects the rounded iterate with the exact A.
+  R22 Two exact closing passes (exact_tail = 2): the last two of the v - 1
+      passes of Alg. 7 -- the A X and A^T Y of the loop's final iteration --
+      are exact, one exact power step applied to the basis the rounded
+      passes found.  This is the stronger refinement taken when one exact
+      pass leaves the rounded form's residual above 1.05x the exact one's
+      (the E4M3 form at rank 200 of the 32768^2 workload).
 
 Pins: see tests/test_oracle_pins.py (GETRF against LAPACK and the textbook
 definition, crafted ties, zero columns; thin QR against exact arithmetic;
@@ -146,7 +152,7 @@ class RangeRecord:
 
 def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
                 record: RangeRecord | None = None, pass_round=None,
-                exact_last: bool = False) -> np.ndarray:
+                exact_last: bool = False, exact_tail: int = 0) -> np.ndarray:
     """Alg. 7.  Returns an orthonormal n x l basis V of (A^T A)^P A^T Omega
     (v even, Omega m x l) or (A^T A)^P Omega (v odd, Omega n x l), with
     P = floor((v - 1) / 2).  Makes v - 1 passes over A; the caller's final
@@ -162,6 +168,9 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
     A^T X), and is accumulated exactly.  Nothing else is rounded.
     exact_last: the last of the v - 1 products (the one whose result the
     final QR orthonormalizes) is exact even when pass_round is given.
+    exact_tail: the last exact_tail of the v - 1 products are exact
+    (exact_last is exact_tail = 1; 2 makes the closing A X, A^T Y pair one
+    exact power step on the rounded iterate, reading R22).
     """
     if v < 2:
         raise ValueError("v >= 2 (Alg. 7 REQUIRE)")
@@ -169,11 +178,12 @@ def range_basis(A: np.ndarray, Omega: np.ndarray, v: int,
     m, n = A.shape
     P = (v - 1) // 2
     rec = record if record is not None else RangeRecord()
+    tail = max(int(exact_tail), 1 if exact_last else 0)
 
     def rounded():         # is the product about to be taken a rounded one?
         if pass_round is None:
             return False
-        return not (exact_last and rec.passes - start == v - 2)
+        return rec.passes - start < v - 1 - tail
 
     def times(X):          # A X, the products of the loop
         if not rounded():
@@ -258,7 +268,7 @@ def assemble(A: np.ndarray, Vk: np.ndarray, Y: np.ndarray | None = None) -> Fact
 
 
 def powerlu(A: np.ndarray, k: int, Omega: np.ndarray, v: int,
-            pass_round=None, exact_last: bool = False) -> Factorization:
+            pass_round=None, exact_last: bool = False, exact_tail: int = 0) -> Factorization:
     """PowerLU (Alg. 5 with Alg. 7 in place of steps 1-2).  Omega is the
     caller's Gaussian matrix: m x l for even v, n x l for odd v, l = k + q.
     pass_round, exact_last: precision form of the v - 1 range passes (see
@@ -269,7 +279,7 @@ def powerlu(A: np.ndarray, k: int, Omega: np.ndarray, v: int,
     if not (1 <= k <= l < min(m, n)):
         raise ValueError("need 1 <= k <= l < min(m, n)")
     rec = RangeRecord()
-    V = range_basis(A, Omega, v, rec, pass_round, exact_last)
+    V = range_basis(A, Omega, v, rec, pass_round, exact_last, exact_tail)
     fac = assemble(A, V[:, :k])
     fac.passes = rec.passes + 1
     fac.normA2 = float(np.sum(A * A))
@@ -319,7 +329,7 @@ def rank_rule(normA2: float, colnorm2: np.ndarray, eps: float, b: int,
 
 def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
                column_mode: bool = True, pass_round=None,
-               exact_last: bool = False, restart_omegas=()) -> Factorization:
+               exact_last: bool = False, restart_omegas=(), exact_tail: int = 0) -> Factorization:
     """PowerLU_FP (Alg. 9) on top of Alg. 8 (block rule) or Alg. 11 (column
     rule).  l = Omega.shape[1] must be a multiple of b (Sec. 4.1, l = s b).
     pass_round: precision form of the v - 1 range passes; G = A V is exact.
@@ -341,7 +351,7 @@ def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
         raise ValueError("need b | l and (rounds * l) < min(m, n)")
     normA2 = float(np.sum(A * A))
     rec = RangeRecord()
-    V = range_basis(A, Omega, v, rec, pass_round, exact_last)
+    V = range_basis(A, Omega, v, rec, pass_round, exact_last, exact_tail)
     G = A @ V
     colnorm2 = np.sum(G * G, axis=0)
     k, ok = rank_rule(normA2, colnorm2, eps, b, column_mode)
@@ -352,7 +362,7 @@ def powerlu_fp(A: np.ndarray, eps: float, b: int, Omega: np.ndarray, v: int,
         used += 1
         R = A - G @ V.T                                  # remainder A (I - V V^T)
         Vr = range_basis(R, np.asarray(Om, dtype=np.float64), v, RangeRecord(),
-                         pass_round, exact_last)
+                         pass_round, exact_last, exact_tail)
         for _ in range(2):                               # against the columns kept so far
             Vr = Vr - V @ (V.T @ Vr)
         Vr = thin_qr(Vr)

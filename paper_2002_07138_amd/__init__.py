@@ -28,6 +28,7 @@ PREC_FP32 = 0
 PREC_BF16 = 1
 PREC_FP8_E4M3 = 2
 PREC_REFINE_LAST = 16
+PREC_REFINE_TWO = 32
 LAYOUT_ROW = 0
 LAYOUT_COL = 1
 

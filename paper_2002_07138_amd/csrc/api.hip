@@ -66,8 +66,9 @@ inline bool valid_layout(int32_t layout) { return layout == PLU_ROW_MAJOR || lay
 
 bool valid_prec(int prec) {
   const int fmt = prec & PLU_PREC_FORMAT_MASK;
+  if ((prec & PLU_PREC_REFINE_LAST) && (prec & PLU_PREC_REFINE_TWO)) return false;
   return fmt >= PLU_PREC_FP32 && fmt <= PLU_PREC_FP8_E4M3 &&
-         (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST)) == 0;
+         (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST | PLU_PREC_REFINE_TWO)) == 0;
 }
 inline int64_t ru(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -662,9 +663,10 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
   const GetrfWork gw = getrf_work(h, w, 0);
   const QrWork qw = qr_work(w, w.qb, lp);
   const int fmt = prec & PLU_PREC_FORMAT_MASK;
-  const bool refine = (prec & PLU_PREC_REFINE_LAST) != 0;
+  // the last `exact_tail` of the v - 1 passes run on the fp32 A
+  const int exact_tail = (prec & PLU_PREC_REFINE_TWO) ? 2 : (prec & PLU_PREC_REFINE_LAST) ? 1 : 0;
   // the rounded copies are needed only if some pass is rounded
-  const bool any_rounded = fmt != PLU_PREC_FP32 && !(refine && v == 2);
+  const bool any_rounded = fmt != PLU_PREC_FP32 && v - 1 > exact_tail;
   if (any_rounded && fmt == PLU_PREC_BF16) {
     if ((e = convert_a_bf16(h, w, m, n, A, lda, normA2)) != hipSuccess) return e;
     first = false;
@@ -673,10 +675,10 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
     first = false;
   }
   // one of the v - 1 passes of Alg. 7 (the first one also yields ||A||_F^2);
-  // with refine, the last of them (it feeds the final QR) runs on the fp32 A
+  // with a refinement flag the last one or two of them run on the fp32 A
   int pidx = 0;
   auto pass = [&](int trans, const float* X, float* out) -> hipError_t {
-    const bool rounded = any_rounded && !(refine && pidx == v - 2);
+    const bool rounded = any_rounded && pidx < v - 1 - exact_tail;
     ++pidx;
     hipError_t r;
     if (rounded && fmt == PLU_PREC_BF16) {

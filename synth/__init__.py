@@ -19,6 +19,9 @@ Matrix families
 * ``sprand_csr``: sparse matrices like MATLAB's sprand (uniform values at
   random positions, Sec. 6.1's sparse experiment), in compressed rows;
   ``csr_dense`` expands them.
+* ``crafted_tie_matrix``: tall matrices on which partial pivoting meets exact
+  ties at every step while float32 elimination stays exact (pivot tie-break
+  tests).
 
 Seed scheme: ``seed = 1000 * workload + role`` with role 0 the left factor,
 1 the right factor, 2 the noise, 3 + s the Gaussian test matrix of run s.
@@ -33,6 +36,7 @@ from .generators import (  # noqa: F401
     gaussian_omega,
     sprand_csr,
     csr_dense,
+    crafted_tie_matrix,
     WORKLOADS,
     workload_matrix_factors,
     workload_matrix,

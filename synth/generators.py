@@ -203,6 +203,35 @@ def request_stream(count: int = 1024, rate_per_s: float = 200.0, seed: int = 500
     return out
 
 
+def crafted_tie_matrix(m: int, c: int, seed: int) -> np.ndarray:
+    """An m x c matrix (float64 values exactly representable in float32) on
+    which partial pivoting meets exact ties at its steps while every
+    elimination step stays exact in float32: the rows are C D with D a c x c
+    upper triangular matrix (diagonal +-2, +-4 or +-8, integers in [-2, 2]
+    above), C holding the unit rows, for each j one or two rows +-e_j plus
+    +-1/4 e_t (t > j) -- these tie with row j of D in column j -- and filler
+    rows with entries in {0, +-1/4, +-1/2}; rows shuffled.  Whether a given
+    seed keeps every step exact (no filler row grows into a pivot) is a
+    property checked by the tests that use it."""
+    rng = np.random.default_rng(seed)
+    D = np.triu(rng.integers(-2, 3, size=(c, c)).astype(np.float64), 1)
+    D[np.arange(c), np.arange(c)] = np.exp2(rng.integers(1, 4, size=c)) * rng.choice([-1, 1], size=c)
+    rows = [np.eye(c)]
+    for j in range(c):
+        for _ in range(rng.integers(1, 3)):
+            r = np.zeros(c)
+            r[j] = rng.choice([-1.0, 1.0])
+            if j + 1 < c:
+                r[rng.integers(j + 1, c)] += 0.25 * rng.choice([-1.0, 1.0])
+            rows.append(r[None])
+    nf = m - sum(x.shape[0] for x in rows)
+    if nf < 0:
+        raise ValueError("m too small for the tie rows")
+    rows.append(rng.choice([0.0, 0.0, 0.25, -0.25, 0.5, -0.5], size=(nf, c)))
+    X = np.concatenate(rows) @ D
+    return X[rng.permutation(m)]
+
+
 def sprand_csr(m: int, n: int, density: float, seed: int):
     """A sparse m x n matrix like MATLAB's ``sprand(m, n, density)`` (the
     sparse inputs of Sec. 6.1): uniform (0, 1) values at about

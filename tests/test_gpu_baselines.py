@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 
 import paper_2002_07138_amd as plu
-from tests.gpu_common import torch, have_gpu, handle, dev, host, pivot_prefix_ok
+from tests.gpu_common import torch, have_gpu, handle, dev, host, assert_pivots, assert_factors_close
 from oracle import baselines as Bo
 from oracle import powerlu as O
 from synth import gaussian_omega, lowrank_plus_noise, spectrum
@@ -62,7 +62,7 @@ def _proj(X):
     return Q @ Q.T
 
 
-def _check_randlu(h, A, k, p_over, pw, seed, col=False):
+def _check_randlu(h, A, k, p_over, pw, seed, col=False, expect=(None, None)):
     m, n = A.shape
     l = k + p_over
     Om = gaussian_omega(n, l, seed=seed)
@@ -75,14 +75,10 @@ def _check_randlu(h, A, k, p_over, pw, seed, col=False):
     r_ref = O.relative_residual(A, ref.p, ref.q, ref.L, ref.U)
     print(f"{m}x{n} k {k} l {l} p {pw} col {col}: residual gpu {r_gpu:.5g} oracle {r_ref:.5g}")
     assert r_gpu <= 1.05 * r_ref + 64 * U32, (r_gpu, r_ref)
-    okp, stop_p = pivot_prefix_ok(p[:k], ref.p[:k], ref.lu1.gaps, TAU)
-    assert okp, f"row pivots differ before step {stop_p}"
-    if stop_p == k:
-        okq, stop_q = pivot_prefix_ok(q[:k], ref.q[:k], ref.lu2.gaps, TAU)
-        assert okq, f"column pivots differ before step {stop_q}"
-        if stop_q == k:
-            assert np.max(np.abs(L - ref.L)) <= 1e-3 * np.max(np.abs(ref.L))
-            assert np.max(np.abs(U - ref.U)) <= 1e-3
+    sp = assert_pivots(p[:k], ref.p[:k], ref.lu1.gaps, TAU, expect[0], "row pivots")
+    sq = assert_pivots(q[:k], ref.q[:k], ref.lu2.gaps, TAU, expect[1], "column pivots")
+    if sp == k and sq == k:
+        assert_factors_close(L, U, ref.L, ref.U)
     assert np.allclose(np.diag(U[:, :k]), 1.0) and np.all(np.tril(U[:, :k], -1) == 0.0)
     assert np.max(np.abs(U)) <= 1.0 + 1e-6
     return f, ref, r_gpu
@@ -93,7 +89,9 @@ def _check_randlu(h, A, k, p_over, pw, seed, col=False):
                                           (2000, 1999, 100, 10)])
 def test_randlu_against_oracle(h, m, n, k, p_over, pw):
     A = lowrank_plus_noise(m, n, spectrum("exp", min(m, n) // 2, tau=20.0), m + 3, n + 4, 1e-6, 5)
-    _check_randlu(h, A, k, p_over, pw, seed=m + 7 * pw)
+    # one input has an oracle row-pivot gap of 4.4e-5 (< tau) at step 95
+    expect = (95, None) if (m, k, pw) == (2000, 100, 1) else (None, None)
+    _check_randlu(h, A, k, p_over, pw, seed=m + 7 * pw, expect=expect)
 
 
 @pytest.mark.parametrize("pw", [0, 1])

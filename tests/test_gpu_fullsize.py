@@ -14,7 +14,7 @@ k = 100, l = 110 -- the shapes, tuned plans and kernels the benchmark times.
 import numpy as np
 import pytest
 
-from tests.gpu_common import torch, have_gpu, handle, dev, host, pivot_prefix_ok
+from tests.gpu_common import torch, have_gpu, handle, dev, host, assert_pivots, assert_factors_close
 from oracle import powerlu as O
 from synth import WORKLOADS, gaussian_omega, workload_matrix
 
@@ -82,11 +82,11 @@ def test_full_size_fixed_rank_against_oracle(h, workload):
     A64 = A.astype(np.float64)
     ref = O.powerlu(A64, K, Om.astype(np.float64), v)
     assert sorted(p.tolist()) == list(range(m)) and sorted(q.tolist()) == list(range(n))
-    okp, stop_p = pivot_prefix_ok(p[:K], ref.p[:K], ref.lu1.gaps, TAU)
-    assert okp, f"row pivots differ before step {stop_p}"
-    if stop_p == K:
-        okq, stop_q = pivot_prefix_ok(q[:K], ref.q[:K], ref.lu2.gaps, TAU)
-        assert okq, f"column pivots differ before step {stop_q}"
+    # every oracle gap of both final LUs is above tau on this input (the
+    # smallest are 1.4e-4 and 2.8e-4): both orders are compared in full
+    stop_p = assert_pivots(p[:K], ref.p[:K], ref.lu1.gaps, TAU, None, "row pivots")
+    assert_pivots(q[:K], ref.q[:K], ref.lu2.gaps, TAU, None, "column pivots")
+    assert_factors_close(L, U, ref.L, ref.U)
     r_gpu = O.relative_residual(A64, p, q, L, U)
     r_ref = O.relative_residual(A64, ref.p, ref.q, ref.L, ref.U)
     print(f"20000^2 v {v}: residual gpu {r_gpu:.8g} oracle {r_ref:.8g}; pivots equal to "

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import paper_2002_07138_amd as plu
-from tests.gpu_common import torch, have_gpu, handle, dev, host, pivot_prefix_ok
+from tests.gpu_common import torch, have_gpu, handle, dev, host, assert_pivots, assert_factors_close
 from oracle import baselines as Bo
 from oracle import powerlu as O
 from synth import csr_dense, gaussian_omega, sprand_csr
@@ -126,14 +126,10 @@ def test_sparse_fixed_rank_against_oracle(h, m, n, density, k, p_over, v):
     print(f"sparse {m}x{n} d {density} k {k} v {v}: residual gpu {r_gpu:.6g} oracle {r_ref:.6g}")
     assert abs(f.info["normA2"] - float(np.sum(A * A))) <= 1e-12 * float(np.sum(A * A))
     assert r_gpu <= 1.05 * r_ref + 64 * U32
-    okp, stop_p = pivot_prefix_ok(p[:k], ref.p[:k], ref.lu1.gaps, TAU)
-    assert okp, f"row pivots differ before step {stop_p}"
-    if stop_p == k:
-        okq, stop_q = pivot_prefix_ok(q[:k], ref.q[:k], ref.lu2.gaps, TAU)
-        assert okq, f"column pivots differ before step {stop_q}"
-        if stop_q == k:
-            assert np.max(np.abs(L - ref.L)) <= 1e-3 * np.max(np.abs(ref.L))
-            assert np.max(np.abs(U - ref.U)) <= 1e-3
+    sp = assert_pivots(p[:k], ref.p[:k], ref.lu1.gaps, TAU, None, "row pivots")
+    sq = assert_pivots(q[:k], ref.q[:k], ref.lu2.gaps, TAU, None, "column pivots")
+    if sp == k and sq == k:
+        assert_factors_close(L, U, ref.L, ref.U)
     S.close()
 
 

@@ -4,7 +4,8 @@ Each test names the step of the path it covers."""
 import numpy as np
 import pytest
 
-from tests.gpu_common import torch, have_gpu, handle, dev, host, equal_up_to_signs, pivot_prefix_ok
+from tests.gpu_common import torch, have_gpu, handle, dev, host, equal_up_to_signs, assert_pivots
+from tests.test_crafted_ties import TIE_CASES
 from oracle import powerlu as O
 from oracle import philox as PH
 from synth import gaussian_omega, lowrank_plus_noise, spectrum
@@ -55,33 +56,29 @@ def test_getrf_matches_oracle(h, M, c, seed):
     perm, U, info = h.getrf(F)
     ref = O.getrf(X.astype(np.float64))
     V_ref, _ = O.lur(X.astype(np.float64))
-    ok, stop = pivot_prefix_ok(host(perm)[:c], ref.perm[:c], ref.gaps, 1e-4)
-    assert ok, f"pivots differ before step {stop}"
-    if stop == c:
-        assert np.array_equal(host(perm), ref.perm)
-        assert np.max(np.abs(host(F) - V_ref)) < 1e-3
-        assert np.max(np.abs(host(U) - ref.U)) <= 1e-4 * np.max(np.abs(ref.U)) * np.sqrt(c) + 1e-5
+    # these Gaussian inputs have every oracle gap above 1e-4: compared in full
+    assert_pivots(host(perm)[:c], ref.perm[:c], ref.gaps, 1e-4)
+    assert np.array_equal(host(perm), ref.perm)
+    assert np.max(np.abs(host(F) - V_ref)) < 1e-3
+    assert np.max(np.abs(host(U) - ref.U)) <= 1e-4 * np.max(np.abs(ref.U)) * np.sqrt(c) + 1e-5
     assert info["zero_pivot_step"] == -1
 
 
-def test_getrf_crafted_ties_follow_lapack_order(h):
-    """Exact ties (small integers, identical in fp32 and fp64): the first
-    maximum in the current row order wins, as in the oracle."""
-    rng = np.random.default_rng(9)
-    X = rng.integers(-3, 4, size=(700, 40)).astype(np.float32)
-    X[:, 0] = 0.0
-    X[[5, 17, 600], 0] = [3.0, -3.0, 3.0]
-    F = dev(X)
+@pytest.mark.parametrize("M,c,seed", TIE_CASES)
+def test_getrf_crafted_ties_follow_lapack_order(h, M, c, seed):
+    """Exact ties at every step, on inputs whose elimination is exact in
+    float32 (checked on the CPU by tests/test_crafted_ties.py): the first
+    maximum in the current row order wins at every one of the c steps, as in
+    the oracle, and the factors are bit-identical."""
+    X = crafted_tie_matrix(M, c, seed)
+    F = dev(X.astype(np.float32))
     perm, U, info = h.getrf(F)
-    ref = O.getrf(X.astype(np.float64))
-    # exact ties are resolved identically only while the arithmetic stays exact
-    assert host(perm)[0] == ref.perm[0] == 5
-    exact_steps = 0
-    for j in range(40):
-        if host(perm)[j] != ref.perm[j]:
-            break
-        exact_steps += 1
-    assert exact_steps >= 1
+    ref = O.getrf(X)
+    V_ref, _ = O.lur(X)
+    assert int(np.sum(np.asarray(ref.gaps[:c]) == 0.0)) == c
+    assert np.array_equal(host(perm), ref.perm)
+    assert np.array_equal(host(U).astype(np.float64), ref.U)
+    assert np.array_equal(host(F).astype(np.float64), V_ref)
 
 
 def test_getrf_zero_column_reports_step(h):

@@ -118,6 +118,31 @@ def test_precision_form_rounds_exactly_the_range_passes():
         O.powerlu(A, 8, Om, v, pass_round=rec, exact_last=True)
         assert len(calls) == 2 * (v - 2)
         assert [ax for (shape, ax) in calls[0::2]] == a_axes[:v - 2]
+        # with exact_tail = 2 the last two are not (none of them when v <= 3)
+        calls.clear()
+        O.powerlu(A, 8, Om, v, pass_round=rec, exact_tail=2)
+        assert len(calls) == 2 * max(v - 3, 0)
+        assert [ax for (shape, ax) in calls[0::2]] == a_axes[:max(v - 3, 0)]
+        # exact_last is exact_tail = 1
+        calls.clear()
+        O.powerlu(A, 8, Om, v, pass_round=rec, exact_tail=1)
+        assert len(calls) == 2 * (v - 2)
+
+
+@pytest.mark.parametrize("v", [2, 3, 4, 5])
+def test_exact_tail_covering_every_pass_is_the_exact_algorithm(v):
+    """With exact_tail >= v - 1 no range product is rounded: the factors are
+    the exact algorithm's bit for bit, under a real (E4M3) rounding; with
+    fewer exact passes they differ."""
+    A = lowrank_plus_noise(140, 100, spectrum("exp", 30, tau=5.0), 4, 5, 1e-6, 6, dtype=np.float64)
+    Om = gaussian_omega(140 if v % 2 == 0 else 100, 12, seed=30 + v).astype(np.float64)
+    f0 = O.powerlu(A, 8, Om, v)
+    f1 = O.powerlu(A, 8, Om, v, pass_round=LP.round_mx_e4m3, exact_tail=v - 1)
+    assert np.array_equal(f0.L, f1.L) and np.array_equal(f0.U, f1.U)
+    assert np.array_equal(f0.p, f1.p) and np.array_equal(f0.q, f1.q)
+    if v >= 3:
+        f2 = O.powerlu(A, 8, Om, v, pass_round=LP.round_mx_e4m3, exact_tail=v - 2)
+        assert not np.array_equal(f0.L, f2.L)
 
 
 @pytest.mark.parametrize("v", [2, 3, 4])
