@@ -53,8 +53,12 @@ def assert_pivots(gpu_perm, ref_perm, gaps, tau, expect_steps=None, what="pivots
     compared), or exactly expect_steps (an input whose oracle gap sequence is
     known to fall below tau at that step).  Returns the compared length."""
     c = len(gaps)
-    ok, stop = pivot_prefix_ok(np.asarray(gpu_perm)[:c], np.asarray(ref_perm)[:c], gaps, tau)
-    assert ok, f"{what} differ from the oracle's before step {stop}"
+    g, r = np.asarray(gpu_perm)[:c], np.asarray(ref_perm)[:c]
+    ok, stop = pivot_prefix_ok(g, r, gaps, tau)
+    if not ok:
+        j = int(np.flatnonzero(g[:stop] != r[:stop])[0])
+        raise AssertionError(f"{what} differ from the oracle's at step {j} (oracle gap there "
+                             f"{gaps[j]:.3e}, tau {tau:g}, {stop} steps above tau)")
     want = c if expect_steps is None else expect_steps
     assert stop == want, (f"{what}: the oracle's gap falls below tau = {tau:g} at step {stop} "
                           f"(expected {want} of {c} steps compared)")
@@ -75,3 +79,34 @@ def assert_factors_close(L, U, ref_L, ref_U, l_tol=1e-4, u_tol=1e-3):
     assert dl <= l_tol * float(np.max(np.abs(ref_L))), ("L", dl, float(np.max(np.abs(ref_L))))
     assert du <= u_tol, ("U", du)
     return dl / float(np.max(np.abs(ref_L))), du
+
+
+def column_deviation(Vg, Vr):
+    """Per column j: max|Vg[:, j] - s Vr[:, j]| / max|Vr[:, j]| with s = +-1
+    the sign that aligns the two (a thin-Q basis is unique up to signs)."""
+    out = np.empty(Vr.shape[1])
+    for j in range(Vr.shape[1]):
+        s = np.sign(Vg[:, j] @ Vr[:, j]) or 1.0
+        out[j] = np.max(np.abs(Vg[:, j] - s * Vr[:, j])) / np.max(np.abs(Vr[:, j]))
+    return out
+
+
+def assert_pivots_measured(gpu_perm, ref_perm, gaps, col_dev, margin=10.0, tau=1e-4,
+                           min_steps=0, what="pivots"):
+    """Pivot parity with a threshold from the measured deviation of the GPU's
+    basis (the parity rule's tau = a multiple of the GPU's relative deviation
+    from the oracle): step j is decided above rounding when the oracle's gap
+    there exceeds max(tau, margin x the largest column deviation among the
+    first j + 1 columns).  The orders must agree up to the first step that is
+    not, and at least min_steps steps must be compared.  Returns that count."""
+    c = len(gaps)
+    thr = np.maximum(tau, margin * np.maximum.accumulate(np.asarray(col_dev)[:c]))
+    below = np.flatnonzero(np.asarray(gaps[:c]) < thr)
+    stop = int(below[0]) if len(below) else c
+    g, r = np.asarray(gpu_perm)[:stop], np.asarray(ref_perm)[:stop]
+    if not np.array_equal(g, r):
+        j = int(np.flatnonzero(g != r)[0])
+        raise AssertionError(f"{what} differ from the oracle's at step {j} (oracle gap "
+                             f"{gaps[j]:.3e}, threshold {thr[j]:.3e})")
+    assert stop >= min_steps, f"{what}: only {stop} steps decided above the measured deviation"
+    return stop

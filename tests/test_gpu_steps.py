@@ -8,7 +8,7 @@ from tests.gpu_common import torch, have_gpu, handle, dev, host, equal_up_to_sig
 from tests.test_crafted_ties import TIE_CASES
 from oracle import powerlu as O
 from oracle import philox as PH
-from synth import gaussian_omega, lowrank_plus_noise, spectrum
+from synth import crafted_tie_matrix, gaussian_omega, lowrank_plus_noise, spectrum
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
 
