@@ -24,8 +24,22 @@
  *  - L (m x k) is lower trapezoidal with diag(L) = diag(U2); U (k x n) is unit
  *    upper trapezoidal with |u_ij| <= 1 (U = L2^T, Alg. 5 step 8).
  *  - Return value: 0 on success; -i when argument i (1-based) is invalid;
- *    a positive PLU_* code otherwise.  The library keeps workspace on the
- *    handle and grows it on demand (PLU_ERR_OOM if that fails).
+ *    a positive PLU_* code otherwise.
+ *  - Workspace: plu_fixed_rank and plu_fixed_precision take an optional
+ *    caller workspace (work, work_bytes: device memory, any alignment, at
+ *    least plu_workspace_size bytes; owned by the caller, contents on entry
+ *    irrelevant, clobbered by the call; one call at a time may use it).
+ *    With work = NULL -- and for every other call -- the library keeps a
+ *    workspace on the handle and grows it on demand (PLU_ERR_OOM if that
+ *    fails).
+ *  - Graph capture: a call whose workspace already exists (a caller
+ *    workspace, or an earlier call of the same shape on the handle) makes no
+ *    allocation and no synchronization when info is NULL, so it can be
+ *    captured into a HIP graph on the handle's stream (plu_fixed_rank, and
+ *    plu_fixed_precision with max_rounds = 1).  Captured calls run the
+ *    default split of the passes unless an eager call of the same shape has
+ *    already tuned it in the process; each replay recomputes from the
+ *    current contents of the captured buffers.
  */
 #ifndef POWERLU_H
 #define POWERLU_H
@@ -102,11 +116,13 @@ typedef struct {
 int plu_create(plu_handle* h, int device, void* hip_stream);
 int plu_destroy(plu_handle h);
 int plu_set_stream(plu_handle h, void* hip_stream);
-/* Bytes of device workspace the handle will hold for a fixed-rank or
- * fixed-precision call of this shape, sketch width l and pass precision
- * (the bfloat16 form adds two rounded copies of A, 4 m n bytes). */
-int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, int32_t prec,
-                       size_t* bytes);
+/* Bytes of device workspace a fixed-rank call (l = k + p_over, max_rounds
+ * = 1) or fixed-precision call (l its sketch width, with its max_rounds) of
+ * this shape and pass precision needs, as a caller workspace or on the
+ * handle (the bfloat16 form adds two rounded copies of A, 4 m n bytes; the
+ * E4M3 form 2 m n bytes and scales).                                      */
+int plu_workspace_size(plu_handle h, int64_t m, int64_t n, int32_t l, int32_t max_rounds,
+                       int32_t prec, size_t* bytes);
 const char* plu_status_string(int status);
 
 /* ---- Fixed-rank problem (Def. 1.1, Sec. 1) solved by PowerLU: Alg. 5 with
@@ -129,12 +145,14 @@ const char* plu_status_string(int status);
  *          the Philox4x32-10 layout of plu_gaussian.
  *   p, q   device int32 outputs, lengths m and n.
  *   L, U   device outputs: L m x k (ldl >= k), U k x n (ldu >= n).
+ *   work, work_bytes  nullable caller workspace (see the conventions);
+ *          -20 when work_bytes is too small.
  *   info   host, nullable (non-NULL synchronizes).                        */
 int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
                    int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
                    const float* Omega, uint64_t seed,
                    int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
-                   plu_info* info);
+                   void* work, size_t work_bytes, plu_info* info);
 
 /* ---- Fixed-precision problem (Sec. 1, last paragraph of Def. 1.1's
  * discussion) solved by PowerLU_FP: Alg. 9 on top of Alg. 8 (block rule) or
@@ -154,16 +172,29 @@ int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const flo
  *          round.  Needs l * max_rounds columns of L and rows of U.
  *   L, U   device outputs with room for l * max_rounds columns / rows:
  *          L m x (l max_rounds) (ldl >= l max_rounds), U (l max_rounds) x n
- *          (ldu >= n); only the leading rank columns/rows are written.
- *   rank_out host int32*, nullable: receives k (the call synchronizes to read
- *          it; the rank is also in info).
+ *          (ldu >= n); the leading rank columns / rows hold the factors,
+ *          the rest is unspecified.
+ *   rank_dev device int32*, nullable: receives the rank k.  With
+ *          max_rounds = 1 the rank never leaves the device: the rule of
+ *          Alg. 8 / Alg. 11 runs in a kernel, and the assembly's launches,
+ *          sized for l columns, stop at the rank they read there, so the
+ *          call is asynchronous when info is NULL (and capturable).  k = 0
+ *          (a zero matrix, or a non-finite A: then info reports
+ *          PLU_ERR_NONFINITE) leaves p and q the identity.
+ *   work, work_bytes  nullable caller workspace; -24 when too small.
+ *   info   host, nullable: synchronizes and reports the rank, the status
+ *          and whether eps was reached.
  * If eps is not met within l * max_rounds columns, that factorization is
- * returned with PLU_TOL_NOT_REACHED.  A zero matrix gives rank 0.         */
+ * returned (status PLU_TOL_NOT_REACHED in info, and as the return value
+ * when max_rounds > 1 or info is given).  A zero matrix gives rank 0.
+ * With the pivot trace on, each final LU of a max_rounds = 1 call records l
+ * entries, of which the first rank are its steps.                         */
 int plu_fixed_precision(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
                         int64_t lda, double eps, int32_t b, int32_t l, int32_t v,
                         int32_t column_exact, int32_t max_rounds, int32_t prec,
                         const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
-                        int64_t ldl, float* U, int64_t ldu, int32_t* rank_out, plu_info* info);
+                        int64_t ldl, float* U, int64_t ldu, int32_t* rank_dev, void* work,
+                        size_t work_bytes, plu_info* info);
 
 /* ---- Single-pass randomized LU (Alg. 10, Sec. 5): G = A^T Omega and
  * H = A G from one pass over A, [L1, U1, P] = lu(H), [L2, U2, Q] =
@@ -246,10 +277,11 @@ int plu_randsvd(plu_handle h, int32_t layout, int64_t m, int64_t n, const float*
  *     stream.
  *   plu_sparse_fixed_rank, plu_sparse_fixed_precision, plu_sparse_randlu,
  *   plu_sparse_randsvd: as plu_fixed_rank, plu_fixed_precision, plu_randlu
- *     and plu_randsvd with (layout, m, n, A, lda) replaced by sp; m and n
- *     are the matrix's; prec must be PLU_PREC_FP32.  Argument errors are
- *     -(index in this signature): the dense index minus 4 for every argument
- *     after sp.                                                            */
+ *     and plu_randsvd with (layout, m, n, A, lda) replaced by sp and without
+ *     the caller workspace (they use the handle's); m and n are the
+ *     matrix's; prec must be PLU_PREC_FP32.  Argument errors are -(index in
+ *     this signature): the dense index minus 4 for every argument after sp.
+ */
 typedef struct plu_sparse_s* plu_sparse;
 int plu_sparse_create(plu_handle h, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
                       const int32_t* colidx, const float* vals, plu_sparse* out);
@@ -262,7 +294,7 @@ int plu_sparse_fixed_rank(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over
 int plu_sparse_fixed_precision(plu_handle h, plu_sparse sp, double eps, int32_t b, int32_t l,
                                int32_t v, int32_t column_exact, int32_t max_rounds, int32_t prec,
                                const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
-                               int64_t ldl, float* U, int64_t ldu, int32_t* rank_out,
+                               int64_t ldl, float* U, int64_t ldu, int32_t* rank_dev,
                                plu_info* info);
 int plu_sparse_randlu(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, int32_t pw,
                       const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
@@ -294,10 +326,12 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
  *                          rounded copies); others give status
  *                          PLU_ERR_NOT_IMPLEMENTED.
  * Outputs (host, in each request): rank, status and info; the call
- * synchronizes once for the fixed-precision ranks and once at the end.
- * flags: PLU_BATCH_GRAPH captures the merged launch sequence of a batch of
- * fixed-rank problems into a HIP graph kept by the handle and replays it
- * when the next call has the same requests (same shapes and pointers).
+ * synchronizes once, at the end (the fixed-precision ranks stay on the
+ * device until then, as in plu_fixed_precision).
+ * flags: PLU_BATCH_GRAPH captures the merged launch sequence of the batch
+ * (fixed-rank and fixed-precision problems alike) into a HIP graph kept by
+ * the handle and replays it when the next call has the same requests (same
+ * shapes and pointers).
  * Returns PLU_OK, or -3 when some request is invalid (its status then holds
  * -i for its i-th field, counted from 1 in declaration order).             */
 /* ---- Pivot trace: the pivot rows and relative pivot gaps of every GETRF of

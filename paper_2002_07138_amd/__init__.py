@@ -110,13 +110,13 @@ def _lib():
             "plu_create": [ctypes.POINTER(vp), ctypes.c_int, vp],
             "plu_destroy": [vp],
             "plu_set_stream": [vp, vp],
-            "plu_workspace_size": [vp, i64, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "plu_workspace_size": [vp, i64, i64, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
             "plu_status_string": [ctypes.c_int],
             "plu_fixed_rank": [vp, i32, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
-                               vp, vp, vp, i64, vp, i64, pinfo],
+                               vp, vp, vp, i64, vp, i64, vp, ctypes.c_size_t, pinfo],
             "plu_fixed_precision": [vp, i32, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, i32, vp,
-                                    u64,
-                                    vp, vp, vp, i64, vp, i64, ctypes.POINTER(i32), pinfo],
+                                    u64, vp, vp, vp, i64, vp, i64, vp, vp, ctypes.c_size_t,
+                                    pinfo],
             "plu_residual": [vp, i32, i64, i64, vp, i64, vp, vp, i32, vp, i64, vp, i64,
                              ctypes.POINTER(dbl)],
             "plu_gaussian": [vp, i64, i64, u64, vp, i64],
@@ -141,7 +141,7 @@ def _lib():
             "plu_sparse_fixed_rank": [vp, vp, i32, i32, i32, i32, vp, u64, vp, vp, vp, i64, vp, i64,
                                       pinfo],
             "plu_sparse_fixed_precision": [vp, vp, dbl, i32, i32, i32, i32, i32, i32, vp, u64, vp,
-                                           vp, vp, i64, vp, i64, ctypes.POINTER(i32), pinfo],
+                                           vp, vp, i64, vp, i64, vp, pinfo],
             "plu_sparse_randlu": [vp, vp, i32, i32, i32, vp, u64, vp, vp, vp, i64, vp, i64, pinfo],
             "plu_sparse_randsvd": [vp, vp, i32, i32, i32, vp, u64, vp, i64, vp, vp, i64, pinfo],
             "plu_pivot_trace": [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32,
@@ -398,8 +398,15 @@ class Handle:
         return out
 
     # ------------------------------------------------------------- problems
+    def workspace_size(self, m, n, l, prec=PREC_FP32, max_rounds=1):
+        """Bytes of caller workspace a call of this shape needs (plu_workspace_size)."""
+        b = ctypes.c_size_t()
+        self._rc(_lib().plu_workspace_size(self._h, m, n, l, int(max_rounds), prec,
+                                           ctypes.byref(b)), "plu_workspace_size")
+        return b.value
+
     def fixed_rank(self, A, k, p_over, v, Omega=None, seed=0, prec=PREC_FP32, sync_info=True,
-                   out=None):
+                   out=None, work=None):
         """PowerLU (Alg. 5 with Alg. 7); A is a device tensor or a SparseMatrix."""
         t = self._torch
         _check_mat(Omega, "Omega")
@@ -423,7 +430,9 @@ class Handle:
         else:
             rc = _lib().plu_fixed_rank(self._h, lay, m, n, _ptr(A), lda, k, p_over, v, prec,
                                        _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L), _ld(L),
-                                       _ptr(U), _ld(U), pinfo)
+                                       _ptr(U), _ld(U), _ptr(work),
+                                       0 if work is None else work.numel() * work.element_size(),
+                                       pinfo)
         self._rc(rc, "plu_fixed_rank", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
 
@@ -496,8 +505,13 @@ class Handle:
         return U, S, V, (info.as_dict() if sync_info else {})
 
     def fixed_precision(self, A, eps, b, l=0, v=4, column_exact=True, Omega=None, seed=0,
-                        prec=PREC_FP32, max_rounds=1):
-        """PowerLU_FP (Alg. 9); A is a device tensor or a SparseMatrix."""
+                        prec=PREC_FP32, max_rounds=1, sync_info=True, out=None, work=None):
+        """PowerLU_FP (Alg. 9); A is a device tensor or a SparseMatrix.
+
+        sync_info=True: synchronizes and returns Factors trimmed to the rank.
+        sync_info=False: returns at once (max_rounds = 1): Factors with the
+        full-capacity L, U and rank = the device int32 tensor (1,) the call
+        writes the rank into.  out = (p, q, L, U, rank) reuses buffers."""
         t = self._torch
         _check_mat(Omega, "Omega")
         sparse = isinstance(A, SparseMatrix)
@@ -505,26 +519,33 @@ class Handle:
         m, n = A.shape
         dev = A.device
         lcap = (l if l else min(50 * b, b * ((min(m, n) - 1) // b))) * max(int(max_rounds), 1)
-        p = t.empty(m, dtype=t.int32, device=dev)
-        q = t.empty(n, dtype=t.int32, device=dev)
-        L = t.empty((m, lcap), dtype=t.float32, device=dev)
-        U = t.empty((lcap, n), dtype=t.float32, device=dev)
-        k = ctypes.c_int32()
+        if out is None:
+            p = t.empty(m, dtype=t.int32, device=dev)
+            q = t.empty(n, dtype=t.int32, device=dev)
+            L = t.empty((m, lcap), dtype=t.float32, device=dev)
+            U = t.empty((lcap, n), dtype=t.float32, device=dev)
+            k = t.zeros(1, dtype=t.int32, device=dev)
+        else:
+            p, q, L, U, k = out
         info = PluInfo()
+        pinfo = ctypes.byref(info) if sync_info else None
         if sparse:
             rc = _lib().plu_sparse_fixed_precision(self._h, A._sp, float(eps), b, l, v,
                                                    1 if column_exact else 0, int(max_rounds), prec,
                                                    _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L),
-                                                   _ld(L), _ptr(U), _ld(U), ctypes.byref(k),
-                                                   ctypes.byref(info))
+                                                   _ld(L), _ptr(U), _ld(U), _ptr(k), pinfo)
         else:
             rc = _lib().plu_fixed_precision(self._h, lay, m, n, _ptr(A), lda, float(eps), b, l, v,
                                             1 if column_exact else 0, int(max_rounds), prec,
                                             _ptr(Omega), seed,
                                             _ptr(p), _ptr(q), _ptr(L), _ld(L), _ptr(U), _ld(U),
-                                            ctypes.byref(k), ctypes.byref(info))
+                                            _ptr(k), _ptr(work),
+                                            0 if work is None else work.numel() * work.element_size(),
+                                            pinfo)
         self._rc(rc, "plu_fixed_precision", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT, PLU_TOL_NOT_REACHED))
-        kk = k.value
+        if not sync_info:
+            return Factors(p, q, L, U, k, {})
+        kk = int(info.rank)
         return Factors(p, q, L[:, :kk], U[:kk], kk, info.as_dict())
 
     def batched(self, problems, graph=False):

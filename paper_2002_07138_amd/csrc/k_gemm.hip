@@ -93,7 +93,12 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
   const int ntr = DYN ? g.nt : NT;                 // column tiles of this problem
   const int64_t c0 = (int64_t)gr.by * (DYN ? ntr * 16 : XC);
   const int64_t rb = (int64_t)split * g.rsplit;
-  const int64_t re = (rb + g.rsplit < g.R) ? rb + g.rsplit : g.R;
+  int64_t re = (rb + g.rsplit < g.R) ? rb + g.rsplit : g.R;
+  if (g.kcap) {   // a rank known only on the device (uniform over the workgroup)
+    const int64_t kc = *g.kcap;
+    if (c0 >= kc - g.kc_col_off) return;
+    if (g.kc_red_off >= 0 && re > kc - g.kc_red_off) re = kc - g.kc_red_off;
+  }
   const bool do_ss = (g.sumsq_part != nullptr) && gr.by == 0;
   constexpr int epi = EPI;
   double ss = 0.0;

@@ -53,6 +53,7 @@ struct PanelArgs {
   int msgw;                 // words per message = MSGH + NB
   uint64_t timeout_ticks;
   const int32_t* run_if;    // the panel does nothing when it reads 0 (nullable)
+  const int32_t* kcap;      // nullable: steps at or beyond column *kcap are not taken
 };
 
 __device__ __forceinline__ void st_word(unsigned long long* p, uint32_t payload, uint32_t tag) {
@@ -171,6 +172,14 @@ __device__ __forceinline__ void wave_top2(unsigned long long& k, float& s) {
 template <int NB, int RPT, int NWAVE, int S>
 __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
   if (a.run_if && *a.run_if == 0) return;   // uniform over the grid: every workgroup leaves
+  // steps of this panel: all of its columns, or those below a device-side
+  // column count (the same value in every workgroup)
+  int nbw = a.nbw;
+  if (a.kcap) {
+    const int kc = *a.kcap - a.jb;
+    if (kc <= 0) return;
+    if (kc < nbw) nbw = kc;
+  }
   constexpr int MAXG = 64;                 // message slots (workgroups) at most
   constexpr int kFirstPollSleep = 24;      // s_sleep units of 64 clocks: about 0.7 us
   const int lane = threadIdx.x & 63;
@@ -208,13 +217,13 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
         const bool vec = (reinterpret_cast<uintptr_t>(src) & 15u) == 0;
 #pragma unroll
         for (int jj = 0; jj < NB; jj += 4) {
-          if (vec && jj + 3 < a.nbw) {
+          if (vec && jj + 3 < nbw) {
             const f32x4 v = *reinterpret_cast<const f32x4*>(src + jj);
             x[q][jj] = v.x; x[q][jj + 1] = v.y; x[q][jj + 2] = v.z; x[q][jj + 3] = v.w;
           } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-              if (jj + e < a.nbw) x[q][jj + e] = src[jj + e];
+              if (jj + e < nbw) x[q][jj + e] = src[jj + e];
           }
         }
       }
@@ -410,7 +419,7 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
     }
     // the pivot row's U entries (its window was staged in rowbuf by its wave)
     if (prow >= wave_base && prow < wave_base + RPT * 64) {
-      if (lane >= s && lane < NB && jcur + lane < a.nbw)
+      if (lane >= s && lane < NB && jcur + lane < nbw)
         a.F[(int64_t)prow * a.ldf + a.jb + jcur + lane] = rowbuf[wv][lane];
     }
     const float rinv = (piv != 0.f) ? 1.0f / piv : 0.f;
@@ -449,11 +458,11 @@ __device__ void b_panel(const PanelArgs& a, const Grid& gr) {
     }
   };
 
-  for (int jcur = 0; jcur < a.nbw; jcur += S) {
+  for (int jcur = 0; jcur < nbw; jcur += S) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) lmask[q] = 0u;
     [&]<int... Ss>(std::integer_sequence<int, Ss...>) __attribute__((always_inline)) {
-      ((ok && jcur + Ss < a.nbw ? step(std::integral_constant<int, Ss>{}, jcur) : void()), ...);
+      ((ok && jcur + Ss < nbw ? step(std::integral_constant<int, Ss>{}, jcur) : void()), ...);
     }(std::make_integer_sequence<int, S>{});
     if (!ok) break;
     // the group's multipliers, one store batch per row
@@ -501,6 +510,7 @@ struct TrsmArgs {
   float* u12;
   int64_t ldu12;
   const int32_t* run_if;
+  const int32_t* kcap;      // nullable: columns at or beyond *kcap are not solved
 };
 
 // U12 = L11^{-1} F[pivot rows of the panel, right columns]; written back into
@@ -508,6 +518,12 @@ struct TrsmArgs {
 // 64 right-hand columns are staged in LDS first, then solved in place.
 __device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
   if (a.run_if && *a.run_if == 0) return;
+  int c = a.c;
+  if (a.kcap) {   // the panel stopped at column *kcap: nothing right of it is needed
+    const int kc = *a.kcap;
+    if (a.jb + a.nbw >= kc) return;
+    if (kc < c) c = kc;
+  }
   __shared__ float L11[64][65];
   __shared__ float us[64][65];
   __shared__ int rows[64];
@@ -521,12 +537,12 @@ __device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
     const int s = e >> 6, col = e & 63;
     const float* row = a.F + (int64_t)rows[s] * a.ldf;
     L11[s][col] = (col < s) ? row[a.jb + col] : 0.f;
-    us[s][col] = (cbase + col < a.c) ? row[cbase + col] : 0.f;
+    us[s][col] = (cbase + col < c) ? row[cbase + col] : 0.f;
   }
   __syncthreads();
   if (t >= 64) return;
   const int64_t cc = cbase + t;
-  if (cc >= a.c) return;
+  if (cc >= c) return;
   for (int s = 0; s < a.nbw; ++s) {
     float v = us[s][t];
     for (int k = 0; k < s; ++k) v = fmaf(-L11[s][k], us[k][t], v);
@@ -558,6 +574,7 @@ __device__ void b_getrf_init(const InitArgs& a, const Grid& gr) {
 struct FinalizeArgs {
   float* F; int64_t ldf, M; int c; const int32_t* piv_step; const int32_t* pos; int32_t* perm;
   float* Uout; int64_t ldu; int utrans; const int32_t* run_if;
+  const int32_t* kcap;      // nullable: U entries outside the leading *kcap square are zeros
 };
 
 __device__ void b_getrf_finalize(const FinalizeArgs& fa, const Grid& gr) {
@@ -573,12 +590,18 @@ __device__ void b_getrf_finalize(const FinalizeArgs& fa, const Grid& gr) {
   const int utrans = fa.utrans;
   const int64_t e = (int64_t)gr.bx * 256 + threadIdx.x;
   if (e >= M * (int64_t)c) return;
+  const int kc = fa.kcap ? *fa.kcap : c;
+  if (fa.kcap && Uout && e < (int64_t)c * c) {
+    // the rows and columns of U past the steps taken
+    const int s2 = (int)(e / c), t2 = (int)(e % c);
+    if (s2 >= kc || t2 >= kc) Uout[(int64_t)s2 * ldu + t2] = 0.f;
+  }
   const int64_t i = e / c;
   const int t = (int)(e - i * c);
   const int s = piv_step[i];
   float* f = F + i * ldf + t;
   if (s >= 0) {
-    const float v = *f;
+    const float v = (t < kc) ? *f : 0.f;
     if (t >= s) {
       if (Uout) {
         if (utrans) Uout[(int64_t)t * ldu + s] = v;
@@ -644,12 +667,13 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
     pa.msgw = MSGH + NB;
     pa.timeout_ticks = w.timeout_ticks;
     pa.run_if = w.run_if;
+    pa.kcap = w.kcap;
     e = (rpt == 1) ? launch_panel<NB, 1, NWAVE, S>(pa, nblocks, s)
                    : launch_panel<NB, 2, NWAVE, S>(pa, nblocks, s);
     if (e != hipSuccess) return e;
     const int cs = jb + pa.nbw;
     if (cs < c) {
-      TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12, w.run_if};
+      TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12, w.run_if, w.kcap};
       if ((e = dispatch<TrsmArgs, b_trsm, 256>(ta, dim3((unsigned)((c - cs + 63) / 64)), 0, s)) !=
           hipSuccess)
         return e;
@@ -660,13 +684,17 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
       g.P = M; g.R = pa.nbw; g.C = c - cs;
       g.rowmask = w.piv_step;
       g.run_if = w.run_if;
+      // with a device column count: columns from cs on, panel rows from jb
+      g.kcap = w.kcap;
+      g.kc_col_off = cs;
+      g.kc_red_off = jb;
       GemmPlan pl = plan_gemm(M, pa.nbw, c - cs, 1, 1);
       if ((e = launch_gemm(0, EPI_SUB, 0, g, pl, s)) != hipSuccess) return e;
     }
   }
   const int64_t tot = M * (int64_t)c;
   return dispatch<FinalizeArgs, b_getrf_finalize, 256>(
-      FinalizeArgs{F, ldf, M, c, w.piv_step, w.pos, perm, Uout, ldu, utrans, w.run_if},
+      FinalizeArgs{F, ldf, M, c, w.piv_step, w.pos, perm, Uout, ldu, utrans, w.run_if, w.kcap},
       dim3((unsigned)((tot + 255) / 256)), 0, s);
 }
 

@@ -77,7 +77,7 @@ __device__ void b_copy_pad(const CopyPadArgs& a, const Grid& gr) {
 // U[t][r] = V[rowidx[r]][t] for t < k, r < nrows (32 x 32 LDS tiles).
 struct TGatherArgs {
   const float* V; int64_t ldv; const int32_t* rowidx; int64_t nrows; int k; float* U;
-  int64_t ldu;
+  int64_t ldu; const int32_t* kcap;
 };
 
 __device__ void b_transpose_gather(const TGatherArgs& a, const Grid& gr) {
@@ -85,18 +85,20 @@ __device__ void b_transpose_gather(const TGatherArgs& a, const Grid& gr) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int64_t r0 = (int64_t)gr.bx * 32;
   const int t0 = gr.by * 32;
+  const int kk = a.kcap ? min(a.k, *a.kcap) : a.k;
+  if (t0 >= kk) return;
 #pragma unroll
   for (int yy = 0; yy < 4; ++yy) {
     const int64_t r = r0 + ty + 8 * yy;
     const int t = t0 + tx;
-    if (r < a.nrows && t < a.k) tile[ty + 8 * yy][tx] = a.V[(int64_t)a.rowidx[r] * a.ldv + t];
+    if (r < a.nrows && t < kk) tile[ty + 8 * yy][tx] = a.V[(int64_t)a.rowidx[r] * a.ldv + t];
   }
   __syncthreads();
 #pragma unroll
   for (int yy = 0; yy < 4; ++yy) {
     const int t = t0 + ty + 8 * yy;
     const int64_t r = r0 + tx;
-    if (t < a.k && r < a.nrows) a.U[(int64_t)t * a.ldu + r] = tile[tx][ty + 8 * yy];
+    if (t < kk && r < a.nrows) a.U[(int64_t)t * a.ldu + r] = tile[tx][ty + 8 * yy];
   }
 }
 
@@ -137,6 +139,8 @@ __device__ void b_rank_rule(const RankArgs& a, const Grid& gr) {
   if (nA2 == 0.0) {
     k = 0;
     ok = 1;
+  } else if (!isfinite(nA2)) {
+    k = 0;   // non-finite A: nothing is assembled; the caller reports it
   } else {
     const double acc = a.eps * a.eps * nA2;
     for (int t1 = 0; t1 < l && !ok; t1 += a.b) {
@@ -245,10 +249,11 @@ hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ld
 }
 
 hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,
-                                   int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s) {
+                                   int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s,
+                                   const int32_t* kcap) {
   dim3 grid((unsigned)((nrows + 31) / 32), (unsigned)((k + 31) / 32));
   return dispatch<TGatherArgs, b_transpose_gather, 256>(
-      TGatherArgs{V, ldv, rowidx, nrows, k, U, ldu}, grid, 0, s);
+      TGatherArgs{V, ldv, rowidx, nrows, k, U, ldu, kcap}, grid, 0, s);
 }
 
 hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,

@@ -46,6 +46,13 @@ struct GemmArgs {
   // grouped form only: direction, column tiles per block
   int mode = 0, nt = 0;
   const int32_t* run_if = nullptr;   // device flag: the launch does nothing when it reads 0
+  // device column count k (nullable): output columns at or beyond
+  // *kcap - kc_col_off are not computed (whole column blocks past it return
+  // at once), and with kc_red_off >= 0 the reduction stops at
+  // *kcap - kc_red_off.  Lets a launch sized for l columns serve a rank k
+  // known only on the device.
+  const int32_t* kcap = nullptr;
+  int32_t kc_col_off = 0, kc_red_off = -1;
 };
 
 
@@ -120,6 +127,10 @@ struct GetrfWork {
   uint64_t timeout_ticks;
   int max_waves;
   const int32_t* run_if = nullptr;   // device flag: the whole LU is skipped when it reads 0
+  // device column count (nullable): only the first min(c, *kcap) steps are
+  // taken -- the LU of the leading *kcap columns; U (and U^T) entries
+  // outside that square are written as zeros, perm is that LU's row order
+  const int32_t* kcap = nullptr;
 };
 size_t getrf_msg_words(int64_t M);
 // F: M x c (ldf).  On return F holds V = P^T L (unit lower, original row order).
@@ -159,8 +170,10 @@ hipError_t launch_gaussian(float* out, int64_t ldo, int64_t rows, int64_t cols, 
                            hipStream_t s);
 hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ldd,
                            int64_t rows, int64_t cols, int64_t cols_pad, hipStream_t s);
+// kcap (nullable, device): rows t >= *kcap of U are not written
 hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,
-                                   int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s);
+                                   int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s,
+                                   const int32_t* kcap = nullptr);
 hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,
                             int nvblk, const double* normA2, double eps, int b, int col_mode,
                             int32_t* kout, double* Eout, int32_t* tol, double* colnorm,
