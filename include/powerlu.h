@@ -60,7 +60,9 @@ enum {
   PLU_ERR_HIP = 5,             /* a HIP runtime call failed */
   PLU_ERR_NOT_IMPLEMENTED = 6,
   PLU_ERR_TIMEOUT = 7,         /* a device-side wait in the cooperative LU panel exceeded its bound */
-  PLU_PENDING = 8              /* server: request not finished yet */
+  PLU_PENDING = 8,             /* server: request not finished yet */
+  PLU_ERR_TOO_LARGE = 9        /* plu_fixed_rank_static: the problem's workspace exceeds its
+                                  static scratch */
 };
 
 typedef enum {
@@ -153,6 +155,26 @@ int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const flo
                    const float* Omega, uint64_t seed,
                    int32_t* p, int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
                    void* work, size_t work_bytes, plu_info* info);
+
+/* ---- plu_fixed_rank without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture that brings no
+ * workspace, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, kernels and results as plu_fixed_rank with work = NULL, but the
+ * workspace is a static array of 64 MiB in the library's device code object
+ * -- one per device, present from the library's load on that device until
+ * the process ends -- so the call makes no hipMalloc / hipFree (nor any host
+ * heap allocation) and runs the default split of the passes (no tuning).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the call clears what must start at zero): calls that
+ * overlap on one device -- from two threads, or on two streams -- race.
+ * Returns PLU_ERR_TOO_LARGE when plu_workspace_size(m, n, k + p_over, 1,
+ * prec) exceeds 64 MiB (for example 8192 x 8192 with l = 64 fits; 20000 x
+ * 20000 does not), and PLU_ERR_HIP if the array's device address could not
+ * be obtained when the handle was created.                                */
+int plu_fixed_rank_static(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                          int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
+                          const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                          int64_t ldl, float* U, int64_t ldu, plu_info* info);
 
 /* ---- Fixed-precision problem (Sec. 1, last paragraph of Def. 1.1's
  * discussion) solved by PowerLU_FP: Alg. 9 on top of Alg. 8 (block rule) or

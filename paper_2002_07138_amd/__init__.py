@@ -24,6 +24,7 @@ PLU_ERR_HIP = 5
 PLU_ERR_NOT_IMPLEMENTED = 6
 PLU_ERR_TIMEOUT = 7
 PLU_PENDING = 8
+PLU_ERR_TOO_LARGE = 9
 PREC_FP32 = 0
 PREC_BF16 = 1
 PREC_FP8_E4M3 = 2
@@ -41,7 +42,7 @@ _ENTRY_POINTS = [
     "plu_sparse_fixed_rank", "plu_sparse_fixed_precision", "plu_sparse_randlu",
     "plu_sparse_randsvd", "plu_server_create",
     "plu_server_submit", "plu_server_poll",
-    "plu_server_wait", "plu_server_destroy",
+    "plu_server_wait", "plu_server_destroy", "plu_fixed_rank_static",
 ]
 BATCH_GRAPH = 1
 
@@ -114,6 +115,8 @@ def _lib():
             "plu_status_string": [ctypes.c_int],
             "plu_fixed_rank": [vp, i32, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
                                vp, vp, vp, i64, vp, i64, vp, ctypes.c_size_t, pinfo],
+            "plu_fixed_rank_static": [vp, i32, i64, i64, vp, i64, i32, i32, i32, i32, vp, u64,
+                                      vp, vp, vp, i64, vp, i64, pinfo],
             "plu_fixed_precision": [vp, i32, i64, i64, vp, i64, dbl, i32, i32, i32, i32, i32, i32, vp,
                                     u64, vp, vp, vp, i64, vp, i64, vp, vp, ctypes.c_size_t,
                                     pinfo],
@@ -434,6 +437,28 @@ class Handle:
                                        0 if work is None else work.numel() * work.element_size(),
                                        pinfo)
         self._rc(rc, "plu_fixed_rank", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
+        return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
+
+    def fixed_rank_static(self, A, k, p_over, v, Omega=None, seed=0, prec=PREC_FP32,
+                          sync_info=True, out=None):
+        """plu_fixed_rank_static: PowerLU on the library's static scratch (no
+        allocation by the library; out = (p, q, L, U) preallocated by the
+        caller, or allocated here by torch)."""
+        t = self._torch
+        _check_mat(Omega, "Omega")
+        lay, lda = _layout_of(A)
+        m, n = A.shape
+        if out is None:
+            dev = A.device
+            out = (t.empty(m, dtype=t.int32, device=dev), t.empty(n, dtype=t.int32, device=dev),
+                   t.empty((m, k), dtype=t.float32, device=dev),
+                   t.empty((k, n), dtype=t.float32, device=dev))
+        p, q, L, U = out
+        info = PluInfo()
+        rc = _lib().plu_fixed_rank_static(self._h, lay, m, n, _ptr(A), lda, k, p_over, v, prec,
+                                          _ptr(Omega), seed, _ptr(p), _ptr(q), _ptr(L), _ld(L),
+                                          _ptr(U), _ld(U), ctypes.byref(info) if sync_info else None)
+        self._rc(rc, "plu_fixed_rank_static", ok=(PLU_OK, PLU_WARN_ZERO_PIVOT))
         return Factors(p, q, L, U, k, info.as_dict() if sync_info else {})
 
     def single_pass(self, A, k, Omega=None, seed=0, sync_info=True):

@@ -26,8 +26,16 @@
 
 using namespace plu;
 
+// The workspace of plu_fixed_rank_static: one array per device, in the code
+// object's device memory, held until the process ends.  Host code never uses
+// the name itself (on the host it is not a device address): plu_create looks
+// up its address on each device once (scratch_ptr) and every launch gets that.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct plu_handle_s {
   int device = 0;
+  void* scratch_dev = nullptr;   // this device's address of `scratch`
   hipStream_t stream = nullptr;
   int cu_count = 256;
   uint64_t timeout_ticks = 0;
@@ -127,6 +135,8 @@ struct Ws {
   uint32_t* tags = nullptr;
   // the handle's stream is being captured into a graph: no autotuning runs
   bool capturing = false;
+  // a call that must not allocate (plu_fixed_rank_static): no autotuning runs
+  bool no_tune = false;
 };
 
 int64_t part_need(int64_t m, int64_t n, int64_t l) {
@@ -203,7 +213,9 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
   w.status = L.take<int32_t>(64);
   w.msg_words = getrf_msg_words(Mx);
   w.msg = L.take<unsigned long long>(w.msg_words);
-  w.gram_part = L.take<double>((size_t)kMaxGramChunks * kQB * kQB);
+  // the thin QR's float64 Gram partials: one per 64 rows, at most
+  // kMaxGramChunks (the chunking itself does not depend on this size)
+  w.gram_part = L.take<double>((size_t)std::min<int64_t>(kMaxGramChunks, (Mx + 63) / 64) * kQB * kQB);
   w.gram = L.take<double>(kQB * kQB);
   w.rinv64 = L.take<double>(kQB * kQB);
   w.sumsq_cap = 65536;
@@ -419,7 +431,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   }
   // small passes, recorded (batched) launches and launches under graph
   // capture use the default plan
-  if (!tune_enabled() || thread_recorder() || w.capturing || 2.0 * P * R * C < 2e10)
+  if (!tune_enabled() || thread_recorder() || w.capturing || w.no_tune || 2.0 * P * R * C < 2e10)
     return fits(def) ? def : plan_gemm(P, R, C, 1, 1);
   // PLU_AUTOTUNE_ROWS=64 or 128 holds the tuner to one row-block size
   int only_bp = 0;
@@ -510,7 +522,7 @@ hipError_t pass_launch(plu_handle h, const Ws& w, int trans, const GemmArgs& g0,
 // same plan as the single calls and give the same bits.
 void pretune_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, const float* A,
                   int64_t lda, const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo) {
-  if (w.sp || thread_recorder() || w.capturing) return;
+  if (w.sp || thread_recorder() || w.capturing || w.no_tune) return;
   if (w.acol) {
     trans ^= 1;
     std::swap(m, n);
@@ -913,17 +925,23 @@ int finish_info(plu_handle h, const Ws& w, int status, int rank, int passes, int
     rank = ks[0];
     if (status == PLU_OK && !ks[1]) status = PLU_TOL_NOT_REACHED;
   }
-  std::vector<unsigned char> host(stage_bytes(rank));
-  PLU_TRY_HIP(hipMemcpy(host.data() + kStageSt, w.status, 40 * sizeof(int32_t),
-                        hipMemcpyDeviceToHost));
-  PLU_TRY_HIP(hipMemcpy(host.data() + kStageSc, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost));
-  if (rank > 0) {
-    PLU_TRY_HIP(hipMemcpy(host.data() + kStageGaps, w.gaps1, rank * sizeof(float),
-                          hipMemcpyDeviceToHost));
-    PLU_TRY_HIP(hipMemcpy(host.data() + kStageGaps + 4 * (size_t)rank, w.gaps2,
-                          rank * sizeof(float), hipMemcpyDeviceToHost));
+  // the fixed part of the image on the stack; the gaps' minimum in chunks
+  // (no heap memory: plu_fixed_rank_static allocates nothing)
+  unsigned char img[kStageGaps];
+  PLU_TRY_HIP(hipMemcpy(img + kStageSt, w.status, 40 * sizeof(int32_t), hipMemcpyDeviceToHost));
+  PLU_TRY_HIP(hipMemcpy(img + kStageSc, w.scal, 4 * sizeof(double), hipMemcpyDeviceToHost));
+  float mg = 1.f;
+  for (const float* gp : {w.gaps1, w.gaps2}) {
+    float buf[512];
+    for (int i0 = 0; i0 < rank; i0 += 512) {
+      const int c = std::min(512, rank - i0);
+      PLU_TRY_HIP(hipMemcpy(buf, gp + i0, c * sizeof(float), hipMemcpyDeviceToHost));
+      for (int i = 0; i < c; ++i) mg = std::min(mg, buf[i]);
+    }
   }
-  const int st = info_from_stage(host.data(), status, rank, rank, passes, l, fp, info);
+  const int st = info_from_stage(img, status, 0, 0, passes, l, fp, info);
+  info->rank = rank;
+  info->min_pivot_gap = mg;
   if (fp) info->tol_reached = ks[1] ? 1 : 0;
   return st;
 }
@@ -1675,6 +1693,7 @@ const char* plu_status_string(int status) {
     case PLU_ERR_NOT_IMPLEMENTED: return "not implemented";
     case PLU_ERR_TIMEOUT: return "device-side wait exceeded its bound";
     case PLU_PENDING: return "pending";
+    case PLU_ERR_TOO_LARGE: return "the problem needs more workspace than the static scratch holds";
     default: return status < 0 ? "invalid argument" : "unknown status";
   }
 }
@@ -1696,6 +1715,25 @@ int plu_create(plu_handle* out, int device, void* hip_stream) {
     return PLU_ERR_NOT_IMPLEMENTED;
   }
   h->cu_count = cus > 0 ? cus : 256;
+  {
+    // this device's copy of `scratch`, looked up once per device (with the
+    // device current) and kept for the process
+    static std::mutex mu;
+    static void* addr[256] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 256 && !addr[device]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        std::fprintf(stderr, "libpowerlu: hipGetSymbolAddress(scratch) failed: %s\n",
+                     hipGetErrorString(e));
+        (void)hipGetLastError();
+      } else {
+        addr[device] = ptr;
+      }
+    }
+    h->scratch_dev = device < 256 ? addr[device] : nullptr;
+  }
   // bound on any device-side wait: 5 seconds of the constant-rate wall clock
   h->timeout_ticks = (uint64_t)(clk_khz > 0 ? clk_khz : 100000) * 1000ull * 5ull;
   *out = h;
@@ -1907,7 +1945,7 @@ static int fixed_rank_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, c
                            int64_t lda, const SparseMat* sp, int off, int32_t k, int32_t p_over,
                            int32_t v, int32_t prec, const float* Omega, uint64_t seed, int32_t* p,
                            int32_t* q, float* L, int64_t ldl, float* U, int64_t ldu,
-                           void* work, size_t work_bytes, plu_info* info) {
+                           void* work, size_t work_bytes, plu_info* info, bool no_tune = false) {
   if (!h) return -1;
   if (!sp && !valid_layout(layout)) return -2;
   if (!sp && m <= 0) return -3;
@@ -1934,6 +1972,7 @@ static int fixed_rank_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, c
   if (st) return st;
   w.acol = layout == PLU_COL_MAJOR;
   w.sp = sp;
+  w.no_tune = no_tune;
   trace_reset(h);
   float* V = nullptr;
   int np = 0;
@@ -1952,6 +1991,18 @@ int plu_fixed_rank(plu_handle h, int32_t layout, int64_t m, int64_t n, const flo
                    plu_info* info) {
   return fixed_rank_impl(h, layout, m, n, A, lda, nullptr, 0, k, p_over, v, prec, Omega, seed, p, q,
                          L, ldl, U, ldu, work, work_bytes, info);
+}
+
+int plu_fixed_rank_static(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
+                          int64_t lda, int32_t k, int32_t p_over, int32_t v, int32_t prec,
+                          const float* Omega, uint64_t seed, int32_t* p, int32_t* q, float* L,
+                          int64_t ldl, float* U, int64_t ldu, plu_info* info) {
+  if (!h) return -1;
+  if (!h->scratch_dev) return PLU_ERR_HIP;
+  const int rc = fixed_rank_impl(h, layout, m, n, A, lda, nullptr, 0, k, p_over, v, prec, Omega,
+                                 seed, p, q, L, ldl, U, ldu, h->scratch_dev, kScratchBytes, info,
+                                 true);
+  return rc == -20 ? PLU_ERR_TOO_LARGE : rc;
 }
 
 static int fixed_precision_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,

@@ -41,6 +41,17 @@ def _alone(h, rq):
     return f
 
 
+def _footprint(h, rq):
+    """Device bytes the server holds for a request: A, p, q, L and U at its
+    capacity, and the workspace of its shape (each rounded to 256 bytes)."""
+    m, n = rq["A"].shape
+    l = rq["k"] + rq["p_over"] if rq["mode"] == 0 else rq["l"]
+    cap = rq["k"] if rq["mode"] == 0 else l
+    a = lambda x: (x + 255) // 256 * 256
+    return (a(4 * m * n) + a(4 * m) + a(4 * n) + a(4 * m * cap) + a(4 * cap * n)
+            + a(h.workspace_size(m, n, l)))
+
+
 def _submit(srv, rq):
     kw = {k: v for k, v in rq.items() if k != "A"}
     return srv.submit(rq["A"], **kw)
@@ -80,8 +91,12 @@ def test_server_admission_by_budget():
     reqs = _requests(12, 6)
     h = handle()
     alone = [_alone(h, rq) for rq in reqs]
+    foot = [_footprint(h, rq) for rq in reqs]
     h.close()
-    srv = plu.Server(0, hbm_budget_bytes=256 << 20, max_slots=16)
+    # room for the largest request and a tenth of it: never for all of them
+    budget = int(1.1 * max(foot))
+    assert sum(foot) > 2 * budget
+    srv = plu.Server(0, hbm_budget_bytes=budget, max_slots=16)
     tickets = [_submit(srv, rq) for rq in reqs]
     results = [srv.wait(t) for t in tickets]
     srv.close()
