@@ -61,7 +61,212 @@ def flops_fixed_precision(m: int, n: int, l: int, k: int, v: int) -> float:
     return f
 
 
-FORMS = {"bf16": 1, "fp8_e4m3": 2, "bf16+refine_last": 1 | 16, "fp8_e4m3+refine_last": 2 | 16}
+FORMS = {"bf16": 1, "fp8_e4m3": 2, "bf16+refine_last": 1 | 16, "fp8_e4m3+refine_last": 2 | 16,
+         "fp8_e4m3+refine_two": 2 | 32}
+A_UNCHANGED = 64
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP8_MFMA_TFLOPS = 5000.0
+
+
+def _event_times(fn, reps):
+    """reps calls, each between two events on the current stream (no host
+    synchronization between calls); per-call durations in ms."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        fn()
+        e1.record()
+    evs[-1][1].synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
+def _stats(ts):
+    import numpy as np
+    a = np.asarray(ts, dtype=np.float64)
+    return {"median": round(float(np.median(a)), 4), "p10": round(float(np.percentile(a, 10)), 4),
+            "p90": round(float(np.percentile(a, 90)), 4), "n": int(a.size)}
+
+
+def _pass_times(h, A, l, reps=10, prec=0):
+    """Median time of one pass A X (N) and A^T X (T) with sketch width l."""
+    import numpy as np
+    import torch
+    m, n = A.shape
+    X_n = torch.randn((n, l), device=A.device)
+    X_m = torch.randn((m, l), device=A.device)
+    o_m = torch.empty((m, l), device=A.device)
+    o_n = torch.empty((n, l), device=A.device)
+    out = {}
+    for name, X, o, tr in (("N", X_n, o_m, False), ("T", X_m, o_n, True)):
+        h.pass_(A, X, trans=tr, out=o, prec=prec)                  # tuning / rounded copies
+        torch.cuda.synchronize()
+        keep = prec | (A_UNCHANGED if prec else 0)
+        out[name] = float(np.median(_event_times(lambda: h.pass_(A, X, trans=tr, out=o, prec=keep),
+                                                 reps)))
+    return out
+
+
+def _device_matrix(X, s, Y):
+    """X diag(s) Y^T formed on the device in float32 from float64 factors."""
+    import torch
+    Xd = torch.from_numpy((X * s[None, :]).astype("float32")).cuda()
+    Yd = torch.from_numpy(Y.astype("float32")).cuda()
+    A = Xd @ Yd.t()
+    del Xd, Yd
+    torch.cuda.synchronize()
+    return A
+
+
+def square32768_section(h, reps=5, cpu=True):
+    """The precision-form workload: A = X diag(i^-1.5) Y^T, 32768^2, rank 1000
+    (X, Y the seeded Q factors; the product formed on the device in float32),
+    k = 200, oversampling 20, v = 4.  Each form: call time (median, p10, p90
+    of reps), GFLOP/s of the cost model, full-size residual; the rounded
+    forms again with their copies of A kept (PLU_PREC_A_UNCHANGED).  Passes:
+    the fp32 one against the FP32 MFMA peak, the rounded ones (copies kept:
+    the pass alone) against HBM.  Error against the FP64 oracle: every form on
+    the 4096^2 leading block (synth.workload_slice) with the same Gaussian
+    matrix as the stored oracle residuals (tests/golden, written by a script
+    that calls only the oracle)."""
+    import numpy as np
+    import torch
+    from synth import WORKLOADS, gaussian_omega, workload_matrix_factors, workload_slice
+    w = WORKLOADS["square32768_pow15"]
+    k, p_over, v = 200, 20, 4
+    l = k + p_over
+    t0 = time.perf_counter()
+    X, s, Y = workload_matrix_factors(w)
+    A = _device_matrix(X, s, Y)
+    del X, Y
+    gen = time.perf_counter() - t0
+    m, n = A.shape
+    dev = A.device
+    outs = (torch.empty(m, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+            torch.empty((m, k), device=dev), torch.empty((k, n), device=dev))
+    flops = flops_fixed_rank(m, n, k, l, v)
+    forms = {"fp32": 0, **{kk: vv for kk, vv in FORMS.items() if kk != "fp8_e4m3"}}
+    res = {"workload": w.name, "m": m, "n": n, "k": k, "p_over": p_over, "v": v,
+           "input_generation_s": round(gen, 2), "forms": {}}
+    for name, prec in forms.items():
+        f = h.fixed_rank(A, k, p_over, v, seed=31, prec=prec, out=outs)
+        r = h.residual(A, f)
+        ts = _event_times(lambda: h.fixed_rank(A, k, p_over, v, seed=31, prec=prec,
+                                               sync_info=False, out=outs), reps)
+        e = {"ms": _stats(ts), "gflops": round(flops / (np.median(ts) * 1e-3) / 1e9, 1),
+             "residual_full_size": r}
+        if prec:
+            ts2 = _event_times(lambda: h.fixed_rank(A, k, p_over, v, seed=31,
+                                                    prec=prec | A_UNCHANGED,
+                                                    sync_info=False, out=outs), reps)
+            e["ms_copies_kept"] = _stats(ts2)
+            e["gflops_copies_kept"] = round(flops / (np.median(ts2) * 1e-3) / 1e9, 1)
+        res["forms"][name] = e
+    passes = {}
+    fp32 = _pass_times(h, A, l)
+    ms = 0.5 * (fp32["N"] + fp32["T"])
+    passes["fp32"] = {"ms": fp32, "bound": "mfma", "achieved_tflops": round(2.0 * m * n * l / (ms * 1e-3) / 1e12, 2),
+                      "frac": round(2.0 * m * n * l / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)}
+    for name, prec, bytes_a in (("bf16", 1, 2.0 * m * n), ("fp8_e4m3", 2, m * n * (1 + 1 / 32.0))):
+        t = _pass_times(h, A, l, prec=prec)
+        ms = 0.5 * (t["N"] + t["T"])
+        passes[name] = {"ms": t, "bound": "hbm", "algorithmic_bytes": bytes_a,
+                        "achieved_gbs": round(bytes_a / (ms * 1e-3) / 1e9, 1),
+                        "frac": round(bytes_a / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    res["passes"] = passes
+    del A
+    torch.cuda.empty_cache()
+    # error against the FP64 oracle on the leading 4096^2 block
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "square32768_slice4096_oracle.json")))
+    S = torch.from_numpy(workload_slice(w, 4096, 4096)).to(dev)
+    Om = torch.from_numpy(gaussian_omega(4096, l, seed=gold["omega_seed"])).to(dev)
+    r64 = gold["residual"]["fp32"]
+    sl = {}
+    for name, prec in forms.items():
+        f = h.fixed_rank(S, k, p_over, v, Omega=Om, prec=prec)
+        r = h.residual(S, f)
+        sl[name] = {"residual": r, "vs_fp64_oracle": round(r / r64, 5),
+                    "form_oracle_vs_fp64_oracle": round(gold["residual"][name] / r64, 5)}
+    res["slice4096_vs_fp64_oracle"] = sl
+    if cpu:
+        from oracle import powerlu as O
+        S64 = S.cpu().numpy().astype(np.float64)
+        Om64 = Om.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        O.powerlu(S64, k, Om64, v)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(flops_fixed_rank(4096, 4096, k, l, v) / dt / 1e9, 2),
+                               "unit": "GFLOP/s", "cores": _oracle_threads(), "kind": "oracle",
+                               "sample": f"one fixed-rank PowerLU (v={v}, k={k}, l={l}) of the "
+                                         f"4096x4096 leading block in float64 NumPy, {dt:.2f} s"}
+    del S
+    torch.cuda.empty_cache()
+    return res
+
+
+def rect30000_section(h, reps=3, cpu=True):
+    """The fixed-precision workload: A = X diag(exp(-i/50)) Y^T, 30000 x
+    20000, rank 2000 (the product formed on the device in float32), eps =
+    1e-3, b = 32, l = 1600, v = 4, both rank rules: call time (median, p10,
+    p90), GFLOP/s of the cost model at the rank found, the rank and the
+    residual; the l = 1600 pass against the FP32 MFMA peak.  CPU baseline: the
+    oracle on the same recipe at 6000 x 4000 with l = 1024."""
+    import numpy as np
+    import torch
+    from synth import WORKLOADS, gaussian_omega, workload_matrix, workload_matrix_factors
+    w = WORKLOADS["rect30000x20000_exp50"]
+    eps, b, l, v = 1e-3, 32, 1600, 4
+    t0 = time.perf_counter()
+    X, s, Y = workload_matrix_factors(w)
+    A = _device_matrix(X, s, Y)
+    del X, Y
+    gen = time.perf_counter() - t0
+    m, n = A.shape
+    dev = A.device
+    outs = (torch.empty(m, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+            torch.empty((m, l), device=dev), torch.empty((l, n), device=dev),
+            torch.zeros(1, dtype=torch.int32, device=dev))
+    res = {"workload": w.name, "m": m, "n": n, "eps": eps, "b": b, "l": l, "v": v,
+           "input_generation_s": round(gen, 2), "rules": {}}
+    for col in (True, False):
+        f = h.fixed_precision(A, eps, b, l=l, v=v, column_exact=col, seed=41)
+        r = h.residual(A, f)
+        ts = _event_times(lambda: h.fixed_precision(A, eps, b, l=l, v=v, column_exact=col, seed=41,
+                                                    sync_info=False, out=outs), reps)
+        fl = flops_fixed_precision(m, n, l, f.rank, v)
+        res["rules"]["column" if col else "block"] = {
+            "rank": f.rank, "tol_reached": f.info["tol_reached"], "residual": r,
+            "ms": _stats(ts), "gflops": round(fl / (np.median(ts) * 1e-3) / 1e9, 1)}
+    t = _pass_times(h, A, l, reps=5)
+    ms = 0.5 * (t["N"] + t["T"])
+    res["pass"] = {"ms": t, "bound": "mfma",
+                   "achieved_tflops": round(2.0 * m * n * l / (ms * 1e-3) / 1e12, 2),
+                   "frac": round(2.0 * m * n * l / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)}
+    del A
+    torch.cuda.empty_cache()
+    if cpu:
+        from oracle import powerlu as O
+        Ar = workload_matrix(w, 6000, 4000).astype(np.float64)
+        Om = gaussian_omega(6000, 1024, seed=1000 * w.index + 3).astype(np.float64)
+        t0 = time.perf_counter()
+        ref = O.powerlu_fp(Ar, eps, b, Om, v, True)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {
+            "value": round(flops_fixed_precision(6000, 4000, 1024, ref.rank, v) / dt / 1e9, 2),
+            "unit": "GFLOP/s", "cores": _oracle_threads(), "kind": "oracle",
+            "sample": f"one PowerLU_FP (column rule, eps={eps}, b={b}, l=1024, v={v}, rank "
+                      f"{ref.rank}) of the workload recipe at 6000x4000 in float64 NumPy, {dt:.2f} s"}
+    return res
+
+
+def _oracle_threads():
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        return max((i.get("num_threads", 0) for i in info), default=None) or os.cpu_count()
+    except Exception:
+        return os.cpu_count()
 
 
 def single_pass_section(h, A, k, reps=5):
@@ -520,6 +725,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=20000, help="reduced sizes for quick checks")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision forms")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 32768^2 precision-form and 30000x20000 fixed-precision sections")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the RandLU / RandSVD comparison")
     ap.add_argument("--serving-count", type=int, default=1024,
@@ -582,11 +789,17 @@ def main():
     for i in range(args.warmup):
         step(1000 + i)
     torch.cuda.synchronize()
+    # per-step events on the library's stream (no host synchronization between steps)
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
     t0 = time.perf_counter()
     for i in range(args.steps):
+        step_ev[i][0].record(stream)
         step(i)
+        step_ev[i][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in step_ev]
     ms_per_step = elapsed * 1e3 / args.steps
     flops_step = sum(flops_fixed_rank(m, n, k, l, v) for v in VS)
     gflops = flops_step / (elapsed / args.steps) / 1e9
@@ -656,6 +869,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
+        "step_ms": _stats(step_ms),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -695,9 +909,12 @@ def main():
         result["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
     else:
         result["cpu_baseline"] = None
+    del A
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        result["square32768_pow15"] = square32768_section(h, cpu=not args.no_cpu_baseline)
+        result["rect30000x20000_exp50"] = rect30000_section(h, cpu=not args.no_cpu_baseline)
     if args.serving_count > 0:
-        del A
-        torch.cuda.empty_cache()
         t_pool = time.perf_counter()
         pool = serving_pool(args.pool)
         t_pool = time.perf_counter() - t_pool

@@ -77,13 +77,22 @@ typedef enum {
                               passes of Alg. 7 (the one whose result the final QR
                               orthonormalizes) also runs on the fp32 A, re-projecting the
                               rounded iterate; for v = 2 nothing is then rounded */
-  PLU_PREC_REFINE_TWO = 32  /* flag, OR-ed with BF16 or FP8_E4M3 (instead of REFINE_LAST):
+  PLU_PREC_REFINE_TWO = 32, /* flag, OR-ed with BF16 or FP8_E4M3 (instead of REFINE_LAST):
                               the last two of the v-1 passes of Alg. 7 -- the A X and
                               A^T Y of its final loop iteration -- run on the fp32 A, one
                               full fp32 power step on the basis the rounded passes
                               found; for v <= 3 nothing is then rounded.  The E4M3 form
                               needs it to stay within 1.05x of the exact residual when
                               the rounding error of A exceeds sigma_{k+1} */
+  PLU_PREC_A_UNCHANGED = 64 /* flag, OR-ed with BF16 or FP8_E4M3: A (same pointer, shape,
+                              leading dimension and storage order) has not changed since
+                              the last call on this handle that rounded it to this format
+                              on the handle's own workspace: the rounded copies still kept
+                              there are reused instead of made again (4 m n bytes read,
+                              4 m n or 2 m n written).  The caller guarantees A is
+                              unchanged; without a matching copy the flag does nothing.
+                              Any call on the handle in another format or shape
+                              invalidates the copies. */
 } plu_prec;
 
 /* Storage order of the input matrix A (the paper's A is m x n, Def. 1.1).
@@ -141,7 +150,8 @@ const char* plu_status_string(int status);
  *          Y = A V(:,1:k) always runs in FP32 on the fp32 A: it is the
  *          refinement pass of the precision form.
  *          The rounded copies of A cost 4 m n (BF16) or 2 m n (FP8) bytes
- *          of workspace and are rebuilt on every call.
+ *          of workspace; they are made on every call unless prec carries
+ *          PLU_PREC_A_UNCHANGED and the handle still holds them.
  *   Omega  device, nullable.  (v even ? m : n) x l Gaussian test matrix with
  *          leading dimension l.  NULL draws it on the device from `seed` with
  *          the Philox4x32-10 layout of plu_gaussian.
@@ -455,7 +465,9 @@ int plu_gaussian(plu_handle h, int64_t rows, int64_t cols, uint64_t seed,
  * trans = 0: out (m x l) = A X with X n x l;  trans = 1: out (n x l) = A^T X
  * with X m x l.  All device.  normA2_out: device double*, nullable; receives
  * ||A||_F^2 accumulated in float64 while A streams through (Alg. 8).
- * prec: PLU_PREC_FP32 or PLU_PREC_BF16 (operands rounded to bf16).       */
+ * prec: PLU_PREC_FP32, PLU_PREC_BF16 or PLU_PREC_FP8_E4M3 (operands rounded
+ * to that format), optionally | PLU_PREC_A_UNCHANGED (the rounded copies of
+ * A from an earlier call are reused: the call is then the pass alone).    */
 int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, int64_t lda,
              int32_t l, const float* X, int64_t ldx, float* out, int64_t ldo,
              int32_t prec, double* normA2_out);

@@ -41,6 +41,15 @@ struct plu_handle_s {
   uint64_t timeout_ticks = 0;
   char* arena = nullptr;
   size_t arena_bytes = 0;
+  // the rounded copies of A at the start of the arena (precision form): which
+  // A they hold (base == nullptr: none)
+  struct {
+    const float* A = nullptr;
+    const char* base = nullptr;
+    int64_t m = 0, n = 0, lda = 0;
+    int fmt = 0;
+    bool acol = false;
+  } lowp;
   uint32_t tag_counter = 0;   // LU panel launches on the arena's message buffer
   uint32_t call_tags = 0;     // the same for a call on a caller workspace or under capture
   size_t msg_off = 0, msg_words = 0;
@@ -77,7 +86,8 @@ bool valid_prec(int prec) {
   const int fmt = prec & PLU_PREC_FORMAT_MASK;
   if ((prec & PLU_PREC_REFINE_LAST) && (prec & PLU_PREC_REFINE_TWO)) return false;
   return fmt >= PLU_PREC_FP32 && fmt <= PLU_PREC_FP8_E4M3 &&
-         (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST | PLU_PREC_REFINE_TWO)) == 0;
+         (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST | PLU_PREC_REFINE_TWO |
+                   PLU_PREC_A_UNCHANGED)) == 0;
 }
 inline int64_t ru(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -137,6 +147,9 @@ struct Ws {
   bool capturing = false;
   // a call that must not allocate (plu_fixed_rank_static): no autotuning runs
   bool no_tune = false;
+  // the workspace is the handle's arena (the rounded copies of A may persist)
+  bool on_arena = false;
+  double* anorm = nullptr;   // ||A||_F^2 of the rounded copies' A (precision form)
 };
 
 int64_t part_need(int64_t m, int64_t n, int64_t l) {
@@ -188,6 +201,23 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
   const int64_t Mx = std::max(m, n);
   const int64_t lp = ru4(std::max<int64_t>(l, 4));
   w.lp = lp;
+  // the rounded copies of A first: their place depends on m, n and the
+  // format only, so calls of other sketch widths find them where they are
+  if (prec == PLU_PREC_BF16) {
+    w.ldab = ru(n, 64);
+    w.ldabt = ru(m, 64);
+    w.ab = L.take<uint16_t>((size_t)m * w.ldab);
+    w.abt = L.take<uint16_t>((size_t)n * w.ldabt);
+    w.anorm = L.take<double>(1);
+  } else if (prec == PLU_PREC_FP8_E4M3) {
+    w.lda8 = ru(n, 128);
+    w.lda8t = ru(m, 128);
+    w.a8 = L.take<uint8_t>((size_t)m * w.lda8);
+    w.a8s = L.take<uint8_t>((size_t)m * (w.lda8 / 32));
+    w.a8t = L.take<uint8_t>((size_t)n * w.lda8t);
+    w.a8ts = L.take<uint8_t>((size_t)n * (w.lda8t / 32));
+    w.anorm = L.take<double>(1);
+  }
   w.om = L.take<float>(Mx * lp);
   w.ym = L.take<float>(m * lp);
   w.zn = L.take<float>(n * lp);
@@ -227,24 +257,14 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
   w.scal = L.take<double>(16);
   w.iscal = L.take<int32_t>(16);
   if (prec == PLU_PREC_BF16) {
-    w.ldab = ru(n, 64);
-    w.ldabt = ru(m, 64);
     w.ldxt = ru(Mx, 64);
     w.xt_rows = std::max(lowp_xt_rows(m, ru(n, 64), l, prec), lowp_xt_rows(n, ru(m, 64), l, prec));
-    w.ab = L.take<uint16_t>((size_t)m * w.ldab);
-    w.abt = L.take<uint16_t>((size_t)n * w.ldabt);
     w.xt = L.take<uint16_t>((size_t)w.xt_rows * w.ldxt);
     w.cvt_cap = ((std::max(ru(m, 64), ru(n, 64)) + 63) / 64) * 8;   // either storage order
     w.cvt_part = L.take<double>(w.cvt_cap);
   } else if (prec == PLU_PREC_FP8_E4M3) {
-    w.lda8 = ru(n, 128);
-    w.lda8t = ru(m, 128);
     w.ldx8 = ru(Mx, 128);
     w.x8_rows = std::max(lowp_xt_rows(m, w.lda8, l, prec), lowp_xt_rows(n, w.lda8t, l, prec));
-    w.a8 = L.take<uint8_t>((size_t)m * w.lda8);
-    w.a8s = L.take<uint8_t>((size_t)m * (w.lda8 / 32));
-    w.a8t = L.take<uint8_t>((size_t)n * w.lda8t);
-    w.a8ts = L.take<uint8_t>((size_t)n * (w.lda8t / 32));
     w.x8 = L.take<uint8_t>((size_t)w.x8_rows * w.ldx8);
     w.x8s = L.take<uint8_t>((size_t)w.x8_rows * (w.ldx8 / 32));
     w.sumsq_cap = std::max<int64_t>(w.sumsq_cap, 1);
@@ -287,6 +307,7 @@ int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
     *out = layout(L, m, n, l, prec, basis_store);
     h->call_tags = 0;
     out->tags = &h->call_tags;
+    out->on_arena = false;
   } else {
     if (need > h->arena_bytes && capturing) {
       std::fprintf(stderr, "libpowerlu: the workspace must exist before graph capture "
@@ -295,22 +316,28 @@ int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
     }
     if (need > h->arena_bytes) {
       if (h->arena) {
-        hipStreamSynchronize(h->stream);
-        hipFree(h->arena);
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->arena);
         h->arena = nullptr;
         h->arena_bytes = 0;
       }
       const size_t alloc = need + need / 8;
       if (hipMalloc(reinterpret_cast<void**>(&h->arena), alloc) != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         return PLU_ERR_OOM;
       }
       h->arena_bytes = alloc;
       h->tag_counter = 0;   // next panel launch clears the message buffer
+      h->lowp.base = nullptr;
     }
     Layout L;
     L.base = h->arena;
     *out = layout(L, m, n, l, prec, basis_store);
+    out->on_arena = true;
+    // a call that lays out the arena differently overwrites the rounded copies
+    const int fmt = prec & PLU_PREC_FORMAT_MASK;
+    if (fmt == PLU_PREC_FP32 || h->lowp.m != m || h->lowp.n != n || h->lowp.fmt != fmt)
+      h->lowp.base = nullptr;
     if (capturing) {
       h->call_tags = 0;
       out->tags = &h->call_tags;
@@ -647,6 +674,32 @@ hipError_t convert_a_fp8(plu_handle h, const Ws& w, int64_t m, int64_t n, const 
   return hipSuccess;
 }
 
+// The rounded copies of A for the precision form (both storage orders), and
+// ||A||_F^2 (float64, from the fp32 values) into normA2_dev (nullable).  With
+// `reuse` -- the caller's PLU_PREC_A_UNCHANGED -- and copies of this very A
+// (same pointer, shape, leading dimension, storage order and format) still in
+// the handle's arena, nothing is converted again.
+hipError_t lowp_copies(plu_handle h, const Ws& w, int fmt, int64_t m, int64_t n, const float* A,
+                       int64_t lda, bool reuse, double* normA2_dev) {
+  const char* base = fmt == PLU_PREC_BF16 ? reinterpret_cast<const char*>(w.ab)
+                                          : reinterpret_cast<const char*>(w.a8);
+  auto& c = h->lowp;
+  const bool hit = reuse && w.on_arena && c.base == base && c.A == A && c.m == m && c.n == n &&
+                   c.lda == lda && c.fmt == fmt && c.acol == w.acol;
+  hipError_t e;
+  if (!hit) {
+    e = fmt == PLU_PREC_BF16 ? convert_a_bf16(h, w, m, n, A, lda, w.anorm)
+                             : convert_a_fp8(h, w, m, n, A, lda, w.anorm);
+    if (e != hipSuccess) return e;
+    if (w.on_arena) {
+      c.A = A; c.base = base; c.m = m; c.n = n; c.lda = lda; c.fmt = fmt; c.acol = w.acol;
+    }
+  }
+  if (normA2_dev)
+    return hipMemcpyAsync(normA2_dev, w.anorm, sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+  return hipSuccess;
+}
+
 // One pass of the FP8 form: both operands block-scaled E4M3, fp32 accumulation.
 hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n,
                         const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo) {
@@ -738,11 +791,10 @@ hipError_t range_basis(plu_handle h, const Ws& w, int64_t m, int64_t n, const fl
   const int exact_tail = (prec & PLU_PREC_REFINE_TWO) ? 2 : (prec & PLU_PREC_REFINE_LAST) ? 1 : 0;
   // the rounded copies are needed only if some pass is rounded
   const bool any_rounded = fmt != PLU_PREC_FP32 && v - 1 > exact_tail;
-  if (any_rounded && fmt == PLU_PREC_BF16) {
-    if ((e = convert_a_bf16(h, w, m, n, A, lda, normA2)) != hipSuccess) return e;
-    first = false;
-  } else if (any_rounded && fmt == PLU_PREC_FP8_E4M3) {
-    if ((e = convert_a_fp8(h, w, m, n, A, lda, normA2)) != hipSuccess) return e;
+  if (any_rounded) {
+    if ((e = lowp_copies(h, w, fmt, m, n, A, lda, (prec & PLU_PREC_A_UNCHANGED) != 0, normA2)) !=
+        hipSuccess)
+      return e;
     first = false;
   }
   // one of the v - 1 passes of Alg. 7 (the first one also yields ||A||_F^2);
@@ -1625,8 +1677,10 @@ int fixed_precision_rounds(plu_handle h, const Ws& w, int64_t m, int64_t n, cons
   for (int r = 0; r < rounds; ++r) {
     float* V = nullptr;
     int npr = 0;
+    // later rounds keep the rounded copies of A the first one made
     PLU_TRY_HIP(range_basis(h, w, m, n, A, lda, l, v, r == 0 ? Omega : nullptr,
-                            seed + (uint64_t)r, &V, &npr, prec, w.vall, w.gall, off));
+                            seed + (uint64_t)r, &V, &npr, r == 0 ? prec : prec | PLU_PREC_A_UNCHANGED,
+                            w.vall, w.gall, off));
     np += npr;
     float* Vr = w.vall + off;
     PLU_TRY_HIP(hipMemcpy2DAsync(Vr, pitch, V, pitch, rowb, n, hipMemcpyDeviceToDevice,
@@ -1802,19 +1856,17 @@ int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, 
   if (ldx < l) return -9;
   if (!out) return -10;
   if (ldo < l) return -11;
-  if (prec != PLU_PREC_FP32 && prec != PLU_PREC_BF16 && prec != PLU_PREC_FP8_E4M3) return -12;
+  const int fmt = prec & ~PLU_PREC_A_UNCHANGED;
+  if (fmt != PLU_PREC_FP32 && fmt != PLU_PREC_BF16 && fmt != PLU_PREC_FP8_E4M3) return -12;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
-  int st = ensure_ws(h, m, n, std::max<int64_t>(l, ru4(ldo)), &w, prec);
+  int st = ensure_ws(h, m, n, std::max<int64_t>(l, ru4(ldo)), &w, fmt);
   if (st) return st;
-  if (prec == PLU_PREC_BF16) {
-    PLU_TRY_HIP(convert_a_bf16(h, w, m, n, A, lda, normA2_out));
-    PLU_TRY_HIP(run_pass_bf16(h, w, trans, m, n, X, ldx, l, out, ldo));
-    return PLU_OK;
-  }
-  if (prec == PLU_PREC_FP8_E4M3) {
-    PLU_TRY_HIP(convert_a_fp8(h, w, m, n, A, lda, normA2_out));
-    PLU_TRY_HIP(run_pass_fp8(h, w, trans, m, n, X, ldx, l, out, ldo));
+  if (fmt != PLU_PREC_FP32) {
+    PLU_TRY_HIP(lowp_copies(h, w, fmt, m, n, A, lda, (prec & PLU_PREC_A_UNCHANGED) != 0,
+                            normA2_out));
+    if (fmt == PLU_PREC_BF16) PLU_TRY_HIP(run_pass_bf16(h, w, trans, m, n, X, ldx, l, out, ldo));
+    else PLU_TRY_HIP(run_pass_fp8(h, w, trans, m, n, X, ldx, l, out, ldo));
     return PLU_OK;
   }
   PLU_TRY_HIP(run_pass(h, w, trans, m, n, A, lda, X, ldx, l, out, ldo, normA2_out, nullptr,

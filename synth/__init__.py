@@ -40,5 +40,6 @@ from .generators import (  # noqa: F401
     WORKLOADS,
     workload_matrix_factors,
     workload_matrix,
+    workload_slice,
     request_stream,
 )

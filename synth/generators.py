@@ -151,6 +151,16 @@ def workload_matrix(w: Workload, m: int | None = None, n: int | None = None,
                               1000 * w.index + 1, noise, 1000 * w.index + 2, dtype)
 
 
+def workload_slice(w: Workload, rows: int, cols: int, dtype=np.float32) -> np.ndarray:
+    """The leading rows x cols block of workload ``w``'s matrix (signal part),
+    formed directly from the full-size factors in float64 and rounded:
+    X[:rows] diag(sigma) Y[:cols]^T.  Noise-free workloads only."""
+    if w.noise:
+        raise ValueError("workload_slice is for noise-free workloads")
+    X, s, Y = workload_matrix_factors(w)
+    return ((X[:rows] * s[None, :]) @ Y[:cols].T).astype(dtype)
+
+
 # ----------------------------------------------------------------------------
 # Request stream for the batched / serving form.
 # ----------------------------------------------------------------------------

@@ -365,3 +365,40 @@ def test_fixed_precision_refined_paper_types(h, t, eps, l, b, fmt):
     if f.info["tol_reached"]:
         r = O.relative_residual(A, host(f.p), host(f.q), host(f.L), host(f.U))
         assert r * r <= eps * eps + 2 * delta / ref.normA2
+
+
+# ---------------------------------------------------------------- rounded copies kept (A unchanged)
+A_UNCHANGED = 64
+
+
+@pytest.mark.parametrize("fmt", [BF16, FP8])
+def test_rounded_copies_reused_when_a_is_unchanged(h, fmt):
+    """PLU_PREC_A_UNCHANGED reuses the handle's rounded copies of A: the same
+    factors as a call that rounds A again, for fixed rank, fixed precision and
+    single passes; a call in another form or shape in between drops the
+    copies (the flag then rounds A again), so a changed A is never served
+    stale copies after such a call."""
+    A1 = lowrank_plus_noise(1500, 1200, spectrum("exp", 200, tau=15.0), 31, 32, 1e-6, 33)
+    A2 = lowrank_plus_noise(1500, 1200, spectrum("exp", 200, tau=9.0), 34, 35, 1e-6, 36)
+    Ad = dev(A1)
+    ref = h.fixed_rank(Ad, 20, 10, 4, seed=3, prec=fmt | REFINE)
+    f = h.fixed_rank(Ad, 20, 10, 4, seed=3, prec=fmt | REFINE | A_UNCHANGED)
+    for a, b in ((f.p, ref.p), (f.q, ref.q), (f.L, ref.L), (f.U, ref.U)):
+        assert np.array_equal(host(a), host(b))
+    g = h.fixed_precision(Ad, 1e-3, 10, l=100, v=4, seed=4, prec=fmt | A_UNCHANGED)
+    g0 = h.fixed_precision(Ad, 1e-3, 10, l=100, v=4, seed=4, prec=fmt)
+    assert g.rank == g0.rank
+    for a, b in ((g.p, g0.p), (g.q, g0.q), (g.L, g0.L), (g.U, g0.U)):
+        assert np.array_equal(host(a), host(b))
+    X = dev(np.random.default_rng(5).standard_normal((1200, 40)).astype(np.float32))
+    o1 = host(h.pass_(Ad, X, prec=fmt))
+    o2 = host(h.pass_(Ad, X, prec=fmt | A_UNCHANGED))
+    assert np.array_equal(o1, o2)
+    # an fp32 call lays the workspace out differently: the copies are gone,
+    # so the flag after it rounds the new contents of A
+    h.fixed_rank(Ad, 20, 10, 4, seed=3)
+    Ad.copy_(dev(A2))
+    f2 = h.fixed_rank(Ad, 20, 10, 4, seed=3, prec=fmt | REFINE | A_UNCHANGED)
+    r2 = h.fixed_rank(dev(A2), 20, 10, 4, seed=3, prec=fmt | REFINE)
+    for a, b in ((f2.p, r2.p), (f2.L, r2.L), (f2.U, r2.U)):
+        assert np.array_equal(host(a), host(b))
