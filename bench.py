@@ -432,29 +432,67 @@ def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
     return res
 
 
+SOURCE_N = 8192
+
+
 def serving_pool(pool_size, seed=5000):
-    """Host matrices of the serving workload: pool_size distinct rank-r
-    low-rank-plus-noise matrices with m, n ~ U[512, 8192], r ~ U[16, 256],
-    sigma_i = exp(-i/(r/4)), ||noise||_F = 1e-4 ||signal||_F, in pinned host
-    memory."""
+    """Host sources of the serving workload: pool_size pinned 8192 x 8192
+    low-rank-plus-noise matrices with ranks r spread evenly over [16, 256],
+    sigma_i = exp(-i/(r/4)), ||noise||_F = 1e-4 ||signal||_F.  Each request
+    takes its own m x n block of one of them (``request_stream``)."""
     import numpy as np
     import torch
     from synth import spectrum, lowrank_factors
-    rng = np.random.default_rng(seed)
     pool = []
-    for i in range(pool_size):
-        m, n = (int(x) for x in rng.integers(512, 8193, 2))
-        r = int(rng.integers(16, 257))
+    N = SOURCE_N
+    for i, r in enumerate(np.linspace(16, 256, pool_size).round().astype(int)):
+        r = int(r)
         sig = spectrum("exp", r, tau=r / 4.0)
-        X, sg, Y = lowrank_factors(m, n, sig, seed + 100 * i + 1, seed + 100 * i + 2)
-        S = (X * sg) @ Y.T
+        X, sg, Y = lowrank_factors(N, N, sig, seed + 100 * i + 1, seed + 100 * i + 2)
+        XS = (X * sg).astype(np.float32)
+        Yt = np.ascontiguousarray(Y.T.astype(np.float32))
         g = np.random.default_rng(seed + 100 * i + 3)
-        N = g.standard_normal((m, n), dtype=np.float32)
-        N *= np.float32(1e-4 * np.linalg.norm(sig) / max(np.linalg.norm(N), 1e-30))
-        A = torch.empty((m, n), dtype=torch.float32, pin_memory=True)
-        A.numpy()[...] = (S + N).astype(np.float32)
+        scale = np.float32(1e-4 * np.linalg.norm(sig) / N)
+        A = torch.empty((N, N), dtype=torch.float32, pin_memory=True)
+        An = A.numpy()
+        for r0 in range(0, N, 1024):
+            blk = XS[r0:r0 + 1024] @ Yt
+            blk += scale * g.standard_normal((blk.shape[0], N), dtype=np.float32)
+            An[r0:r0 + 1024] = blk
         pool.append((A, r))
     return pool
+
+
+def request_stream(pool, count, seed):
+    """cfg5's request distribution: per request m, n ~ U[512, 8192] and
+    r ~ U[16, 256]; the data is an m x n block at a random offset of the
+    source whose rank is nearest r (a strided view of pinned host memory)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ranks = np.array([r for (_, r) in pool])
+    out = []
+    for i in range(count):
+        m, n = (int(x) for x in rng.integers(512, 8193, 2))
+        r = int(rng.integers(16, 257))
+        j = int(np.argmin(np.abs(ranks - r)))
+        r0 = int(rng.integers(0, SOURCE_N - m + 1))
+        c0 = int(rng.integers(0, SOURCE_N - n + 1))
+        src = pool[j][0]
+        out.append((src[r0:r0 + m, c0:c0 + n], int(ranks[j])))
+    return out
+
+
+def pass_roofline_s(prm, m, n, rank):
+    """Attainable time of a request's passes over A on their roofline: each
+    pass max(2 m n c / FP32 MFMA peak, 4 m n / HBM peak) with c its columns
+    (every other step taken as free)."""
+    def one(c):
+        return max(2.0 * m * n * c / (PEAK_FP32_MFMA_TFLOPS * 1e12), 4.0 * m * n / (PEAK_HBM_GBS * 1e9))
+    if prm["mode"] == 0:
+        l = prm["k"] + prm["p_over"]
+        return (prm["v"] - 1) * one(l) + one(prm["k"])
+    l = min(50 * 16, 16 * ((min(m, n) - 1) // 16))
+    return prm["v"] * one(l)
 
 
 def request_params(i, r, m, n, rng):
@@ -481,13 +519,11 @@ def batched_vs_single(h, pool, count=32):
     import torch
     rng = np.random.default_rng(11)
     dev = torch.device("cuda:0")
-    dA = [A.to(dev, non_blocking=True) for (A, r) in pool]
     probs = []
-    for i in range(count):
-        j = i % len(pool)
-        m, n = pool[j][0].shape
-        prm = request_params(i, pool[j][1], m, n, rng)
-        probs.append(dict(A=dA[j], **prm))
+    for i, (Ab, r) in enumerate(request_stream(pool, count, seed=12)):
+        m, n = Ab.shape
+        prm = request_params(i, r, m, n, rng)
+        probs.append(dict(A=Ab.to(dev).contiguous(), **prm))
     torch.cuda.synchronize()
 
     def single():
@@ -527,10 +563,14 @@ def batched_vs_single(h, pool, count=32):
     t_fr_batch = time.perf_counter() - t0
     flops = sum(request_flops(pr, pr["A"].shape[0], pr["A"].shape[1], o.rank)
                 for pr, o in zip(probs, b_out))
+    t_att = sum(pass_roofline_s(pr, pr["A"].shape[0], pr["A"].shape[1], o.rank)
+                for pr, o in zip(probs, b_out))
     return {
-        "problems": count, "distinct_matrices": len(pool),
+        "problems": count, "shapes": "per problem: m, n ~ U[512, 8192], r ~ U[16, 256]",
         "single_calls_ms": round(t_single * 1e3, 2), "batched_ms": round(t_batch * 1e3, 2),
         "speedup": round(t_single / t_batch, 3), "batched_gflops": round(flops / t_batch / 1e9, 1),
+        "pass_roofline_ms": round(t_att * 1e3, 3),
+        "attainable_frac": round(t_att / t_batch, 4),
         "results_identical": bool(same),
         "fixed_rank_subset": {"problems": len(fr), "batched_ms": round(t_fr_batch * 1e3, 2),
                               "graph_replay_ms": round(t_graph * 1e3, 2)},
@@ -538,10 +578,10 @@ def batched_vs_single(h, pool, count=32):
 
 
 def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
-    """Replay of a Poisson request stream through the serving loop: requests
-    cycle the pool's matrices (host, pinned); latency = completion minus
-    scheduled arrival.  rate None: every request submitted at once (the
-    loop's capacity)."""
+    """Replay of a Poisson request stream through the serving loop: each
+    request its own m x n block of a pinned host source (request_stream);
+    latency = completion minus scheduled arrival.  rate None: every request
+    submitted at once (the loop's capacity)."""
     import threading
     import numpy as np
     import paper_2002_07138_amd as plu
@@ -558,12 +598,12 @@ def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
                 time.sleep(0.0005)
             results[i] = srv.wait(tickets[i])
 
+    stream = request_stream(pool, count, seed=seed + 2)
     th = threading.Thread(target=waiter)
     th.start()
     t_start = time.perf_counter()
     for i in range(count):
-        j = i % len(pool)
-        A, r = pool[j]
+        A, r = stream[i]
         m, n = A.shape
         prm = request_params(i, r, m, n, rng)
         delay = t_start + sched[i] - time.perf_counter()
@@ -580,14 +620,19 @@ def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
     queue = np.array([res["t_admit"] - res["t_submit"] for res in results])
     service = np.array([res["t_done"] - res["t_admit"] for res in results])
     flops = sum(request_flops(prm, m, n, res["rank"]) for (prm, m, n), res in zip(meta, results))
+    t_att = sum(pass_roofline_s(prm, m, n, res["rank"]) for (prm, m, n), res in zip(meta, results))
     ok = sum(1 for res in results if res["status"] in (0, 1, 2))
     return {
-        "requests": count, "rate_per_s": rate, "distinct_matrices": len(pool),
+        "requests": count, "rate_per_s": rate,
+        "shapes": "per request: m, n ~ U[512, 8192], r ~ U[16, 256]",
+        "sources": f"{len(pool)} pinned {SOURCE_N}^2 matrices, ranks {pool[0][1]}..{pool[-1][1]}",
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
         "mean_ms": round(float(lat.mean()) * 1e3, 2),
         "throughput_req_per_s": round(count / (t_end - t_start), 1),
         "gflops": round(flops / (t_end - t_start) / 1e9, 1),
+        "pass_roofline_s": round(t_att, 4),
+        "attainable_frac": round(t_att / (t_end - t_start), 4),
         "completed_ok": ok,
         "mean_queue_ms": round(float(queue.mean()) * 1e3, 2),
         "mean_service_ms": round(float(service.mean()) * 1e3, 2),
@@ -602,8 +647,15 @@ def serving(pool, count=1024, rate=200.0, budget_gb=64, slots=64, seed=5000):
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2002_07138_amd", "csrc", "k_gemm.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """sha256[:16] over the pass kernel's source and the split planner
+    (pass_plan in api.hip): the counted bytes depend on both."""
+    csrc = os.path.join(ROOT, "paper_2002_07138_amd", "csrc")
+    api = open(os.path.join(csrc, "api.hip")).read()
+    i = api.index("GemmPlan pass_plan(")
+    planner = api[i:api.index("\n}\n", i) + 3]
+    h = hashlib.sha256(open(os.path.join(csrc, "k_gemm.hip"), "rb").read())
+    h.update(planner.encode())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():
@@ -782,13 +834,32 @@ def main():
                 torch.empty((m, k), dtype=torch.float32, device=dev),
                 torch.empty((k, n), dtype=torch.float32, device=dev)) for v in VS}
 
+    probs = [dict(A=A, mode=0, k=k, p_over=p_over, v=v, seed=0, out=outs[v]) for v in VS]
+
     def step(seed):
+        # the four factorizations as one batch (plu_batched): side by side on
+        # the handle's streams, so one's LU panels overlap another's passes
+        for v, pr in zip(VS, probs):
+            pr["seed"] = seed * 16 + v
+        h.batched(probs)
+
+    def step_single(seed):
+        # the same four factorizations one call after another on one stream
         for v in VS:
             h.fixed_rank(A, k, p_over, v, seed=seed * 16 + v, sync_info=False, out=outs[v])
 
     for i in range(args.warmup):
+        step_single(1000 + i)
         step(1000 + i)
     torch.cuda.synchronize()
+    # the batch gives the single calls' bits
+    step(5)
+    torch.cuda.synchronize()
+    got = {v: [t.clone() for t in outs[v]] for v in VS}
+    step_single(5)
+    torch.cuda.synchronize()
+    batch_identical = all(all(torch.equal(a, b) for a, b in zip(got[v], outs[v])) for v in VS)
+    del got
     # per-step events on the library's stream (no host synchronization between steps)
     step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
@@ -803,6 +874,28 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     flops_step = sum(flops_fixed_rank(m, n, k, l, v) for v in VS)
     gflops = flops_step / (elapsed / args.steps) / 1e9
+
+    # the same step as four single calls in sequence, and as a graph replay
+    # of the batch (same requests every replay)
+    single_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(args.steps)]
+    for i in range(args.steps):
+        single_ev[i][0].record(stream)
+        step_single(i)
+        single_ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    single_ms = [e0.elapsed_time(e1) for e0, e1 in single_ev]
+    for v, pr in zip(VS, probs):
+        pr["seed"] = 31 * 16 + v
+    h.batched(probs, graph=True)
+    graph_ms = []
+    for i in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.batched(probs, graph=True)
+        e1.record(stream)
+        e1.synchronize()
+        graph_ms.append(e0.elapsed_time(e1))
 
     # per-v latency (one call each, events on the library's stream)
     per_v = {}
@@ -870,6 +963,12 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
         "step_ms": _stats(step_ms),
+        "step": "the four factorizations (v = 2, 3, 4, 5) as one plu_batched call, side by side "
+                "on the handle's streams; bitwise equal to four single calls: "
+                + str(bool(batch_identical)),
+        "single_calls_step_ms": _stats(single_ms),
+        "single_calls_gflops": round(flops_step / (float(np.median(single_ms)) * 1e-3) / 1e9, 2),
+        "batch_graph_replay_step_ms": _stats(graph_ms),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

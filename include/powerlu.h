@@ -360,10 +360,18 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
  * Outputs (host, in each request): rank, status and info; the call
  * synchronizes once, at the end (the fixed-precision ranks stay on the
  * device until then, as in plu_fixed_precision).
- * flags: PLU_BATCH_GRAPH captures the merged launch sequence of the batch
- * (fixed-rank and fixed-precision problems alike) into a HIP graph kept by
- * the handle and replays it when the next call has the same requests (same
- * shapes and pointers).
+ * Execution: the problems run side by side on up to four streams of the
+ * handle, forked from its stream and joined back into it (the longest
+ * problem first, each to the least loaded stream), so that one problem's
+ * latency-bound steps (the LU panels, the thin QR) overlap other problems'
+ * passes over A.  A stream with one problem launches its kernels as the
+ * single call does; a stream with several merges their launch sequences into
+ * grouped launches.  Results are bitwise those of the single calls either way.
+ * flags: PLU_BATCH_GRAPH captures the batch's launches (fixed-rank and
+ * fixed-precision problems alike, every stream) into a HIP graph kept by the
+ * handle and replays it when the next call has the same requests (same
+ * shapes and pointers).  PLU_BATCH_ONE_STREAM keeps every problem on the
+ * handle's stream, in one merged launch sequence.
  * Returns PLU_OK, or -3 when some request is invalid (its status then holds
  * -i for its i-th field, counted from 1 in declaration order).             */
 /* ---- Pivot trace: the pivot rows and relative pivot gaps of every GETRF of
@@ -410,6 +418,7 @@ typedef struct {
 } plu_request;
 
 #define PLU_BATCH_GRAPH 1
+#define PLU_BATCH_ONE_STREAM 2
 
 int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags);
 

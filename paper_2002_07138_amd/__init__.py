@@ -46,6 +46,7 @@ _ENTRY_POINTS = [
     "plu_server_wait", "plu_server_destroy", "plu_fixed_rank_static",
 ]
 BATCH_GRAPH = 1
+BATCH_ONE_STREAM = 2
 
 
 class PluInfo(ctypes.Structure):
@@ -574,12 +575,14 @@ class Handle:
         kk = int(info.rank)
         return Factors(p, q, L[:, :kk], U[:kk], kk, info.as_dict())
 
-    def batched(self, problems, graph=False):
+    def batched(self, problems, graph=False, one_stream=False):
         """Solve many problems in one batched call (plu_batched).  Each
         problem is a dict with A (device fp32 matrix) and either
         mode=0, k, p_over, v or mode=1, eps, b, l (0: default), v,
-        column_exact; optional Omega, seed.  Returns a list of Factors (the
-        fixed-precision ones trimmed to their rank)."""
+        column_exact; optional Omega, seed, out = (p, q, L, U) device
+        buffers.  one_stream: every problem on the handle's stream (no side
+        streams).  Returns a list of Factors (the fixed-precision ones
+        trimmed to their rank)."""
         t = self._torch
         reqs = (PluRequest * len(problems))()
         keep = []
@@ -605,14 +608,22 @@ class Handle:
                 _check_mat(Om, "Omega")
             r.Omega = Om.data_ptr() if Om is not None else None
             r.seed = int(pr.get("seed", 0))
-            p = t.empty(m, dtype=t.int32, device=A.device)
-            q = t.empty(n, dtype=t.int32, device=A.device)
-            L = t.empty((m, cap), dtype=t.float32, device=A.device)
-            U = t.empty((cap, n), dtype=t.float32, device=A.device)
-            r.p, r.q, r.L, r.ldl, r.U, r.ldu = p.data_ptr(), q.data_ptr(), L.data_ptr(), cap, \
-                U.data_ptr(), n
+            if pr.get("out") is not None:
+                p, q, L, U = pr["out"]
+                _check_mat(L, "L")
+                _check_mat(U, "U")
+                if L.shape[1] < cap or U.shape[0] < cap:
+                    raise ValueError("out: L needs >= %d columns and U >= %d rows" % (cap, cap))
+            else:
+                p = t.empty(m, dtype=t.int32, device=A.device)
+                q = t.empty(n, dtype=t.int32, device=A.device)
+                L = t.empty((m, cap), dtype=t.float32, device=A.device)
+                U = t.empty((cap, n), dtype=t.float32, device=A.device)
+            r.p, r.q, r.L, r.ldl, r.U, r.ldu = p.data_ptr(), q.data_ptr(), L.data_ptr(), \
+                _ld(L), U.data_ptr(), _ld(U)
             keep.append((p, q, L, U, A, Om))
-        rc = _lib().plu_batched(self._h, len(problems), reqs, BATCH_GRAPH if graph else 0)
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_ONE_STREAM if one_stream else 0)
+        rc = _lib().plu_batched(self._h, len(problems), reqs, flags)
         if rc != PLU_OK:
             bad = [(i, r.status) for i, r in enumerate(reqs) if r.status != 0]
             raise PowerLUError(rc, f"plu_batched (request statuses {bad})")

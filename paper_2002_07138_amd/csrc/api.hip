@@ -63,6 +63,15 @@ struct plu_handle_s {
   std::vector<unsigned char> gsig;
   plu::MergeBuffers gbuf;
   hipStream_t gstream = nullptr;   // capture stream (the handle's may be the null stream)
+  // batched path: the streams a batch's problems run on side by side, forked
+  // from and joined back into the caller's stream, with the merged-launch
+  // tables of each (eager, and kept for the captured graph)
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSide] = {};
+  plu::MergeBuffers sbuf[kSide];
+  plu::MergeBuffers sgbuf[kSide];
   // pivot trace of the last call (plu_set_pivot_trace / plu_pivot_trace):
   // device copies of every GETRF's pivot rows and gaps, in order
   int32_t* trace_piv = nullptr;
@@ -445,7 +454,10 @@ bool tune_enabled() {
 
 GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, float* out, int64_t ldo) {
   const int64_t P = g.P, R = g.R, C = g.C;
-  const GemmPlan def = plan_gemm(P, R, C, kMaxSplit, kTargetWgs);
+  // split boundaries on whole 128-byte lines of A's rows (32 floats), so no
+  // line is fetched by two workgroups of adjacent splits
+  constexpr int kLineAlign = 32;
+  const GemmPlan def = plan_gemm(P, R, C, kMaxSplit, kTargetWgs, kLineAlign);
   auto fits = [&](const GemmPlan& p) {
     return (p.nsplit == 1 || (int64_t)p.nsplit * P * part_ld(ldo) <= w.part_cap) &&
            (int64_t)p.pblocks * p.nsplit <= w.sumsq_cap;
@@ -469,7 +481,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
       if (bp != only_bp) continue;
     }
     for (int slots : {512, 768, 1024, 1280, 1536, 2048}) {
-      GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots, GEMM_BK, bp);
+      GemmPlan p = plan_gemm(P, R, C, kMaxSplit, slots, kLineAlign, bp);
       if (!fits(p)) continue;
       bool dup = false;
       for (auto& c : cands) dup |= c.nsplit == p.nsplit && c.bp == p.bp;
@@ -500,11 +512,20 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
       else cand_ms[c] = std::min(cand_ms[c], ms);
     }
   }
+  // the fastest, or among the candidates within 2% of it the one with the
+  // fewest splits: fewer split partials written and read back (each split
+  // adds 8 P l bytes of traffic to the pass)
   GemmPlan best = cands[0];
   float best_ms = 1e30f;
+  for (size_t c = 0; c < cands.size(); ++c)
+    if (cand_ok[c]) best_ms = std::min(best_ms, cand_ms[c]);
+  float kept_ms = 1e30f;
+  int kept_split = 1 << 30;
   for (size_t c = 0; c < cands.size(); ++c) {
-    if (cand_ok[c] && cand_ms[c] < best_ms) {
-      best_ms = cand_ms[c];
+    if (!cand_ok[c] || cand_ms[c] > best_ms * 1.02f) continue;
+    if (cands[c].nsplit < kept_split || (cands[c].nsplit == kept_split && cand_ms[c] < kept_ms)) {
+      kept_split = cands[c].nsplit;
+      kept_ms = cand_ms[c];
       best = cands[c];
     }
   }
@@ -1005,6 +1026,7 @@ void drop_graph(plu_handle h) {
   h->graph = nullptr;
   h->gsig.clear();
   h->gbuf.destroy();
+  for (auto& b : h->sgbuf) b.destroy();
 }
 
 // Checks one batched request; returns 0 or -(field index, from 1, in the
@@ -1106,6 +1128,101 @@ hipError_t record_and_run(plu_handle h, std::vector<BatchProblem*>& ps, F fn, Me
   (void)dry_size_only;
   (void)table_bytes;
   return run_merged(lists, h->stream, h->cu_count, buf, nullptr);
+}
+
+hipError_t ensure_side_streams(plu_handle h) {
+  if (h->fork_ev) return hipSuccess;
+  hipError_t e;
+  for (int i = 0; i < plu_handle_s::kSide; ++i) {
+    if (!h->side[i] && (e = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking)) != hipSuccess)
+      return e;
+    if (!h->join_ev[i] &&
+        (e = hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming)) != hipSuccess)
+      return e;
+  }
+  return hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+}
+
+// The problems of a batch side by side on up to kSide streams forked from
+// the caller's stream (and joined back into it): the longest problem first,
+// each to the least loaded stream (work estimated as m n l v).  A stream with
+// one problem launches its kernels directly; a stream with several runs their
+// merged launch sequence.  The LU panels' workgroups wait on each other, so
+// the merged panels of one stream are held to cu_count / streams workgroups
+// at a time, and a direct problem's panel has at most 64: the panels in
+// flight at once always fit on the device.
+struct SidePlan {
+  int S = 0;
+  std::vector<std::vector<BatchProblem*>> groups;
+  std::vector<std::vector<const Recorder*>> lists;
+};
+
+// Partition, recording of the merged streams' launches, and (for a graph
+// capture, which may allocate nothing) their table buffers: all before any
+// launch or capture.
+hipError_t side_prepare(plu_handle h, std::vector<BatchProblem*>& all, bool capture,
+                        SidePlan& sp) {
+  hipError_t e;
+  if ((e = ensure_side_streams(h)) != hipSuccess) return e;
+  sp.S = (int)std::min<size_t>(plu_handle_s::kSide, all.size());
+  std::vector<BatchProblem*> order(all);
+  auto work = [](const BatchProblem* b) {
+    return (double)b->r->m * (double)b->r->n * (double)b->l * (double)b->r->v;
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](const BatchProblem* a, const BatchProblem* b) { return work(a) > work(b); });
+  sp.groups.assign((size_t)sp.S, {});
+  sp.lists.assign((size_t)sp.S, {});
+  std::vector<double> load((size_t)sp.S, 0.0);
+  for (BatchProblem* b : order) {
+    const size_t g = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    sp.groups[g].push_back(b);
+    load[g] += work(b);
+  }
+  for (int g = 0; g < sp.S; ++g) {
+    if (sp.groups[(size_t)g].size() < 2) continue;
+    for (BatchProblem* b : sp.groups[(size_t)g]) {
+      b->rec.ops.clear();
+      thread_recorder() = &b->rec;
+      e = batch_phase_a(*b);
+      thread_recorder() = nullptr;
+      if (e != hipSuccess) return e;
+      sp.lists[(size_t)g].push_back(&b->rec);
+    }
+    if (capture &&
+        (e = h->sgbuf[g].reserve(merged_table_bytes(sp.lists[(size_t)g], h->cu_count / sp.S))) !=
+            hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// The launches of a prepared batch, forked from and joined into stream s
+// (capture: s is capturing a graph; the merged tables live in the buffers
+// kept for it).
+hipError_t side_launch(plu_handle h, hipStream_t s, SidePlan& sp, bool capture) {
+  hipError_t e;
+  if ((e = hipEventRecord(h->fork_ev, s)) != hipSuccess) return e;
+  for (int g = 0; g < sp.S; ++g)
+    if ((e = hipStreamWaitEvent(h->side[g], h->fork_ev, 0)) != hipSuccess) return e;
+  for (int g = 0; g < sp.S; ++g) {
+    if (sp.groups[(size_t)g].size() == 1) {
+      BatchProblem& b = *sp.groups[(size_t)g][0];
+      b.hs.stream = h->side[g];
+      if ((e = batch_phase_a(b)) != hipSuccess) return e;
+    } else {
+      MergeBuffers& buf = capture ? h->sgbuf[g] : h->sbuf[g];
+      buf.capturing = capture;
+      e = run_merged(sp.lists[(size_t)g], h->side[g], h->cu_count / sp.S, buf, nullptr);
+      buf.capturing = false;
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int g = 0; g < sp.S; ++g) {
+    if ((e = hipEventRecord(h->join_ev[g], h->side[g])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, h->join_ev[g], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Inputs of a batch that decide its launch sequence (for graph reuse).
@@ -1799,6 +1916,12 @@ int plu_destroy(plu_handle h) {
   (void)hipStreamSynchronize(h->stream);
   drop_graph(h);
   if (h->gstream) (void)hipStreamDestroy(h->gstream);
+  for (int i = 0; i < plu_handle_s::kSide; ++i) {
+    if (h->side[i]) (void)hipStreamDestroy(h->side[i]);
+    if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+    h->sbuf[i].destroy();
+  }
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   h->mbuf.destroy();
   if (h->arena) (void)hipFree(h->arena);
   if (h->batch_arena) (void)hipFree(h->batch_arena);
@@ -2748,7 +2871,37 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       b.hs.gbuf = MergeBuffers();
       all.push_back(&b);
     }
-    if (use_graph) {
+    const bool one_stream = (flags & PLU_BATCH_ONE_STREAM) != 0;
+    if (use_graph && !one_stream) {
+      drop_graph(h);
+      if (!h->gstream) PLU_TRY_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+      SidePlan sp;
+      hipError_t pe = side_prepare(h, all, true, sp);
+      if (pe != hipSuccess) return pe == hipErrorOutOfMemory ? PLU_ERR_OOM : PLU_ERR_HIP;
+      PLU_TRY_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = side_launch(h, h->gstream, sp, true);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(h->gstream, &g);
+      if (ce != hipSuccess || ee != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        std::fprintf(stderr, "libpowerlu: batch graph capture failed: %s / %s\n",
+                     hipGetErrorString(ce), hipGetErrorString(ee));
+        if (ce == hipErrorOutOfMemory) return PLU_ERR_OOM;
+        return ce == hipErrorStreamCaptureUnsupported || ee == hipErrorStreamCaptureUnsupported
+                   ? PLU_ERR_NOT_IMPLEMENTED
+                   : PLU_ERR_HIP;
+      }
+      h->graph = g;
+      PLU_TRY_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+      h->gsig = sig;
+      PLU_TRY_HIP(hipGraphLaunch(h->gexec, h->stream));
+    } else if (!one_stream) {
+      SidePlan sp;
+      hipError_t e = side_prepare(h, all, false, sp);
+      if (e == hipSuccess) e = side_launch(h, h->stream, sp, false);
+      if (e != hipSuccess) return e == hipErrorOutOfMemory ? PLU_ERR_OOM : PLU_ERR_HIP;
+    } else if (use_graph) {
       drop_graph(h);
       // record, size the tables outside the capture, then capture the launches
       std::vector<const Recorder*> lists;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <mutex>
 #include <unordered_set>
 
@@ -14,6 +15,14 @@ namespace plu {
 Recorder*& thread_recorder() {
   static thread_local Recorder* r = nullptr;
   return r;
+}
+
+bool coop_launch() {
+  static const bool on = [] {
+    const char* e = std::getenv("PLU_COOP_LAUNCH");
+    return e && e[0] == '1';
+  }();
+  return on;
 }
 
 hipError_t set_dynamic_lds(const void* fn, size_t bytes) {

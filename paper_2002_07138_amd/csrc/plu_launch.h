@@ -103,6 +103,18 @@ Recorder*& thread_recorder();
 
 hipError_t set_dynamic_lds(const void* fn, size_t bytes);
 
+// Whether the kernels whose workgroups wait on each other (the LU panel) go
+// out as cooperative launches (PLU_COOP_LAUNCH=1) or as ordinary ones (the
+// default).  A cooperative launch waits for the device to drain the other
+// queues' work, which cost about 30 us per panel and kept panels from
+// overlapping other streams' kernels.  An ordinary launch relies on the
+// grid's workgroups all becoming resident: they are few (at most 64 of 512
+// threads per panel, and the batched path keeps the panels in flight within
+// one per CU), every other kernel's workgroups finish on their own and free
+// their slots, and every wait in the panel is bounded in time (a starved
+// panel returns PLU_ERR_TIMEOUT, it does not hang).
+bool coop_launch();
+
 // Pinned host staging and device copy of the argument tables of a merged
 // launch sequence (owned by a handle; grown on demand).
 struct MergeBuffers {
@@ -147,6 +159,11 @@ hipError_t launch_grouped(const void* tab, const GroupDim* dims, const uint32_t*
       hipError_t e = set_dynamic_lds(fc, dynlds);
       if (e != hipSuccess) return e;
     }
+    if (!coop_launch()) {
+      hipLaunchKernelGGL((k_group_coop<Args, Body, NTHR, MINW>), dim3(total), dim3(NTHR), dynlds,
+                         s, t, dims, start, n);
+      return hipGetLastError();
+    }
     void* params[] = {(void*)&t, (void*)&dims, (void*)&start, (void*)&n};
     return hipLaunchCooperativeKernel(fc, dim3(total), dim3(NTHR), params, (unsigned)dynlds, s);
   }
@@ -183,7 +200,7 @@ hipError_t dispatch(const Args& a, dim3 grid, size_t dynlds, hipStream_t s, bool
     hipError_t e = set_dynamic_lds(fn, dynlds);
     if (e != hipSuccess) return e;
   }
-  if (coop) {
+  if (coop && coop_launch()) {
     void* params[] = {(void*)&a};
     return hipLaunchCooperativeKernel(fn, grid, dim3(NTHR), params, (unsigned)dynlds, s);
   }

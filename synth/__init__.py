@@ -12,6 +12,8 @@ Matrix families
   Type 1 (slow decay)      sigma_k = k^-2,
   Type 2 (fast decay)      sigma_k = exp(-k/7),
   Type 3 (S-shaped decay)  sigma_k = 1e-4 + 1/(1 + exp(k - 30)).
+  ``paper_type_family(n, seed)`` builds several types on one pair of
+  factors (Table 1's size, n = 8000, without three pairs of n x n QRs).
 * ``lowrank_plus_noise``: X diag(sigma) Y^T + noise with X, Y the Q factors
   of seeded Gaussian matrices, the workload shapes used for measurement
   (square 2000, 20000, 32768; 30000 x 20000; mixed request sizes).
@@ -31,6 +33,7 @@ from .generators import (  # noqa: F401
     spectrum,
     orthonormal,
     paper_type,
+    paper_type_family,
     lowrank_factors,
     lowrank_plus_noise,
     gaussian_omega,

@@ -57,6 +57,26 @@ def paper_type(t: int, n: int, seed: int, m: int | None = None,
     return (U * s[None, :]) @ V.T
 
 
+def paper_type_family(n: int, seed: int, types=(1, 2, 3), dtype=np.float32,
+                      chunk: int = 2000) -> dict:
+    """Matrices of several Matrix Types (Sec. 6.2) at size n x n sharing one
+    pair of random orthonormal factors U, V (the same draws ``paper_type``
+    makes for ``seed``), so the two n x n QRs are paid once for all types:
+    {t: U diag(sigma_t) V^T}, formed in float64 row chunks and rounded to
+    ``dtype``."""
+    U = orthonormal(np.random.default_rng(seed * 1000 + 0), n, n)
+    V = orthonormal(np.random.default_rng(seed * 1000 + 1), n, n)
+    out = {}
+    for t in types:
+        s = spectrum(f"type{t}", n)
+        A = np.empty((n, n), dtype=dtype)
+        for r0 in range(0, n, chunk):
+            r1 = min(n, r0 + chunk)
+            A[r0:r1] = (U[r0:r1] * s[None, :]) @ V.T
+        out[t] = A
+    return out
+
+
 def lowrank_factors(m: int, n: int, sigma: np.ndarray, seed_left: int,
                     seed_right: int):
     """(X, sigma, Y) with X (m x r), Y (n x r) Q factors of seeded Gaussians."""

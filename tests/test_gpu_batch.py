@@ -1,5 +1,7 @@
 """Batched problems (plu_batched): many fixed-rank and fixed-precision
-problems of uneven shapes merged into grouped launches.  Every problem runs
+problems of uneven shapes, side by side on the handle's streams (a stream
+with several problems merges them into grouped launches), or all merged on
+one stream (one_stream).  Every problem runs
 the same kernels on the same data as its single-problem call, so each result
 must be bit-identical to that call; the single-problem path is itself
 checked against the oracle by the other GPU tests, and one problem here is
@@ -57,10 +59,14 @@ def _same(f, g):
         assert np.array_equal(host(a), host(b))
 
 
-def test_batch_matches_single_calls_bitwise(h):
-    probs = _problems(1)
+@pytest.mark.parametrize("one_stream", [False, True])
+@pytest.mark.parametrize("count", [3, 8])
+def test_batch_matches_single_calls_bitwise(h, one_stream, count):
+    """count 3: one problem per side stream (direct launches); count 8: two
+    per stream (merged launches on each)."""
+    probs = _problems(1)[:count]
     singles = [_single(h, pr) for pr in probs]
-    outs = h.batched(probs)
+    outs = h.batched(probs, one_stream=one_stream)
     for pr, f, g in zip(probs, outs, singles):
         _same(f, g)
         assert f.info["passes"] == pr["v"]
@@ -91,14 +97,16 @@ def test_batch_of_one_and_repeat(h):
     _same(a[0], _single(h, probs[0]))
 
 
-def test_batch_graph_replays_match_eager(h):
-    """Fixed-rank batch captured into a HIP graph: the first call captures
-    and launches, later calls replay; every replay (with other eager work and
-    synchronizations in between) equals the eager single-problem results."""
+@pytest.mark.parametrize("one_stream", [False, True])
+def test_batch_graph_replays_match_eager(h, one_stream):
+    """Fixed-rank batch captured into a HIP graph (side by side: one branch
+    per stream): the first call captures and launches, later calls replay;
+    every replay (with other eager work and synchronizations in between)
+    equals the eager single-problem results."""
     probs = [p for p in _problems(3) if p["mode"] == 0]
     singles = [_single(h, pr) for pr in probs]
     for rep in range(3):
-        outs = h.batched(probs, graph=True)
+        outs = h.batched(probs, graph=True, one_stream=one_stream)
         for f, g in zip(outs, singles):
             _same(f, g)
         # unrelated eager work between replays
@@ -114,12 +122,14 @@ def test_batch_rejects_invalid_request(h):
         h.batched([dict(A=A, mode=0, k=70, p_over=20, v=3)])
 
 
+@pytest.mark.parametrize("one_stream", [False, True])
 @pytest.mark.parametrize("rows", [64, 128])
-def test_batch_tuned_plans_match_single_calls(h, rows, monkeypatch):
+def test_batch_tuned_plans_match_single_calls(h, rows, one_stream, monkeypatch):
     """Passes large enough for the split tuner (2 m n l >= 2e10 flops), with
     the tuner held to one row-block size: the plan tuned on the single calls
-    also runs the batch's grouped launches (the 64- or 128-row grouped
-    kernel), so the batch still equals the single calls bitwise."""
+    also runs the batch's launches (one_stream: the 64- or 128-row grouped
+    kernel; side by side: the single calls' kernels on two streams at once),
+    so the batch still equals the single calls bitwise."""
     monkeypatch.setenv("PLU_AUTOTUNE_ROWS", str(rows))
     m, n = 9611 + rows, 9600
     gen = torch.Generator(device="cuda:0")
@@ -131,7 +141,7 @@ def test_batch_tuned_plans_match_single_calls(h, rows, monkeypatch):
     probs = [dict(A=A, mode=0, k=100, p_over=10, v=3, seed=1),
              dict(A=A, mode=0, k=100, p_over=10, v=4, seed=2)]
     singles = [_single(h, pr) for pr in probs]
-    outs = h.batched(probs)
+    outs = h.batched(probs, one_stream=one_stream)
     for f, g in zip(outs, singles):
         _same(f, g)
     del A, U, V
