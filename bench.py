@@ -64,6 +64,7 @@ def flops_fixed_precision(m: int, n: int, l: int, k: int, v: int) -> float:
 FORMS = {"bf16": 1, "fp8_e4m3": 2, "bf16+refine_last": 1 | 16, "fp8_e4m3+refine_last": 2 | 16,
          "fp8_e4m3+refine_two": 2 | 32}
 A_UNCHANGED = 64
+FP64_INDICATOR = 128
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP8_MFMA_TFLOPS = 5000.0
 
@@ -229,15 +230,21 @@ def rect30000_section(h, reps=3, cpu=True):
             torch.zeros(1, dtype=torch.int32, device=dev))
     res = {"workload": w.name, "m": m, "n": n, "eps": eps, "b": b, "l": l, "v": v,
            "input_generation_s": round(gen, 2), "rules": {}}
-    for col in (True, False):
-        f = h.fixed_precision(A, eps, b, l=l, v=v, column_exact=col, seed=41)
+    for name, col, prec in (("column", True, 0), ("block", False, 0),
+                            ("column+fp64_indicator", True, FP64_INDICATOR)):
+        f = h.fixed_precision(A, eps, b, l=l, v=v, column_exact=col, seed=41, prec=prec)
         r = h.residual(A, f)
         ts = _event_times(lambda: h.fixed_precision(A, eps, b, l=l, v=v, column_exact=col, seed=41,
-                                                    sync_info=False, out=outs), reps)
+                                                    prec=prec, sync_info=False, out=outs), reps)
         fl = flops_fixed_precision(m, n, l, f.rank, v)
-        res["rules"]["column" if col else "block"] = {
+        res["rules"][name] = {
             "rank": f.rank, "tol_reached": f.info["tol_reached"], "residual": r,
+            "E_final_rel": f.info["E_final"] / f.info["normA2"],
             "ms": _stats(ts), "gflops": round(fl / (np.median(ts) * 1e-3) / 1e9, 1)}
+        if prec:
+            # its extra float64 work: G = A V (2 m n l) and the two Grams (l^2 (m + n))
+            extra = 2.0 * m * n * l + 1.0 * l * l * (m + n)
+            res["rules"][name]["fp64_extra_flops"] = extra
     t = _pass_times(h, A, l, reps=5)
     ms = 0.5 * (t["N"] + t["T"])
     res["pass"] = {"ms": t, "bound": "mfma",

@@ -92,7 +92,16 @@ typedef enum {
                               4 m n or 2 m n written).  The caller guarantees A is
                               unchanged; without a matching copy the flag does nothing.
                               Any call on the handle in another format or shape
-                              invalidates the copies. */
+                              invalidates the copies. */,
+  PLU_PREC_FP64_INDICATOR = 128 /* flag, fixed precision only (any format; dense A, one
+                              round): the stopping indicator of Thm 4.3 from G = A V
+                              with float64 products and sums, first-order corrected for
+                              the basis' deviation from orthonormality (V^T V - I in
+                              float64), instead of the float32 column energies of G.  The
+                              float32 indicator resolves E to about 1e-8 ||A||_F^2, so
+                              tolerances eps below about 3e-4 need this form; it costs
+                              one more pass over A in float64 and two l x l float64
+                              Gram products. */
 } plu_prec;
 
 /* Storage order of the input matrix A (the paper's A is m x n, Def. 1.1).

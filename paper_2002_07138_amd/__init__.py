@@ -31,6 +31,7 @@ PREC_FP8_E4M3 = 2
 PREC_REFINE_LAST = 16
 PREC_REFINE_TWO = 32
 PREC_A_UNCHANGED = 64
+PREC_FP64_INDICATOR = 128
 LAYOUT_ROW = 0
 LAYOUT_COL = 1
 

@@ -91,12 +91,22 @@ inline int64_t ru4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 inline bool valid_layout(int32_t layout) { return layout == PLU_ROW_MAJOR || layout == PLU_COL_MAJOR; }
 
+// PLU_FP64_IND_G32=1: the float64 indicator's correction applied to the
+// float32 G (no float64 pass), for measuring what each part contributes
+bool fp64_ind_on_g32() {
+  static const bool on = [] {
+    const char* e = std::getenv("PLU_FP64_IND_G32");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
 bool valid_prec(int prec) {
   const int fmt = prec & PLU_PREC_FORMAT_MASK;
   if ((prec & PLU_PREC_REFINE_LAST) && (prec & PLU_PREC_REFINE_TWO)) return false;
   return fmt >= PLU_PREC_FP32 && fmt <= PLU_PREC_FP8_E4M3 &&
          (prec & ~(PLU_PREC_FORMAT_MASK | PLU_PREC_REFINE_LAST | PLU_PREC_REFINE_TWO |
-                   PLU_PREC_A_UNCHANGED)) == 0;
+                   PLU_PREC_A_UNCHANGED | PLU_PREC_FP64_INDICATOR)) == 0;
 }
 inline int64_t ru(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -132,6 +142,9 @@ struct Ws {
   size_t msg_words;
   double *gram_part, *gram, *rinv64, *sumsq_part, *colsq_part, *vsq_part, *colnorm, *scal;
   int32_t* iscal;
+  // float64 indicator: G = A V in float64 (m x lp), V^T V - I (lp x lp), and
+  // the per-row-block column terms of the corrected energies
+  double *g64 = nullptr, *w64 = nullptr, *ind_part = nullptr;
   int64_t sumsq_cap, colsq_cap;
   // precision form: bfloat16 copies of A (row-major and transposed) and of the
   // sketch (transposed), padded to multiples of 64 along the contraction index
@@ -205,6 +218,7 @@ int64_t lowp_part_need(int64_t m, int64_t n, int64_t l, int prec) {
 
 Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
           bool basis_store = false) {
+  const bool ind64 = (prec & PLU_PREC_FP64_INDICATOR) != 0;
   prec &= PLU_PREC_FORMAT_MASK;
   Ws w{};
   const int64_t Mx = std::max(m, n);
@@ -281,6 +295,11 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
   if (basis_store) {
     w.vall = L.take<float>(n * lp);
     w.gall = L.take<float>(m * lp);
+  }
+  if (ind64) {
+    w.g64 = L.take<double>(m * lp);
+    w.w64 = L.take<double>(lp * lp);
+    w.ind_part = L.take<double>((size_t)f64_row_blocks(l) * lp);
   }
   return w;
 }
@@ -428,15 +447,28 @@ QrWork qr_work(const Ws& w, float* q, int64_t ldq) {
 // every later pass of that shape (single calls and batches alike) runs the
 // same plan and gives the same bits.  The row-block size leaves every output
 // element's summation order unchanged; the split does not.
+// The tuner's choices are kept per size class: the kept and reduced
+// dimensions in quarter-octave buckets, the sketch width exactly (it sets the
+// kernel's column tiles), so that a stream of requests of ever new shapes
+// tunes once per class, not once per shape.
 struct TuneKey {
-  int device, trans;
-  int64_t P, R, C, ldo;
+  int device, trans, pb, rb, only_bp;
+  int64_t C;
   bool operator<(const TuneKey& o) const {
-    return std::tie(device, trans, P, R, C, ldo) < std::tie(o.device, o.trans, o.P, o.R, o.C, o.ldo);
+    return std::tie(device, trans, pb, rb, only_bp, C) <
+           std::tie(o.device, o.trans, o.pb, o.rb, o.only_bp, o.C);
   }
 };
+int size_bucket(int64_t x) {
+  return (int)std::floor(4.0 * std::log2((double)std::max<int64_t>(x, 1)));
+}
+// a tuned choice: row-block size and the concurrent-workgroup count the split
+// is planned for (plan_gemm turns them into the plan of any shape of the class)
+struct TunedChoice {
+  int bp, slots;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, GemmPlan> g_tuned;
+std::map<TuneKey, TunedChoice> g_tuned;
 
 // row stride of the split partials of a pass whose output has row stride ldo
 int64_t part_ld(int64_t ldo) { return (ldo + 3) & ~int64_t(3); }
@@ -462,20 +494,25 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
     return (p.nsplit == 1 || (int64_t)p.nsplit * P * part_ld(ldo) <= w.part_cap) &&
            (int64_t)p.pblocks * p.nsplit <= w.sumsq_cap;
   };
-  const TuneKey key{h->device, trans, P, R, C, ldo};
+  // PLU_AUTOTUNE_ROWS=64 or 128 holds the tuner to one row-block size
+  int only_bp = 0;
+  if (const char* rows = std::getenv("PLU_AUTOTUNE_ROWS")) only_bp = std::atoi(rows);
+  const TuneKey key{h->device, trans, size_bucket(P), size_bucket(R), only_bp, C};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
-    if (it != g_tuned.end() && fits(it->second)) return it->second;
+    if (it != g_tuned.end()) {
+      const GemmPlan p = plan_gemm(P, R, C, kMaxSplit, it->second.slots, kLineAlign, it->second.bp);
+      if (fits(p)) return p;
+      return fits(def) ? def : plan_gemm(P, R, C, 1, 1);
+    }
   }
   // small passes, recorded (batched) launches and launches under graph
   // capture use the default plan
   if (!tune_enabled() || thread_recorder() || w.capturing || w.no_tune || 2.0 * P * R * C < 2e10)
     return fits(def) ? def : plan_gemm(P, R, C, 1, 1);
-  // PLU_AUTOTUNE_ROWS=64 or 128 holds the tuner to one row-block size
-  int only_bp = 0;
-  if (const char* rows = std::getenv("PLU_AUTOTUNE_ROWS")) only_bp = std::atoi(rows);
   std::vector<GemmPlan> cands;
+  std::vector<int> cand_slots;
   for (int bp : {GEMM_BP, 64}) {
     if (only_bp == 64 || only_bp == GEMM_BP) {
       if (bp != only_bp) continue;
@@ -487,6 +524,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
       for (auto& c : cands) dup |= c.nsplit == p.nsplit && c.bp == p.bp;
       if (dup) continue;
       cands.push_back(p);
+      cand_slots.push_back(slots);
     }
   }
   if (cands.empty()) return plan_gemm(P, R, C, 1, 1);
@@ -516,6 +554,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   // fewest splits: fewer split partials written and read back (each split
   // adds 8 P l bytes of traffic to the pass)
   GemmPlan best = cands[0];
+  int best_slots = cand_slots[0];
   float best_ms = 1e30f;
   for (size_t c = 0; c < cands.size(); ++c)
     if (cand_ok[c]) best_ms = std::min(best_ms, cand_ms[c]);
@@ -527,6 +566,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
       kept_split = cands[c].nsplit;
       kept_ms = cand_ms[c];
       best = cands[c];
+      best_slots = cand_slots[c];
     }
   }
   (void)hipEventDestroy(e0);
@@ -539,7 +579,7 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
                    cands[c].nsplit == best.nsplit) ? "  <- kept" : "");
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned[key] = best;
+  g_tuned[key] = TunedChoice{best.bp, best_slots};
   return best;
 }
 
@@ -2099,7 +2139,7 @@ int plu_range_basis(plu_handle h, int32_t layout, int64_t m, int64_t n, const fl
   if (lda < (layout == PLU_COL_MAJOR ? m : n)) return -6;
   if (l <= 0 || l >= std::min(m, n)) return -7;
   if (v < 2) return -8;
-  if (!valid_prec(prec)) return -9;
+  if (!valid_prec(prec) || (prec & PLU_PREC_FP64_INDICATOR)) return -9;
   if (!V) return -12;
   if (ldv < l) return -13;
   PLU_TRY_HIP(hipSetDevice(h->device));
@@ -2132,7 +2172,7 @@ static int fixed_rank_impl(plu_handle h, int32_t layout, int64_t m, int64_t n, c
   const int64_t l = (int64_t)k + p_over;
   if (l >= std::min(m, n)) return -(8 - off);
   if (v < 2) return -(9 - off);
-  if (!valid_prec(prec)) return -(10 - off);
+  if (!valid_prec(prec) || (prec & PLU_PREC_FP64_INDICATOR)) return -(10 - off);
   if (sp && prec != PLU_PREC_FP32) return -(10 - off);   // sparse passes are float32
   if (!p) return -(13 - off);
   if (!q) return -(14 - off);
@@ -2202,6 +2242,8 @@ static int fixed_precision_impl(plu_handle h, int32_t layout, int64_t m, int64_t
   if (max_rounds < 1 || (int64_t)l * max_rounds >= mn) return -(12 - off);
   if (!valid_prec(prec)) return -(13 - off);
   if (sp && prec != PLU_PREC_FP32) return -(13 - off);   // sparse passes are float32
+  // the float64 indicator: one round on a dense A
+  if ((prec & PLU_PREC_FP64_INDICATOR) && max_rounds > 1) return PLU_ERR_NOT_IMPLEMENTED;
   if (!p) return -(16 - off);
   if (!q) return -(17 - off);
   if (!L) return -(18 - off);
@@ -2234,12 +2276,27 @@ static int fixed_precision_impl(plu_handle h, int32_t layout, int64_t m, int64_t
   PLU_TRY_HIP(run_pass(h, w, 0, m, n, A, lda, V, w.lp, l, w.ym, w.lp, nullptr, w.colsq_part,
                        &nblk));
   ++np;
-  // float64 squared norms of the basis columns (first-order normalization)
-  PLU_TRY_HIP(launch_splitk_reduce(V, 0, 1, nullptr, w.lp, n, l, w.vsq_part, 64, h->stream));
-  const int nvblk = (int)((n + 63) / 64);
-  PLU_TRY_HIP(launch_rank_rule(w.colsq_part, nblk, l, w.vsq_part, nvblk, w.scal + 0, eps, b,
-                               column_exact ? 1 : 0, w.iscal + 0, w.scal + 1, w.iscal + 1,
-                               w.colnorm, h->stream));
+  if (prec & PLU_PREC_FP64_INDICATOR) {
+    // the indicator from G = A V in float64, corrected to first order for
+    // V^T V - I (one more pass over A, not counted among the v of Alg. 7)
+    const bool g32 = fp64_ind_on_g32();
+    if (!g32)
+      PLU_TRY_HIP(launch_f64_gemm(w.acol ? 1 : 0, A, lda, V, w.lp, m, n, l, w.g64, w.lp,
+                                  h->stream));
+    PLU_TRY_HIP(launch_f64_gram_w(V, w.lp, n, l, w.w64, w.lp, h->stream));
+    PLU_TRY_HIP(launch_f64_corr(g32 ? nullptr : w.g64, w.ym, w.lp, m, l, w.w64, w.lp,
+                                w.ind_part, h->stream));
+    PLU_TRY_HIP(launch_rank_rule(w.ind_part, f64_row_blocks(l), l, nullptr, 0, w.scal + 0, eps, b,
+                                 column_exact ? 1 : 0, w.iscal + 0, w.scal + 1, w.iscal + 1,
+                                 w.colnorm, h->stream));
+  } else {
+    // float64 squared norms of the basis columns (first-order normalization)
+    PLU_TRY_HIP(launch_splitk_reduce(V, 0, 1, nullptr, w.lp, n, l, w.vsq_part, 64, h->stream));
+    const int nvblk = (int)((n + 63) / 64);
+    PLU_TRY_HIP(launch_rank_rule(w.colsq_part, nblk, l, w.vsq_part, nvblk, w.scal + 0, eps, b,
+                                 column_exact ? 1 : 0, w.iscal + 0, w.scal + 1, w.iscal + 1,
+                                 w.colnorm, h->stream));
+  }
   // Alg. 9 steps 2-6 at the rank the rule left on the device (0 for a zero
   // or non-finite A: the LUs then take no step and p, q are the identity)
   PLU_TRY_HIP(assemble(h, w, m, n, l, V, p, q, L, ldl, U, ldu, nullptr, w.iscal));
@@ -2801,7 +2858,7 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       bad = true;
       continue;
     }
-    if ((r.prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32) {
+    if ((r.prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32 || (r.prec & PLU_PREC_FP64_INDICATOR)) {
       r.status = PLU_ERR_NOT_IMPLEMENTED;
       bad = true;
       continue;
@@ -3019,7 +3076,8 @@ int plu_server_submit(plu_server S, const plu_request* req, uint64_t* ticket) {
   int64_t l = 0;
   const int c = check_request(*req, &l);
   if (c) return c;
-  if ((req->prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32) return PLU_ERR_NOT_IMPLEMENTED;
+  if ((req->prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32 || (req->prec & PLU_PREC_FP64_INDICATOR))
+    return PLU_ERR_NOT_IMPLEMENTED;
   auto j = std::make_unique<ServerJob>();
   j->host = *req;
   j->cap = req->mode == 0 ? req->k : l;

@@ -174,6 +174,21 @@ hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ld
 hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,
                                    int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s,
                                    const int32_t* kcap = nullptr);
+// Float64 indicator (k_f64.hip).  out (P x C, float64) = op(A) B with
+// op(A)(p, r) = A[p * lda + r] (mode 0) or A[r * lda + p] (mode 1).
+hipError_t launch_f64_gemm(int mode, const float* A, int64_t lda, const float* B, int64_t ldb,
+                           int64_t P, int64_t R, int64_t C, double* out, int64_t ldo,
+                           hipStream_t s);
+// W = X^T X - I (X: R x l float32), tiles on and above the diagonal.
+hipError_t launch_f64_gram_w(const float* X, int64_t ldx, int64_t R, int64_t l, double* W,
+                             int64_t ldw, hipStream_t s);
+// part[blk * l + j] (blk < f64_row_blocks(l)): the row block's share of
+// M_jj (1 - W_jj) - 2 sum_{i<j} W_ij M_ij, M = Y^T Y (Y float64, or Y32
+// float32 when Y is null).
+hipError_t launch_f64_corr(const double* Y, const float* Y32, int64_t ldy, int64_t R, int64_t l,
+                           const double* W, int64_t ldw, double* part, hipStream_t s);
+int f64_row_blocks(int64_t l);
+
 hipError_t launch_rank_rule(const double* colsq_part, int nblk, int l, const double* vsq_part,
                             int nvblk, const double* normA2, double eps, int b, int col_mode,
                             int32_t* kout, double* Eout, int32_t* tol, double* colnorm,
