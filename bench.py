@@ -749,6 +749,33 @@ def profile_pass(m, n):
                       "copy_bytes_each_direction": 4 * 2 ** 28}))
 
 
+def profile_lu(M=20000, c=110, reps=10):
+    """The LU panel kernel alone: GETRF with partial pivoting of a seeded
+    Gaussian M x c matrix (Alg. 6/7's lu(.) at the bench shape), one warm
+    call, then reps calls, then 3 copies of 1 GiB (the byte counters'
+    calibration kernel)."""
+    import torch
+    import paper_2002_07138_amd as plu
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(M + c)
+    X0 = torch.randn(M, c, device=dev, generator=g)
+    X = X0.clone()
+    h = plu.Handle(0)
+    h.getrf(X, sync_info=False)
+    for _ in range(reps):
+        X.copy_(X0)
+        h.getrf(X, want_perm=True, want_u=True, sync_info=False)
+    src = torch.empty(2 ** 28, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    h.close()
+    print(json.dumps({"profile_lu": True, "M": M, "c": c, "reps": reps,
+                      "algorithmic_bytes": 8.0 * M * c, "copy_bytes_each_direction": 4 * 2 ** 28}))
+
+
 def profile_single_pass(m, n, k=100):
     """HBM bytes of the single-pass LU: after a 1 GiB fill (the start mark),
     one call on a column-major A (one pass), a 1 GiB copy (calibration, and
@@ -796,6 +823,9 @@ def main():
     ap.add_argument("--profile-single-pass", action="store_true",
                     help="run only the single-pass LU on a column-major and a row-major A "
                          "around a plain 1 GiB copy, for hardware-counter runs")
+    ap.add_argument("--profile-lu", action="store_true",
+                    help="run only the LU of a 20000 x 110 Gaussian matrix (10 calls) and a plain "
+                         "1 GiB copy, for kernel-trace and hardware-counter runs")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run only the pass kernels at the workload shape (3 launches per "
                          "direction) and a plain 1 GiB copy, for hardware-counter runs")
@@ -817,6 +847,9 @@ def main():
         return
     if args.profile_single_pass:
         profile_single_pass(m, n)
+        return
+    if args.profile_lu:
+        profile_lu()
         return
     if args.serving_only:
         pool = serving_pool(args.pool)

@@ -19,6 +19,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <array>
 #include <vector>
 
 #include "../../include/powerlu.h"
@@ -619,6 +620,23 @@ void pretune_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, co
   g0.A = A; g0.lda = lda; g0.X = X; g0.ldx = ldx;
   g0.P = trans ? n : m; g0.R = trans ? m : n; g0.C = l;
   (void)pass_plan(h, w, trans, g0, out, ldo);
+}
+
+// Whether pretune_pass with these arguments would still time candidates (a
+// large pass whose size class has no tuned choice yet).
+bool pass_needs_tuning(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, int64_t l) {
+  if (w.sp || !tune_enabled()) return false;
+  if (w.acol) {
+    trans ^= 1;
+    std::swap(m, n);
+  }
+  const int64_t P = trans ? n : m, R = trans ? m : n;
+  if (2.0 * P * R * l < 2e10) return false;
+  int only_bp = 0;
+  if (const char* rows = std::getenv("PLU_AUTOTUNE_ROWS")) only_bp = std::atoi(rows);
+  const TuneKey key{h->device, trans, size_bucket(P), size_bucket(R), only_bp, l};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tuned.find(key) == g_tuned.end();
 }
 
 hipError_t run_pass(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n, const float* A,
@@ -1342,6 +1360,8 @@ struct ServerJob {
   hipEvent_t up = nullptr;     // recorded after the copy of A on the upload stream
   bool uploaded = false;       // that copy has landed: its steps may be issued
   double t_up = 0, t_issued = 0, t_computed = 0;   // server-side timestamps
+  int lane = 0;                // the stream its launches go to
+  double work = 0;             // m n l v: its share of that lane's load
   plu_result res{};
 };
 
@@ -1433,19 +1453,34 @@ void server_loop(plu_server S) {
   (void)hipSetDevice(S->device);
   plu_handle h = S->h;
   constexpr size_t kGroupsPerIter = 32;
-  // issued launch batches (sequence number, event recorded after it), oldest
-  // first; batches complete in order on the one compute stream
-  std::deque<std::pair<uint64_t, hipEvent_t>> inflight;
-  uint64_t seq = 0, completed = 0;
-  // retires completed batches; with block, waits for the oldest first.  An
-  // event goes back to the pool only here, once nothing refers to it.
-  auto retire = [&](bool block) {
+  // Admitted problems are spread over lanes, one stream each (the handle's
+  // side streams), least loaded first: one lane's LU panels and thin QRs
+  // overlap the passes of the others.  Within a lane the problems' launch
+  // sequences are merged continuously.  A lane's merged LU panels are held
+  // to cu_count / lanes workgroups, so all panels in flight fit at once.
+  constexpr int kLanes = plu_handle_s::kSide;
+  if (ensure_side_streams(h) != hipSuccess) {
+    std::fprintf(stderr, "libpowerlu server: could not create its streams\n");
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->fatal = PLU_ERR_HIP;
+  }
+  auto lane_stream = [&](int ln) { return h->side[ln] ? h->side[ln] : S->stream; };
+  // per lane: issued launch batches (sequence number, event recorded after
+  // it), oldest first; a lane's batches complete in order on its stream
+  std::array<std::deque<std::pair<uint64_t, hipEvent_t>>, kLanes> inflight;
+  std::array<uint64_t, kLanes> seq{}, completed{};
+  std::array<double, kLanes> load{};
+  // retires a lane's completed batches; with block, waits for its oldest
+  // first.  An event goes back to the pool only here, once nothing refers to it.
+  auto retire = [&](int ln, bool block) {
     bool first = true;
-    while (!inflight.empty()) {
-      hipEvent_t e = inflight.front().second;
+    bool any = false;
+    while (!inflight[ln].empty()) {
+      hipEvent_t e = inflight[ln].front().second;
       if (!e) {   // no event could be recorded (reported as fatal)
-        completed = inflight.front().first;
-        inflight.pop_front();
+        completed[ln] = inflight[ln].front().first;
+        inflight[ln].pop_front();
+        any = true;
         continue;
       }
       if (block && first) {
@@ -1456,11 +1491,18 @@ void server_loop(plu_server S) {
         break;
       }
       first = false;
-      completed = inflight.front().first;
-      inflight.pop_front();
+      any = true;
+      completed[ln] = inflight[ln].front().first;
+      inflight[ln].pop_front();
       std::lock_guard<std::mutex> lk(S->mu);
       S->events.push_back(e);
     }
+    return any;
+  };
+  auto inflight_any = [&] {
+    for (auto& q : inflight)
+      if (!q.empty()) return true;
+    return false;
   };
   auto ready = [](const ServerJob* j) { return j->uploaded && !j->waiting; };
   for (;;) {
@@ -1489,7 +1531,7 @@ void server_loop(plu_server S) {
       bool runnable = false;
       for (auto& up : S->active)
         if (ready(up.get())) runnable = true;
-      if (!runnable && inflight.empty() && !upwait) {
+      if (!runnable && !inflight_any() && !upwait) {
         const auto tw = std::chrono::steady_clock::now();
         S->cv_work.wait(lk, [&] {
           bool r = false;
@@ -1502,7 +1544,7 @@ void server_loop(plu_server S) {
         S->t_idle += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
       }
       if (S->stop && S->pending.empty() && S->active.empty() && S->nfinishing == 0 &&
-          inflight.empty())
+          !inflight_any())
         return;
       // a slot is held from admission until the result is copied out
       while (!S->pending.empty() && (int)S->active.size() + S->nfinishing < S->max_slots) {
@@ -1595,6 +1637,9 @@ void server_loop(plu_server S) {
       int64_t l = 0;
       (void)check_request(d, &l);
       bp.l = l;
+      j->work = (double)d.m * (double)d.n * (double)l * (double)d.v;
+      j->lane = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[(size_t)j->lane] += j->work;
       {
         // splits of large passes tuned eagerly (on this problem's workspace,
         // once A has landed), so the recorded launches equal the single calls
@@ -1602,8 +1647,10 @@ void server_loop(plu_server S) {
         L.base = ws;
         Ws w = layout(L, d.m, d.n, l);
         w.acol = d.layout == PLU_COL_MAJOR;
-        const int64_t P0 = w.acol ? d.n : d.m, R0 = w.acol ? d.m : d.n;
-        if (2.0 * P0 * R0 * l >= 2e10 && tune_enabled()) {
+        // (only a size class not tuned yet waits for the copy of A)
+        if (pass_needs_tuning(&bp.hs, w, 0, d.m, d.n, l) ||
+            pass_needs_tuning(&bp.hs, w, 1, d.m, d.n, l) ||
+            (d.mode == 0 && pass_needs_tuning(&bp.hs, w, 0, d.m, d.n, d.k))) {
           if (j->up) (void)hipEventSynchronize(j->up);
           pretune_pass(&bp.hs, w, 0, d.m, d.n, d.A, d.lda, w.om, w.lp, l, w.ym, w.lp);
           pretune_pass(&bp.hs, w, 1, d.m, d.n, d.A, d.lda, w.om, w.lp, l, w.zn, w.lp);
@@ -1620,22 +1667,27 @@ void server_loop(plu_server S) {
       if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
     }
     S->t_record += std::chrono::duration<double>(std::chrono::steady_clock::now() - trec).count();
-    // issue one batch of merged groups over the problems with steps left
-    std::vector<const Recorder*> lists;
-    std::vector<size_t> heads;
-    std::vector<ServerJob*> js;
-    for (auto& up : S->active)
-      if (ready(up.get())) {
-        lists.push_back(&up->bp.rec);
-        heads.push_back(up->head);
-        js.push_back(up.get());
-      }
-    if (!js.empty()) {
-      // bound the queue: wait for the batch before last
-      while (inflight.size() >= 2) retire(true);
+    // per lane: issue one batch of merged groups over its problems with
+    // steps left
+    bool issued = false;
+    for (int ln = 0; ln < kLanes; ++ln) {
+      std::vector<const Recorder*> lists;
+      std::vector<size_t> heads;
+      std::vector<ServerJob*> js;
+      for (auto& up : S->active)
+        if (up->lane == ln && ready(up.get())) {
+          lists.push_back(&up->bp.rec);
+          heads.push_back(up->head);
+          js.push_back(up.get());
+        }
+      if (js.empty()) continue;
+      issued = true;
+      const hipStream_t ls = lane_stream(ln);
+      // bound the lane's queue: wait for its batch before last
+      while (inflight[ln].size() >= 2) retire(ln, true);
       const auto ti = std::chrono::steady_clock::now();
-      hipError_t e = run_merged_steps(lists, heads, S->stream, h->cu_count, kGroupsPerIter,
-                                      h->mbuf, &S->stats);
+      hipError_t e = run_merged_steps(lists, heads, ls, h->cu_count / kLanes, kGroupsPerIter,
+                                      h->sbuf[ln], &S->stats);
       // problems with all steps issued: queue the copies of their small
       // results behind them, so that the event below covers those too
       for (size_t i = 0; i < js.size() && e == hipSuccess; ++i) {
@@ -1643,7 +1695,7 @@ void server_loop(plu_server S) {
         if (heads[i] < j->bp.rec.ops.size() || !S->stage[j->slot]) continue;
         // the gaps of both final LUs: k steps, or up to l for a rank on the device
         const int nst = j->dev.mode == 0 ? j->dev.k : (int)j->bp.l;
-        e = stage_info(j->bp.w, nst, S->stage[j->slot], S->stream);
+        e = stage_info(j->bp.w, nst, S->stage[j->slot], ls);
       }
       S->t_issue += std::chrono::duration<double>(std::chrono::steady_clock::now() - ti).count();
       ++S->batches;
@@ -1654,37 +1706,49 @@ void server_loop(plu_server S) {
         S->sum_pending += S->pending.size();
       }
       hipEvent_t ev = take_event(S);
-      if (e == hipSuccess && ev) e = hipEventRecord(ev, S->stream);
+      if (e == hipSuccess && ev) e = hipEventRecord(ev, ls);
       if (e != hipSuccess || !ev) {
         std::fprintf(stderr, "libpowerlu server: %s\n", hipGetErrorString(e));
         std::lock_guard<std::mutex> lk(S->mu);
         S->fatal = PLU_ERR_HIP;
       }
-      inflight.push_back({++seq, ev});
+      inflight[ln].push_back({++seq[ln], ev});
       for (size_t i = 0; i < js.size(); ++i) {
         js[i]->head = heads[i];
         if (js[i]->head >= js[i]->bp.rec.ops.size()) {
           js[i]->waiting = true;
-          js[i]->done_seq = seq;
+          js[i]->done_seq = seq[ln];
           js[i]->t_issued = now_s(S->t0);
         }
       }
-    } else if (!inflight.empty()) {
-      retire(true);
-    } else if (upwait) {
-      // nothing to issue until a copy of A lands
-      const auto tw = std::chrono::steady_clock::now();
-      (void)hipEventSynchronize(upwait);
-      S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
+    }
+    if (!issued) {
+      if (inflight_any()) {
+        // nothing to issue: wait until some lane's oldest batch completes
+        const auto tw = std::chrono::steady_clock::now();
+        for (;;) {
+          bool any = false;
+          for (int ln = 0; ln < kLanes; ++ln) any |= retire(ln, false);
+          if (any || !inflight_any()) break;
+          std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
+      } else if (upwait) {
+        // nothing to issue until a copy of A lands
+        const auto tw = std::chrono::steady_clock::now();
+        (void)hipEventSynchronize(upwait);
+        S->t_devwait += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw).count();
+      }
     }
     // problems whose steps are all complete
-    retire(false);
+    for (int ln = 0; ln < kLanes; ++ln) retire(ln, false);
     std::vector<ServerJob*> to_finish;
     for (auto& up : S->active) {
       ServerJob* j = up.get();
       if (!j->waiting) continue;
-      if (!S->fatal && completed < j->done_seq) continue;
+      if (!S->fatal && completed[(size_t)j->lane] < j->done_seq) continue;
       to_finish.push_back(j);
+      load[(size_t)j->lane] -= j->work;
     }
     if (!to_finish.empty()) {
       std::lock_guard<std::mutex> lk(S->mu);

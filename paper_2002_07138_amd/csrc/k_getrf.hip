@@ -1353,8 +1353,13 @@ struct TrsmArgs {
 };
 
 // U12 = L11^{-1} F[pivot rows of the panel, right columns]; written back into
-// the pivot rows and into a compact nbw x (c - jb - nbw) buffer.  The block's
-// 64 right-hand columns are staged in LDS first, then solved in place.
+// the pivot rows and into a compact nbw x (c - jb - nbw) buffer.  One wave per
+// right-hand column, lane r holding row r: at step s row s is final, its value
+// is broadcast from lane s (readlane, no LDS round trip) and every lane
+// subtracts its multiple, the next step's multiplier already loaded.  The
+// strictly lower L11 is staged in LDS (zeros on and above the diagonal, so
+// rows at or above s are left exactly as they are).  Each entry sees the same
+// fmaf sequence as a left-looking substitution (its terms in ascending s).
 __device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
   if (a.run_if && *a.run_if == 0) return;
   int c = a.c;
@@ -1364,33 +1369,40 @@ __device__ void b_trsm(const TrsmArgs& a, const Grid& gr) {
     if (kc < c) c = kc;
   }
   __shared__ float L11[64][65];
-  __shared__ float us[64][65];
   __shared__ int rows[64];
-  const int t = threadIdx.x;
-  if (t < a.nbw) rows[t] = a.piv_row[a.jb + t];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int nbw = a.nbw;
+  if (t < 64) rows[t] = t < nbw ? a.piv_row[a.jb + t] : 0;
   __syncthreads();
-  const int cs = a.jb + a.nbw;
-  const int64_t cbase = (int64_t)cs + (int64_t)gr.bx * 64;
-  // stage L11 and the block's 64 right-hand columns with all 256 threads
-  for (int e = t; e < a.nbw * 64; e += 256) {
-    const int s = e >> 6, col = e & 63;
-    const float* row = a.F + (int64_t)rows[s] * a.ldf;
-    L11[s][col] = (col < s) ? row[a.jb + col] : 0.f;
-    us[s][col] = (cbase + col < c) ? row[cbase + col] : 0.f;
+  {
+    // every load issued before the first is waited for
+    float lv[16];
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int e = it * 256 + t, r = e >> 6, s = e & 63;
+      lv[it] = (r < nbw && s < r) ? a.F[(int64_t)rows[r] * a.ldf + a.jb + s] : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int e = it * 256 + t;
+      L11[e >> 6][e & 63] = lv[it];
+    }
   }
   __syncthreads();
-  if (t >= 64) return;
-  const int64_t cc = cbase + t;
-  if (cc >= c) return;
-  for (int s = 0; s < a.nbw; ++s) {
-    float v = us[s][t];
-    for (int k = 0; k < s; ++k) v = fmaf(-L11[s][k], us[k][t], v);
-    us[s][t] = v;
+  const int cs = a.jb + nbw;
+  const int64_t cc = (int64_t)cs + (int64_t)gr.bx * 4 + wave;
+  if (cc >= c) return;   // uniform over the wave; no barrier follows
+  float x = (lane < nbw) ? a.F[(int64_t)rows[lane] * a.ldf + cc] : 0.f;
+  float lnext = L11[lane][0];
+  for (int s = 0; s < nbw - 1; ++s) {
+    const float lcur = lnext;
+    lnext = L11[lane][s + 1];
+    const float xs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), s));
+    x = fmaf(-lcur, xs, x);
   }
-  for (int s = 0; s < a.nbw; ++s) {
-    const float v = us[s][t];
-    a.F[(int64_t)rows[s] * a.ldf + cc] = v;
-    a.u12[(int64_t)s * a.ldu12 + (cc - cs)] = v;
+  if (lane < nbw) {
+    a.F[(int64_t)rows[lane] * a.ldf + cc] = x;
+    a.u12[(int64_t)lane * a.ldu12 + (cc - cs)] = x;
   }
 }
 
@@ -1524,7 +1536,7 @@ hipError_t getrf_run(float* F, int64_t ldf, int64_t M, int c, const GetrfWork& w
     const int cs = jb + pa.nbw;
     if (cs < c) {
       TrsmArgs ta{F, ldf, jb, pa.nbw, c, w.piv_row, w.u12, w.ldu12, w.run_if, w.kcap};
-      if ((e = dispatch<TrsmArgs, b_trsm, 256>(ta, dim3((unsigned)((c - cs + 63) / 64)), 0, s)) !=
+      if ((e = dispatch<TrsmArgs, b_trsm, 256>(ta, dim3((unsigned)((c - cs + 3) / 4)), 0, s)) !=
           hipSuccess)
         return e;
       GemmArgs g;
