@@ -90,15 +90,25 @@ def _stats(ts):
             "p90": round(float(np.percentile(a, 90)), 4), "n": int(a.size)}
 
 
+def _sketch(rows, l, dev, gen=None, fill=True):
+    """rows x l float32 with rows padded to a multiple of 4 floats (the
+    layout of the library's own iterates and pass outputs)."""
+    import torch
+    lp = (l + 3) // 4 * 4
+    t = (torch.randn((rows, lp), device=dev, generator=gen) if fill
+         else torch.empty((rows, lp), device=dev))
+    return t[:, :l]
+
+
 def _pass_times(h, A, l, reps=10, prec=0):
     """Median time of one pass A X (N) and A^T X (T) with sketch width l."""
     import numpy as np
     import torch
     m, n = A.shape
-    X_n = torch.randn((n, l), device=A.device)
-    X_m = torch.randn((m, l), device=A.device)
-    o_m = torch.empty((m, l), device=A.device)
-    o_n = torch.empty((n, l), device=A.device)
+    X_n = _sketch(n, l, A.device)
+    X_m = _sketch(m, l, A.device)
+    o_m = _sketch(m, l, A.device, fill=False)
+    o_n = _sketch(n, l, A.device, fill=False)
     out = {}
     for name, X, o, tr in (("N", X_n, o_m, False), ("T", X_m, o_n, True)):
         h.pass_(A, X, trans=tr, out=o, prec=prec)                  # tuning / rounded copies
@@ -725,10 +735,10 @@ def profile_pass(m, n):
     g.manual_seed(2)
     A = torch.randn((m, n), device=dev, generator=g)
     l = K_RANK + P_OVER
-    X_n = torch.randn((n, l), device=dev, generator=g)
-    X_m = torch.randn((m, l), device=dev, generator=g)
-    out_m = torch.empty((m, l), device=dev)
-    out_n = torch.empty((n, l), device=dev)
+    X_n = _sketch(n, l, dev, g)
+    X_m = _sketch(m, l, dev, g)
+    out_m = _sketch(m, l, dev, fill=False)
+    out_n = _sketch(n, l, dev, fill=False)
     h = plu.Handle(0)
     # the first pass of each direction picks its split plan (timed candidates);
     # the counted launches are the three of each direction after it
@@ -950,10 +960,12 @@ def main():
 
     # dominant kernel: one pass over A (both directions), timed live with HIP
     # events on the stream the library launches on
-    X_n = torch.randn((n, l), device=dev, dtype=torch.float32)
-    X_m = torch.randn((m, l), device=dev, dtype=torch.float32)
-    out_m = torch.empty((m, l), device=dev)
-    out_n = torch.empty((n, l), device=dev)
+    # the sketch and the output laid out as the factorizations' own passes
+    # have them (rows padded to whole float4s)
+    X_n = _sketch(n, l, dev)
+    X_m = _sketch(m, l, dev)
+    out_m = _sketch(m, l, dev, fill=False)
+    out_n = _sketch(n, l, dev, fill=False)
     reps = 20
     for _ in range(3):
         h.pass_(A, X_n, trans=False, out=out_m)

@@ -531,14 +531,19 @@ GemmPlan pass_plan(plu_handle h, const Ws& w, int trans, const GemmArgs& g, floa
   if (cands.empty()) return plan_gemm(P, R, C, 1, 1);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return cands[0];
-  // every candidate once to warm up (clocks, caches, code), then three rounds
-  // over all candidates in turn, keeping each one's fastest round, so that a
-  // clock still rising during the first launches favours none of them
+  // five rounds over all candidates in turn, keeping each one's fastest
+  // round, so that a clock still rising during the first launches favours
+  // none of them
   std::vector<float> cand_ms(cands.size(), 1e30f);
   std::vector<char> cand_ok(cands.size(), 1);
+  // a few launches first to bring the clocks up (the first timed round
+  // would otherwise favour the candidates timed last), then every candidate
+  // once to warm up its code and caches
+  for (int r = 0; r < 4; ++r)
+    (void)pass_launch(h, w, trans, g, cands[0], out, ldo, nullptr, h->stream);
   for (size_t c = 0; c < cands.size(); ++c)
     cand_ok[c] = pass_launch(h, w, trans, g, cands[c], out, ldo, nullptr, h->stream) == hipSuccess;
-  for (int round = 0; round < 3; ++round) {
+  for (int round = 0; round < 5; ++round) {
     for (size_t c = 0; c < cands.size(); ++c) {
       if (!cand_ok[c]) continue;
       float ms = 0.f;
