@@ -120,3 +120,34 @@ def test_server_one_slot_serializes():
         _check_same(res, f)
     for a, b in zip(results, results[1:]):
         assert b["t_admit"] >= a["t_done"]
+
+
+def test_server_strided_host_blocks():
+    """Requests that are blocks of a larger host matrix (row stride above the
+    block width): a stride up to 3x the width goes up as one contiguous span
+    kept with its stride on the device, a wider one as a 2-D copy; either way
+    each result equals the single call on a packed device copy, bit for bit."""
+    import paper_2002_07138_amd as plu
+    rng = np.random.default_rng(21)
+    big = lowrank_plus_noise(2600, 3000, spectrum("exp", 60, tau=15.0), 31, 32, 1e-5, 33)
+    reqs = []
+    for i, (r0, c0, m, n) in enumerate([(10, 20, 1500, 1400),     # stride 3000 / 1400: span
+                                        (500, 100, 900, 2600),     # span
+                                        (0, 0, 2000, 700),         # 3000 / 700 > 3: 2-D copy
+                                        (300, 2000, 1200, 900)]):  # span
+        blk = big[r0:r0 + m, c0:c0 + n]
+        if i % 2:
+            b = 8
+            l = min(16 * b, b * ((min(m, n) - 1) // b))
+            reqs.append(dict(A=blk, mode=1, eps=1e-3, b=b, l=l, v=4, seed=90 + i))
+        else:
+            reqs.append(dict(A=blk, mode=0, k=20, p_over=10, v=3, seed=90 + i))
+    h = handle()
+    alone = [_alone(h, rq) for rq in reqs]
+    h.close()
+    srv = plu.Server(0, hbm_budget_bytes=2 << 30, max_slots=8)
+    tickets = [_submit(srv, rq) for rq in reqs]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for res, f in zip(results, alone):
+        _check_same(res, f)
