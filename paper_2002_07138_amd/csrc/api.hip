@@ -196,22 +196,56 @@ int64_t part_need(int64_t m, int64_t n, int64_t l) {
   return need;
 }
 
-// Contraction padding of the reduced-precision copies (the depth of one
-// stage of the pass kernel).
-inline int64_t lowp_kalign(int prec) { return prec == PLU_PREC_FP8_E4M3 ? 128 : 64; }
+// Split plan of the bfloat16 pass: workgroups of 256 rows, one per CU (their
+// LDS), splits on multiples of 128 along K, at most max_split.  The pass is
+// bound by the bytes of A, so the split weighs the rounds of cu_count
+// workgroups it needs (idle CUs in the last round) against the bytes its
+// float32 partials add (written and read back: 8 P l per split, against
+// 2 P K for A).
+GemmPlan plan_bf16(int64_t P, int64_t K, int64_t C, int cu_count, int max_split) {
+  GemmPlan pl = plan_gemm(P, K, C, 1, 1, 64);          // column blocks and tiles
+  pl.pblocks = (int)((P + 255) / 256);
+  const int64_t base = (int64_t)pl.pblocks * pl.cblocks;
+  const int64_t hi =
+      std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kMaxSplit, max_split), K / 256));
+  int64_t best_ns = 1;
+  double best_cost = 1e30;
+  for (int64_t ns = 1; ns <= hi; ++ns) {
+    const int64_t tot = base * ns, rounds = (tot + cu_count - 1) / cu_count;
+    const double cost = (double)(rounds * cu_count) / (double)tot +
+                        (ns > 1 ? (double)ns * 8.0 * C / (2.0 * K) : 0.0);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best_ns = ns;
+    }
+  }
+  const int64_t rs = ru((K + best_ns - 1) / best_ns, 128);
+  pl.nsplit = (int)((K + rs - 1) / rs);
+  pl.rsplit = rs;
+  return pl;
+}
 
-// Rows of the transposed sketch a reduced-precision pass over C columns reads.
-int64_t lowp_xt_rows(int64_t P, int64_t K, int64_t C, int prec) {
-  const GemmPlan pl = plan_gemm(P, K, C, kMaxSplit, kLowpWgs, (int)lowp_kalign(prec));
+// Contraction padding of the reduced-precision copies (the depth of one
+// stage of either pass kernel).
+constexpr int64_t kLowpKAlign = 128;
+
+// Rows of the transposed sketch a reduced-precision pass over C columns
+// reads (both pass kernels take plan_gemm's column blocking).
+int64_t lowp_xt_rows(int64_t P, int64_t K, int64_t C) {
+  const GemmPlan pl = plan_gemm(P, K, C, 1, 1, (int)kLowpKAlign);
   return ru((int64_t)pl.cblocks * pl.nt * 16, 64);
 }
 
+// Float32 partials of the split passes of the precision form, on a device of
+// kLowpWgs / 2 CUs (run_pass_bf16 takes a smaller split where it must).
 int64_t lowp_part_need(int64_t m, int64_t n, int64_t l, int prec) {
   int64_t need = 0;
-  const int64_t lp = ru4(l), ka = lowp_kalign(prec);
+  const int64_t lp = ru4(l);
   for (int tr = 0; tr < 2; ++tr) {
-    const int64_t P = tr ? n : m, K = ru(tr ? m : n, ka);
-    const GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, (int)ka);
+    const int64_t P = tr ? n : m, K = ru(tr ? m : n, kLowpKAlign);
+    const GemmPlan pl = prec == PLU_PREC_BF16
+                            ? plan_bf16(P, K, l, kLowpWgs / 2, kMaxSplit)
+                            : plan_gemm(P, K, l, kMaxSplit, kLowpWgs, (int)kLowpKAlign);
     if (pl.nsplit > 1) need = std::max(need, (int64_t)pl.nsplit * P * lp);
   }
   return need;
@@ -228,8 +262,8 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
   // the rounded copies of A first: their place depends on m, n and the
   // format only, so calls of other sketch widths find them where they are
   if (prec == PLU_PREC_BF16) {
-    w.ldab = ru(n, 64);
-    w.ldabt = ru(m, 64);
+    w.ldab = ru(n, 128);
+    w.ldabt = ru(m, 128);
     w.ab = L.take<uint16_t>((size_t)m * w.ldab);
     w.abt = L.take<uint16_t>((size_t)n * w.ldabt);
     w.anorm = L.take<double>(1);
@@ -281,14 +315,14 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
   w.scal = L.take<double>(16);
   w.iscal = L.take<int32_t>(16);
   if (prec == PLU_PREC_BF16) {
-    w.ldxt = ru(Mx, 64);
-    w.xt_rows = std::max(lowp_xt_rows(m, ru(n, 64), l, prec), lowp_xt_rows(n, ru(m, 64), l, prec));
+    w.ldxt = ru(Mx, 128);
+    w.xt_rows = std::max(lowp_xt_rows(m, ru(n, 128), l), lowp_xt_rows(n, ru(m, 128), l));
     w.xt = L.take<uint16_t>((size_t)w.xt_rows * w.ldxt);
-    w.cvt_cap = ((std::max(ru(m, 64), ru(n, 64)) + 63) / 64) * 8;   // either storage order
+    w.cvt_cap = ((std::max(ru(m, 128), ru(n, 128)) + 63) / 64) * 8;   // either storage order
     w.cvt_part = L.take<double>(w.cvt_cap);
   } else if (prec == PLU_PREC_FP8_E4M3) {
     w.ldx8 = ru(Mx, 128);
-    w.x8_rows = std::max(lowp_xt_rows(m, w.lda8, l, prec), lowp_xt_rows(n, w.lda8t, l, prec));
+    w.x8_rows = std::max(lowp_xt_rows(m, w.lda8, l), lowp_xt_rows(n, w.lda8t, l));
     w.x8 = L.take<uint8_t>((size_t)w.x8_rows * w.ldx8);
     w.x8s = L.take<uint8_t>((size_t)w.x8_rows * (w.ldx8 / 32));
     w.sumsq_cap = std::max<int64_t>(w.sumsq_cap, 1);
@@ -713,15 +747,19 @@ hipError_t convert_a_bf16(plu_handle h, const Ws& w, int64_t m, int64_t n, const
 // convert_a_bf16), fp32 accumulation.
 hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n,
                          const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo) {
-  const int64_t P = trans ? n : m, Kl = trans ? m : n, K = ru(Kl, 64);
+  const int64_t P = trans ? n : m, Kl = trans ? m : n;
   const uint16_t* M = trans ? w.abt : w.ab;
   const int64_t ldm = trans ? w.ldabt : w.ldab;
   const int64_t pld = part_ld(ldo);
-  GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, 64);
-  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * pld > w.part_cap)
-    pl = plan_gemm(P, K, l, 1, 1, 64);
+  // the kernel walks K 128 at a time: the copies are padded to that (zeros
+  // past the logical K in A's copies and in the sketch's)
+  const int64_t K = ru(Kl, 128);
+  // the split the partials buffer holds (it is sized for the plan on a
+  // device of kLowpWgs / 2 CUs; on others a smaller split may be taken)
+  const int cap = (int)std::max<int64_t>(1, w.part_cap / std::max<int64_t>(1, P * pld));
+  const GemmPlan pl = plan_bf16(P, K, l, h->cu_count, cap);
   const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
-  if (ct > w.xt_rows || K > w.ldxt) return hipErrorInvalidValue;
+  if (ct > w.xt_rows || K > w.ldxt || K > ldm) return hipErrorInvalidValue;
   hipError_t e;
   if ((e = launch_cvt_bf16(X, ldx, Kl, l, nullptr, 0, w.xt, K, ct, nullptr, nullptr,
                            h->stream)) != hipSuccess)

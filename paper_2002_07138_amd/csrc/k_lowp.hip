@@ -114,29 +114,99 @@ __global__ __launch_bounds__(256) void k_cvt_bf16(const float* __restrict__ src,
   }
 }
 
-// One pass on the bfloat16 matrix cores: out[p][c] = sum_k M[p][k] Xt[c][k].
+// One pass on the bfloat16 matrix cores: out[p][c] = sum_k M[p][k] Xt[c][k],
 //   M: P x K bf16 (ld ldm, 16-byte aligned rows, zero beyond the logical K),
-//   Xt: Ct x K bf16 (ld ldx), K a multiple of 64, Ct >= gridDim.y * NT * 16.
-// Workgroup: 256 threads, 128 rows of P (32 per wave, two 16-row MFMA tiles)
-// x NT*16 columns, a contiguous range of K walked 64 at a time.  The lane
-// (r, g) of v_mfma_f32_16x16x32_bf16 step h takes the entries
-// k0 + 16 g + 8 h + [0, 8) of its row of M and of its column of X, so each
-// lane reads 32 contiguous bytes of a row per stage; both operands use the
-// same assignment, so the contraction is unchanged.  A goes from HBM straight
-// to registers (prefetched one stage ahead); the sketch stage is shared by
-// the four waves through a double-buffered LDS tile.
+//   Xt: Ct x K bf16 (ld ldx), K a multiple of 128, Ct >= gridDim.y * NT * 16,
+// with A and the sketch staged through LDS by direct loads (global_load_lds,
+// 16 bytes per lane, nothing held in registers).  A pass over A is bound by
+// HBM, and HBM delivers far less for short runs per row: a plain streaming
+// kernel reads 3.3 TB/s in runs of 128 bytes per row and 5.4-5.9 TB/s in
+// runs of 256-2048 bytes (measured).  So a stage here spans 128 entries of K
+// (256 bytes of each row), and every load instruction moves 4 whole rows of
+// a stage.
+// The 16-byte chunks are placed in LDS by an XOR of chunk and row index so
+// that the MFMA operand reads stay free of bank conflicts.
+//   Workgroup: 512 threads, 256 rows of P x NT*16 columns (NT <= 8).  The
+//   sketch block of a stage is re-read from L2 by every workgroup: 256 rows
+//   keep that traffic at NT * 16 / 256 of A's (measured: with 128 rows the
+//   sketch traffic alone cost a fifth of the pass).  LDS: A in two 64 KB
+//   buffers (loaded up to two stages ahead, non-temporal, from HBM), the
+//   sketch in one of 32 KB.
+//   Each wave loads 32 rows of A (8 instructions) and up to 4 of the
+//   sketch's 4 NT blocks per stage, A last, and waits with vmcnt(8): loads
+//   complete in order, so at that point only its A loads of the next stage
+//   may still be outstanding.  The MFMA work of a stage is split over the
+//   waves along the contraction (2 x 32 entries each, for 64 rows), which
+//   keeps the LDS reads at 1.5 bytes per byte of A; the two partial sums of
+//   each row block are added once at the end.
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+// LDS byte offset of a __shared__ object (its address in the local space).
+__device__ __forceinline__ uint32_t lds_off(const void* p) {
+  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
+      (const __attribute__((address_space(3))) void*)p));
+}
+
+// The MFMA operands of a wave's step of a stage, read from LDS in one block
+// that waits for its own reads: A's fragments of 4 row tiles at a + 4 KB t
+// and the sketch's fragments of NX column tiles at x + 4 KB j.  The compiler
+// does not see these reads, so it adds no wait for the loads to LDS still in
+// flight (it cannot tell that they write other buffers); the kernel orders
+// them itself.
+template <int NX>
+__device__ __forceinline__ void lds_operands(uint32_t a, uint32_t x, u32x4v (&ao)[4],
+                                             u32x4v (&xo)[8]) {
+  if constexpr (NX == 8) {
+    asm volatile(
+        "ds_read_b128 %0, %12\n\t"
+        "ds_read_b128 %1, %12 offset:4096\n\t"
+        "ds_read_b128 %2, %12 offset:8192\n\t"
+        "ds_read_b128 %3, %12 offset:12288\n\t"
+        "ds_read_b128 %4, %13\n\t"
+        "ds_read_b128 %5, %13 offset:4096\n\t"
+        "ds_read_b128 %6, %13 offset:8192\n\t"
+        "ds_read_b128 %7, %13 offset:12288\n\t"
+        "ds_read_b128 %8, %13 offset:16384\n\t"
+        "ds_read_b128 %9, %13 offset:20480\n\t"
+        "ds_read_b128 %10, %13 offset:24576\n\t"
+        "ds_read_b128 %11, %13 offset:28672\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ao[0]), "=&v"(ao[1]), "=&v"(ao[2]), "=&v"(ao[3]), "=&v"(xo[0]), "=&v"(xo[1]),
+          "=&v"(xo[2]), "=&v"(xo[3]), "=&v"(xo[4]), "=&v"(xo[5]), "=&v"(xo[6]), "=&v"(xo[7])
+        : "v"(a), "v"(x)
+        : "memory");
+  } else {
+    static_assert(NX == 4, "4 or 8 sketch fragments");
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %8 offset:4096\n\t"
+        "ds_read_b128 %2, %8 offset:8192\n\t"
+        "ds_read_b128 %3, %8 offset:12288\n\t"
+        "ds_read_b128 %4, %9\n\t"
+        "ds_read_b128 %5, %9 offset:4096\n\t"
+        "ds_read_b128 %6, %9 offset:8192\n\t"
+        "ds_read_b128 %7, %9 offset:12288\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(ao[0]), "=&v"(ao[1]), "=&v"(ao[2]), "=&v"(ao[3]), "=&v"(xo[0]), "=&v"(xo[1]),
+          "=&v"(xo[2]), "=&v"(xo[3])
+        : "v"(a), "v"(x)
+        : "memory");
+  }
+}
+
 template <int NT, int EPI>
-__global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_bf16(const uint16_t* __restrict__ M, int64_t ldm,
-                                                      const uint16_t* __restrict__ Xt, int64_t ldx,
-                                                      float* out, int64_t ldo, int64_t part_stride,
-                                                      int64_t P, int64_t K, int64_t C,
-                                                      int64_t ksplit, int nsplit) {
-  constexpr int KS = 64;
-  constexpr int XR = NT * 16;
-  constexpr int XP = KS + 8;                 // LDS row pitch (elements): 144 bytes
-  constexpr int XCH = XR * (KS / 8);         // 16-byte chunks per sketch stage
-  constexpr int XIT = (XCH + 255) / 256;
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][XR * XP];
+__global__ __launch_bounds__(512, 1) void k_pass_bf16(const uint16_t* __restrict__ M,
+                                                          int64_t ldm,
+                                                          const uint16_t* __restrict__ Xt,
+                                                          int64_t ldx, float* out, int64_t ldo,
+                                                          int64_t part_stride, int64_t P,
+                                                          int64_t K, int64_t C, int64_t ksplit,
+                                                          int nsplit) {
+  static_assert(NT >= 1 && NT <= 8, "at most 8 column tiles");
+  constexpr int KS = 128;
+  constexpr int BLK = 512;                      // uint16 per 1 KB block (4 rows of a stage)
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * BLK];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[32 * BLK];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
@@ -146,105 +216,147 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_bf16(const uint
   const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
   const int npb = nwg / nsplit;
   const int split = lid / npb;
-  const int64_t p0 = (int64_t)(lid % npb) * 128;
-  const int64_t c0 = (int64_t)blockIdx.y * XR;
+  const int64_t p0 = (int64_t)(lid % npb) * 256;
+  const int64_t c0 = (int64_t)blockIdx.y * (NT * 16);
   const int64_t kb = (int64_t)split * ksplit;
   const int64_t ke = (kb + ksplit < K) ? kb + ksplit : K;
+  const int nst = kb < ke ? (int)((ke - kb) / KS) : 0;
 
-  const int64_t pa0 = p0 + wave * 32 + r, pa1 = pa0 + 16;
-  const bool ok0 = pa0 < P, ok1 = pa1 < P;
-  const uint16_t* a0 = M + (ok0 ? pa0 : 0) * ldm + g4 * 16;
-  const uint16_t* a1 = M + (ok1 ? pa1 : 0) * ldm + g4 * 16;
-
-  uint4 ra[2][2], rn[2][2];
-  static_assert(XIT <= 4, "sketch stage larger than 4 chunks per thread");
-  uint4 rx0 = {0u, 0u, 0u, 0u}, rx1 = rx0, rx2 = rx0, rx3 = rx0;   // named: kept in VGPRs
-  f32x4 acc[2][NT];
+  // A load t (0..7) of wave w moves 4 rows of its 32, 256 bytes (the whole
+  // stage) of each: lane l writes the 16 bytes at 16 l of 1 KB block 8 w + t,
+  // i.e. row rho = 4 (t % 4) + l / 16 of 16-row tile 2 w + t / 4, slot
+  // l % 16, and fetches into it the 16-byte chunk (l % 16) ^ rho of that
+  // row.  Chunk c of row rho thus sits at slot c ^ rho: the MFMA reads below
+  // (16 rows, one chunk each) fall in 16 distinct bank groups.  Rows past P
+  // read row P - 1 (valid memory whose products are never stored).
+  const uint16_t* aa[8];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 8; ++t) {
+    const int rho = 4 * (t & 3) + g4;
+    const int64_t ra = p0 + wave * 32 + 16 * (t >> 2) + rho;
+    aa[t] = M + (ra < P ? ra : P - 1) * ldm + kb + ((r ^ rho) * 8);
+  }
+  // sketch block q = 4 wave + i holds columns 4 q .. 4 q + 3 of the column
+  // block, same arrangement (column tile q / 4, rows 4 (q % 4) + l / 16);
+  // blocks past the 4 NT real ones are not loaded
+  const uint16_t* xs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = wave * 4 + i;
+    const int rho = 4 * (q & 3) + g4;
+    xs[i] = Xt + (c0 + 4 * (q < 4 * NT ? q : 0) + g4) * ldx + kb + ((r ^ rho) * 8);
+  }
+  // wave w computes, for rows 64 (w / 2) .. + 64 (4 row tiles) and all NT
+  // column tiles, the 32-deep steps h = 2 (w % 2) and 2 (w % 2) + 1 of every
+  // stage; the two partial products of a row quarter are added at the end.
+  // Its fragment of step h of a 16-row tile: row r, chunk 4 h + g4, at byte
+  // r * 256 + ((4 h + g4) ^ r) * 16 of the tile's 4 KB.
+  const int quarter = wave >> 1, hk = wave & 1;
+  uint32_t off[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int h = 2 * hk + u;
+    off[u] = (uint32_t)(r * 256 + (((4 * h + g4) ^ r) * 16));
+  }
+
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // every thread loads (chunks past the tile re-read its last chunk, which
-  // keeps rx in registers: no load sits under a branch); only real chunks
-  // are stored to LDS
-  auto xsrc = [&](int it, int64_t k) __attribute__((always_inline)) {
-    const int q0 = it * 256 + tid;
-    const int q = q0 < XCH ? q0 : XCH - 1;
-    return reinterpret_cast<const uint4*>(Xt + (c0 + (q >> 3)) * ldx + k + (q & 7) * 8);
-  };
-  auto load_x = [&](int64_t k) __attribute__((always_inline)) {
-    rx0 = *xsrc(0, k);
-    if (XIT > 1) rx1 = *xsrc(1, k);
-    if (XIT > 2) rx2 = *xsrc(2, k);
-    if (XIT > 3) rx3 = *xsrc(3, k);
-  };
-  auto xdst = [&](int it, int buf) __attribute__((always_inline)) {
-    const int q = it * 256 + tid;
-    return reinterpret_cast<uint4*>(&Xs[buf][(q >> 3) * XP + (q & 7) * 8]);
-  };
-  auto store_x = [&](int buf) __attribute__((always_inline)) {
-    if (0 * 256 + tid < XCH) *xdst(0, buf) = rx0;
-    if (XIT > 1 && 1 * 256 + tid < XCH) *xdst(1, buf) = rx1;
-    if (XIT > 2 && 2 * 256 + tid < XCH) *xdst(2, buf) = rx2;
-    if (XIT > 3 && 3 * 256 + tid < XCH) *xdst(3, buf) = rx3;
-  };
-  auto load_a = [&](int64_t k, uint4 (&d)[2][2]) __attribute__((always_inline)) {
-    const uint4 z = {0u, 0u, 0u, 0u};
-    d[0][0] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k) : z;
-    d[0][1] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k + 8) : z;
-    d[1][0] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k) : z;
-    d[1][1] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k + 8) : z;
-  };
-  auto compute = [&](int buf, const uint4 (&a)[2][2]) __attribute__((always_inline)) {
+  // each issue moves the next stage of this wave's blocks and advances its
+  // source pointers by a stage; A is streamed once, so its loads are
+  // non-temporal (they should not push the sketch, re-read by every
+  // workgroup, out of L2)
+  auto issue_a = [&](uint16_t* Ab) __attribute__((always_inline)) {
+    uint16_t* ad = Ab + (wave * 8) * BLK;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const bf16x8 f0 = __builtin_bit_cast(bf16x8, a[0][h]);
-      const bf16x8 f1 = __builtin_bit_cast(bf16x8, a[1][h]);
+    for (int t = 0; t < 8; ++t) {
+      __builtin_amdgcn_global_load_lds(aa[t], ad + t * BLK, 16, 0, 2);
+      aa[t] += KS;
+    }
+  };
+  auto issue_x = [&]() __attribute__((always_inline)) {
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const bf16x8 b =
-            *reinterpret_cast<const bf16x8*>(&Xs[buf][(j * 16 + r) * XP + g4 * 16 + h * 8]);
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, b, acc[0][j], 0, 0, 0);
-        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1, b, acc[1][j], 0, 0, 0);
+    for (int i = 0; i < 4; ++i)
+      if (wave * 4 + i < 4 * NT) {
+        __builtin_amdgcn_global_load_lds(xs[i], Xs + (wave * 4 + i) * BLK, 16, 0, 0);
+        xs[i] += KS;
       }
+  };
+  constexpr int NX = NT <= 4 ? 4 : 8;
+  auto compute = [&](const uint16_t* Ab) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      u32x4v ao[4], xo[8];
+      lds_operands<NX>(lds_off(Ab) + (uint32_t)(quarter * 16384) + off[u], lds_off(Xs) + off[u],
+                       ao, xo);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bf16x8 f = __builtin_bit_cast(bf16x8, ao[t]);
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              f, __builtin_bit_cast(bf16x8, xo[j]), acc[t][j], 0, 0, 0);
+      }
+      // the fragments past NT were read too (the block reads NX); their
+      // values are not needed
+#pragma unroll
+      for (int j = NT; j < NX; ++j) asm volatile("" ::"v"(xo[j]));
     }
   };
-
-  // one stage: prefetch stage k + KS, multiply stage k, publish the prefetched
-  // sketch tile.  The two register sets alternate roles (static indexing).
-  auto stage = [&](int64_t k, const uint4 (&cur)[2][2], uint4 (&nxt)[2][2], int buf)
-      __attribute__((always_inline)) {
-    const bool more = k + KS < ke;
-    if (more) {
-      load_x(k + KS);         // issued first: its wait leaves the A loads in flight
-      load_a(k + KS, nxt);
-    }
-    compute(buf, cur);
-    if (more) store_x(buf ^ 1);
-    __syncthreads();
-  };
-  if (kb < ke) {
-    load_x(kb);
-    load_a(kb, ra);
-    store_x(0);
-    __syncthreads();
-    for (int64_t k = kb;;) {
-      stage(k, ra, rn, 0);
-      k += KS;
-      if (k >= ke) break;
-      stage(k, rn, ra, 1);
-      k += KS;
-      if (k >= ke) break;
-    }
+  // stage s: wait for its loads (A of stage s + 1 may stay in flight: the
+  // last 8 loads of this wave), a plain barrier (not __syncthreads(), whose
+  // fence would wait for every load to LDS in flight) that publishes the
+  // other waves' blocks, multiply, a barrier (every wave is done with the
+  // sketch and with A of stage s), then the sketch of stage s + 1 and A of
+  // stage s + 2 into those buffers.  The multiplication is short next to a
+  // stage of HBM traffic, so A's loads stay 1-2 stages ahead.
+  if (nst > 0) {
+    issue_a(As[0]);
+    issue_x();
+  }
+  if (nst > 1) issue_a(As[1]);
+  for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    compute(As[s & 1]);
+    __builtin_amdgcn_s_barrier();
+    if (s + 1 < nst) issue_x();
+    if (s + 2 < nst) issue_a(As[s & 1]);
   }
 
-  // acc[t][j][e] is out[p][c], p = p0 + 32 wave + 16 t + 4 g4 + e, c = c0 + 16 j + r
+  // the two partial products of each row quarter, added through LDS (the
+  // stage buffers are free: every wave is past its last step's barrier and
+  // no load is outstanding).  Lane-contiguous layout: entry (t, j, e) of a
+  // lane at ((t NT + j) 4 + e) 64 + lane, quarter q's at 28 KB q.
+  float* const red = reinterpret_cast<float*>(As[0]) + quarter * (4 * 8 * 4 * 64);
+  if (hk == 1) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[((t * NT + j) * 4 + e) * 64 + lane] = acc[t][j][e];
+  }
+  __syncthreads();
+  if (hk == 1) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[t][j][e] += red[((t * NT + j) * 4 + e) * 64 + lane];
+
+  // acc[t][j][e] is out[p][c], p = p0 + 64 quarter + 16 t + 4 g4 + e,
+  // c = c0 + 16 j + r
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t p = p0 + wave * 32 + t * 16 + g4 * 4 + e;
+      const int64_t p = p0 + quarter * 64 + t * 16 + g4 * 4 + e;
       if (p >= P) continue;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -256,7 +368,6 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_bf16(const uint
           out[p * ldo + c] = acc[t][j][e];
       }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -562,14 +673,14 @@ hipError_t launch_fp8_nt(int nt, dim3 grid, const uint8_t* M, const uint8_t* Ms,
 }
 
 template <int EPI>
-hipError_t launch_bf16_nt(int nt, dim3 grid, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
-                          int64_t ldx, float* out, int64_t ldo, int64_t ps, int64_t P, int64_t K,
-                          int64_t C, int64_t ks, int ns, hipStream_t s) {
+hipError_t launch_bf16_nt(int nt, dim3 grid, const uint16_t* M, int64_t ldm,
+                              const uint16_t* Xt, int64_t ldx, float* out, int64_t ldo, int64_t ps,
+                              int64_t P, int64_t K, int64_t C, int64_t ks, int ns, hipStream_t s) {
   switch (nt) {
-#define PLU_BF_CASE(N)                                                                      \
-  case N:                                                                                   \
-    hipLaunchKernelGGL((k_pass_bf16<N, EPI>), grid, dim3(256), 0, s, M, ldm, Xt, ldx, out, \
-                       ldo, ps, P, K, C, ks, ns);                                           \
+#define PLU_BF_CASE(N)                                                                       \
+  case N:                                                                                     \
+    hipLaunchKernelGGL((k_pass_bf16<N, EPI>), grid, dim3(512), 0, s, M, ldm, Xt, ldx, out, \
+                       ldo, ps, P, K, C, ks, ns);                                             \
     break;
     PLU_BF_CASE(1) PLU_BF_CASE(2) PLU_BF_CASE(3) PLU_BF_CASE(4)
     PLU_BF_CASE(5) PLU_BF_CASE(6) PLU_BF_CASE(7) PLU_BF_CASE(8)
@@ -580,6 +691,26 @@ hipError_t launch_bf16_nt(int nt, dim3 grid, const uint16_t* M, int64_t ldm, con
 }
 
 }  // namespace
+
+hipError_t launch_pass_bf16(int epi, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
+                                int64_t ldx, float* out, int64_t ldo, int64_t part_stride,
+                                int64_t P, int64_t K, int64_t C, const GemmPlan& pl,
+                                hipStream_t s) {
+  // pl: pblocks of 256 rows, nt <= 8 column tiles per column block, rsplit
+  // and K multiples of 128; the sketch must have gridDim.y * nt * 16 rows
+  if (K % 128 != 0 || pl.rsplit % 128 != 0 || (ldm & 7) || (ldx & 7) || pl.nt > 8 || P <= 0 ||
+      (reinterpret_cast<uintptr_t>(M) & 15u) || (reinterpret_cast<uintptr_t>(Xt) & 15u) ||
+      (int64_t)pl.pblocks * 256 < P)
+    return hipErrorInvalidValue;
+  dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
+  if (epi == EPI_PART)
+    return launch_bf16_nt<EPI_PART>(pl.nt, grid, M, ldm, Xt, ldx, out, ldo, part_stride, P,
+                                        K, C, pl.rsplit, pl.nsplit, s);
+  if (epi == EPI_STORE)
+    return launch_bf16_nt<EPI_STORE>(pl.nt, grid, M, ldm, Xt, ldx, out, ldo, 0, P, K, C,
+                                         pl.rsplit, pl.nsplit, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_cvt_bf16(const float* src, int64_t lds, int64_t R, int64_t C, uint16_t* rm,
                            int64_t ldr, uint16_t* tr, int64_t ldt, int64_t Ct, double* sumsq_part,
@@ -594,22 +725,6 @@ hipError_t launch_cvt_bf16(const float* src, int64_t lds, int64_t R, int64_t C, 
   hipLaunchKernelGGL(k_cvt_bf16, dim3((unsigned)groups, (unsigned)bands), dim3(256), 0, s, src,
                      lds, R, C, rm, ldr, tr, ldt, Ct, ctiles, sumsq_part);
   return hipGetLastError();
-}
-
-hipError_t launch_pass_bf16(int epi, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
-                            int64_t ldx, float* out, int64_t ldo, int64_t part_stride, int64_t P,
-                            int64_t K, int64_t C, const GemmPlan& pl, hipStream_t s) {
-  if (K % 64 != 0 || pl.rsplit % 64 != 0 || (ldm & 7) || (ldx & 7) ||
-      (reinterpret_cast<uintptr_t>(M) & 15u) || (reinterpret_cast<uintptr_t>(Xt) & 15u))
-    return hipErrorInvalidValue;
-  dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
-  if (epi == EPI_PART)
-    return launch_bf16_nt<EPI_PART>(pl.nt, grid, M, ldm, Xt, ldx, out, ldo, part_stride, P, K, C,
-                                    pl.rsplit, pl.nsplit, s);
-  if (epi == EPI_STORE)
-    return launch_bf16_nt<EPI_STORE>(pl.nt, grid, M, ldm, Xt, ldx, out, ldo, 0, P, K, C,
-                                     pl.rsplit, pl.nsplit, s);
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_cvt_fp8(const float* src, int64_t lds, int64_t R, int64_t C, uint8_t* rm,

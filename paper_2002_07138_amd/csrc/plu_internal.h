@@ -103,8 +103,10 @@ hipError_t launch_pass_fp8(int epi, const uint8_t* M, const uint8_t* Ms, int64_t
                            const uint8_t* Xt, const uint8_t* Xsc, int64_t ldx, float* out,
                            int64_t ldo, int64_t part_stride, int64_t P, int64_t K, int64_t C,
                            const GemmPlan& pl, hipStream_t s);
-// out = M Xt^T on bfloat16 MFMA (M: P x K, Xt: Ct x K, K a multiple of 64);
-// the plan comes from plan_gemm(P, K, C, ..., 64); epi EPI_STORE or EPI_PART.
+// out = M Xt^T on bfloat16 MFMA (M: P x K, Xt: Ct x K), A and the sketch
+// staged through LDS by direct loads: workgroups of 512 threads and 256 rows
+// (pl.pblocks counts those, from plan_bf16), K and pl.rsplit multiples of
+// 128, pl.nt <= 8; epi EPI_STORE or EPI_PART.
 hipError_t launch_pass_bf16(int epi, const uint16_t* M, int64_t ldm, const uint16_t* Xt,
                             int64_t ldx, float* out, int64_t ldo, int64_t part_stride, int64_t P,
                             int64_t K, int64_t C, const GemmPlan& pl, hipStream_t s);
