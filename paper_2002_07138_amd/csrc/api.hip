@@ -86,7 +86,8 @@ constexpr int kQB = 128;
 constexpr int kMaxGramChunks = 256;
 constexpr int kTargetWgs = 1024;  // concurrent pass workgroups: 4 per CU on 256 CUs
 constexpr int kMaxSplit = 16;
-constexpr int kLowpWgs = 512;     // concurrent bfloat16 pass workgroups: 2 per CU
+constexpr int kLowpWgs = 512;     // 2 per CU: kLowpWgs / 2 is the CU count the
+                                  // workspace sizing of the precision form assumes
 
 inline int64_t ru4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
@@ -196,15 +197,24 @@ int64_t part_need(int64_t m, int64_t n, int64_t l) {
   return need;
 }
 
-// Split plan of the bfloat16 pass: workgroups of 256 rows, one per CU (their
-// LDS), splits on multiples of 128 along K, at most max_split.  The pass is
-// bound by the bytes of A, so the split weighs the rounds of cu_count
-// workgroups it needs (idle CUs in the last round) against the bytes its
-// float32 partials add (written and read back: 8 P l per split, against
-// 2 P K for A).
-GemmPlan plan_bf16(int64_t P, int64_t K, int64_t C, int cu_count, int max_split) {
+// Split plan of the reduced-precision passes: workgroups of `rows` rows
+// (256 for bfloat16, 192 for FP8), one per CU (their LDS), splits on
+// multiples of the stage depth ka along K, at most max_split.  A sketch of
+// more than 8 column tiles (128 columns) up to wide_max tiles takes the wide
+// kernel (one column block of 192 rows, A streamed once) instead of several
+// column blocks.  The pass is bound by the bytes of A (bpe per entry), so
+// the split weighs the rounds of cu_count workgroups it needs (idle CUs in
+// the last round) against the bytes its float32 partials add (written and
+// read back: 8 P l per split, against bpe P K for A).
+GemmPlan plan_lowp(int64_t P, int64_t K, int64_t C, int cu_count, int max_split, int rows,
+                   int64_t ka, double bpe, int wide_max) {
   GemmPlan pl = plan_gemm(P, K, C, 1, 1, 64);          // column blocks and tiles
-  pl.pblocks = (int)((P + 255) / 256);
+  if (pl.cblocks > 1 && (C + 15) / 16 <= wide_max) {
+    pl.cblocks = 1;
+    pl.nt = (int)((C + 15) / 16);
+    rows = 192;
+  }
+  pl.pblocks = (int)((P + rows - 1) / rows);
   const int64_t base = (int64_t)pl.pblocks * pl.cblocks;
   const int64_t hi =
       std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kMaxSplit, max_split), K / 256));
@@ -213,39 +223,43 @@ GemmPlan plan_bf16(int64_t P, int64_t K, int64_t C, int cu_count, int max_split)
   for (int64_t ns = 1; ns <= hi; ++ns) {
     const int64_t tot = base * ns, rounds = (tot + cu_count - 1) / cu_count;
     const double cost = (double)(rounds * cu_count) / (double)tot +
-                        (ns > 1 ? (double)ns * 8.0 * C / (2.0 * K) : 0.0);
+                        (ns > 1 ? (double)ns * 8.0 * C / (bpe * K) : 0.0);
     if (cost < best_cost) {
       best_cost = cost;
       best_ns = ns;
     }
   }
-  const int64_t rs = ru((K + best_ns - 1) / best_ns, 128);
+  const int64_t rs = ru((K + best_ns - 1) / best_ns, ka);
   pl.nsplit = (int)((K + rs - 1) / rs);
   pl.rsplit = rs;
   return pl;
 }
 
+GemmPlan plan_lowp(int prec, int64_t P, int64_t K, int64_t C, int cu_count, int max_split) {
+  return prec == PLU_PREC_BF16
+             ? plan_lowp(P, K, C, cu_count, max_split, 256, 128, 2.0, 16)
+             : plan_lowp(P, K, C, cu_count, max_split, 192, 256, 33.0 / 32.0, 14);
+}
+
 // Contraction padding of the reduced-precision copies (the depth of one
-// stage of either pass kernel).
-constexpr int64_t kLowpKAlign = 128;
+// stage of the pass kernel).
+inline int64_t lowp_kalign(int prec) { return prec == PLU_PREC_FP8_E4M3 ? 256 : 128; }
 
 // Rows of the transposed sketch a reduced-precision pass over C columns
 // reads (both pass kernels take plan_gemm's column blocking).
 int64_t lowp_xt_rows(int64_t P, int64_t K, int64_t C) {
-  const GemmPlan pl = plan_gemm(P, K, C, 1, 1, (int)kLowpKAlign);
+  const GemmPlan pl = plan_gemm(P, K, C, 1, 1, 64);
   return ru((int64_t)pl.cblocks * pl.nt * 16, 64);
 }
 
 // Float32 partials of the split passes of the precision form, on a device of
-// kLowpWgs / 2 CUs (run_pass_bf16 takes a smaller split where it must).
+// kLowpWgs / 2 CUs (the passes take a smaller split where they must).
 int64_t lowp_part_need(int64_t m, int64_t n, int64_t l, int prec) {
   int64_t need = 0;
-  const int64_t lp = ru4(l);
+  const int64_t lp = ru4(l), ka = lowp_kalign(prec);
   for (int tr = 0; tr < 2; ++tr) {
-    const int64_t P = tr ? n : m, K = ru(tr ? m : n, kLowpKAlign);
-    const GemmPlan pl = prec == PLU_PREC_BF16
-                            ? plan_bf16(P, K, l, kLowpWgs / 2, kMaxSplit)
-                            : plan_gemm(P, K, l, kMaxSplit, kLowpWgs, (int)kLowpKAlign);
+    const int64_t P = tr ? n : m, K = ru(tr ? m : n, ka);
+    const GemmPlan pl = plan_lowp(prec, P, K, l, kLowpWgs / 2, kMaxSplit);
     if (pl.nsplit > 1) need = std::max(need, (int64_t)pl.nsplit * P * lp);
   }
   return need;
@@ -268,8 +282,8 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
     w.abt = L.take<uint16_t>((size_t)n * w.ldabt);
     w.anorm = L.take<double>(1);
   } else if (prec == PLU_PREC_FP8_E4M3) {
-    w.lda8 = ru(n, 128);
-    w.lda8t = ru(m, 128);
+    w.lda8 = ru(n, 256);
+    w.lda8t = ru(m, 256);
     w.a8 = L.take<uint8_t>((size_t)m * w.lda8);
     w.a8s = L.take<uint8_t>((size_t)m * (w.lda8 / 32));
     w.a8t = L.take<uint8_t>((size_t)n * w.lda8t);
@@ -321,7 +335,7 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
     w.cvt_cap = ((std::max(ru(m, 128), ru(n, 128)) + 63) / 64) * 8;   // either storage order
     w.cvt_part = L.take<double>(w.cvt_cap);
   } else if (prec == PLU_PREC_FP8_E4M3) {
-    w.ldx8 = ru(Mx, 128);
+    w.ldx8 = ru(Mx, 256);
     w.x8_rows = std::max(lowp_xt_rows(m, w.lda8, l), lowp_xt_rows(n, w.lda8t, l));
     w.x8 = L.take<uint8_t>((size_t)w.x8_rows * w.ldx8);
     w.x8s = L.take<uint8_t>((size_t)w.x8_rows * (w.ldx8 / 32));
@@ -757,7 +771,7 @@ hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_
   // the split the partials buffer holds (it is sized for the plan on a
   // device of kLowpWgs / 2 CUs; on others a smaller split may be taken)
   const int cap = (int)std::max<int64_t>(1, w.part_cap / std::max<int64_t>(1, P * pld));
-  const GemmPlan pl = plan_bf16(P, K, l, h->cu_count, cap);
+  const GemmPlan pl = plan_lowp(PLU_PREC_BF16, P, K, l, h->cu_count, cap);
   const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
   if (ct > w.xt_rows || K > w.ldxt || K > ldm) return hipErrorInvalidValue;
   hipError_t e;
@@ -825,16 +839,16 @@ hipError_t lowp_copies(plu_handle h, const Ws& w, int fmt, int64_t m, int64_t n,
 // One pass of the FP8 form: both operands block-scaled E4M3, fp32 accumulation.
 hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t n,
                         const float* X, int64_t ldx, int64_t l, float* out, int64_t ldo) {
-  const int64_t P = trans ? n : m, Kl = trans ? m : n, K = ru(Kl, 128);
+  // the kernel walks K 256 at a time (the copies are padded to that)
+  const int64_t P = trans ? n : m, Kl = trans ? m : n, K = ru(Kl, 256);
   const uint8_t* M = trans ? w.a8t : w.a8;
   const uint8_t* Ms = trans ? w.a8ts : w.a8s;
   const int64_t ldm = trans ? w.lda8t : w.lda8;
   const int64_t pld = part_ld(ldo);
-  GemmPlan pl = plan_gemm(P, K, l, kMaxSplit, kLowpWgs, 128);
-  if (pl.nsplit > 1 && (int64_t)pl.nsplit * P * pld > w.part_cap)
-    pl = plan_gemm(P, K, l, 1, 1, 128);
+  const int cap = (int)std::max<int64_t>(1, w.part_cap / std::max<int64_t>(1, P * pld));
+  const GemmPlan pl = plan_lowp(PLU_PREC_FP8_E4M3, P, K, l, h->cu_count, cap);
   const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
-  if (ct > w.x8_rows || K > w.ldx8) return hipErrorInvalidValue;
+  if (ct > w.x8_rows || K > w.ldx8 || K > ldm) return hipErrorInvalidValue;
   hipError_t e;
   if ((e = launch_cvt_fp8(X, ldx, Kl, l, nullptr, nullptr, 0, w.x8, w.x8s, K, ct, h->stream)) !=
       hipSuccess)

@@ -494,31 +494,100 @@ __global__ __launch_bounds__(256) void k_cvt_fp8(const float* __restrict__ src, 
 
 // One pass on the FP8 matrix cores with per-block scales:
 // out[p][c] = sum_k (M[p][k] 2^sM[p][k/32]) (Xt[c][k] 2^sX[c][k/32]).
-//   M: P x K codes (ld ldm, K a multiple of 128), Ms: P x K/32 scale bytes;
-//   Xt: Ct x K codes (ld ldx), Xs: Ct x K/32.
+//   M: P x K codes (ld ldm, K a multiple of 256), Ms: P x K/32 scale bytes
+//   (ld ldm / 32, 4-byte aligned rows); Xt: Ct x K codes (ld ldx), Xsc:
+//   Ct x K/32 (ld ldx / 32).
 // v_mfma_scale_f32_16x16x128_f8f6f4 (layout measured on gfx950): lane
 // (r, g) supplies row r's codes k0 + 16 g + [0, 16) in its first 16 bytes and
 // k0 + 64 + 16 g + [0, 16) in its last 16, and the scale of block
 // k0/32 + g; the hardware applies the scale of lane group b to the 32
 // entries k0 + 32 b + [0, 32), which lane groups 2(b mod 2) and 2(b mod 2)+1
-// hold.  Both operands use this layout.  Same decomposition as k_pass_bf16
-// with 128 of K per stage.
+// hold.  Both operands use this layout.
+// Same design as the bfloat16 pass: a stage is 256 entries of K (256 bytes
+// of each row), every load moves whole rows of a stage into LDS with the
+// chunks XOR-swizzled, A non-temporal in two buffers, the sketch in one.
+// The scale bytes of a stage (8 per row) come along by 4-byte direct loads.
+// LDS holds 192 rows of A per buffer (2 x 48 KB + 2 x 1.5 KB of scales, the
+// sketch 32 KB + 1 KB): 256 rows would not leave room for the scales.  The
+// two 128-deep MFMA steps of a stage are split over the waves (wave w: 3 row
+// tiles of rows 48 (w / 2) .., step w % 2); the two partial sums of each row
+// block are added once at the end.
+// 3 row tiles of A: both 16-byte halves of each fragment, the first at
+// a1 + 4 KB t, the second at a2 + 4 KB t.
+__device__ __forceinline__ void lds_read2x3(uint32_t a1, uint32_t a2, u32x4v (&o)[6]) {
+  asm volatile(
+      "ds_read_b128 %0, %6\n\t"
+      "ds_read_b128 %1, %7\n\t"
+      "ds_read_b128 %2, %6 offset:4096\n\t"
+      "ds_read_b128 %3, %7 offset:4096\n\t"
+      "ds_read_b128 %4, %6 offset:8192\n\t"
+      "ds_read_b128 %5, %7 offset:8192\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5])
+      : "v"(a1), "v"(a2)
+      : "memory");
+}
+
+// 4 column tiles of the sketch: both 16-byte halves of each fragment, the
+// first at x1 + 4 KB j, the second at x2 + 4 KB j.
+__device__ __forceinline__ void lds_read2x4(uint32_t x1, uint32_t x2, u32x4v (&o)[8]) {
+  asm volatile(
+      "ds_read_b128 %0, %8\n\t"
+      "ds_read_b128 %1, %9\n\t"
+      "ds_read_b128 %2, %8 offset:4096\n\t"
+      "ds_read_b128 %3, %9 offset:4096\n\t"
+      "ds_read_b128 %4, %8 offset:8192\n\t"
+      "ds_read_b128 %5, %9 offset:8192\n\t"
+      "ds_read_b128 %6, %8 offset:12288\n\t"
+      "ds_read_b128 %7, %9 offset:12288\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]),
+        "=&v"(o[6]), "=&v"(o[7])
+      : "v"(x1), "v"(x2)
+      : "memory");
+}
+
+// Scale bytes: 3 of A at sa + 128 t, 8 of the sketch at sx + 128 j.
+__device__ __forceinline__ void lds_scales(uint32_t sa, uint32_t sx, uint32_t (&ao)[3],
+                                           uint32_t (&xo)[8]) {
+  asm volatile(
+      "ds_read_u8 %0, %11\n\t"
+      "ds_read_u8 %1, %11 offset:128\n\t"
+      "ds_read_u8 %2, %11 offset:256\n\t"
+      "ds_read_u8 %3, %12\n\t"
+      "ds_read_u8 %4, %12 offset:128\n\t"
+      "ds_read_u8 %5, %12 offset:256\n\t"
+      "ds_read_u8 %6, %12 offset:384\n\t"
+      "ds_read_u8 %7, %12 offset:512\n\t"
+      "ds_read_u8 %8, %12 offset:640\n\t"
+      "ds_read_u8 %9, %12 offset:768\n\t"
+      "ds_read_u8 %10, %12 offset:896\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(ao[0]), "=&v"(ao[1]), "=&v"(ao[2]), "=&v"(xo[0]), "=&v"(xo[1]), "=&v"(xo[2]),
+        "=&v"(xo[3]), "=&v"(xo[4]), "=&v"(xo[5]), "=&v"(xo[6]), "=&v"(xo[7])
+      : "v"(sa), "v"(sx)
+      : "memory");
+}
+
+__device__ __forceinline__ i32x8 cat8(const u32x4v& lo, const u32x4v& hi) {
+  return __builtin_bit_cast(i32x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 template <int NT, int EPI>
-__global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8_t* __restrict__ M,
+__global__ __launch_bounds__(512, 1) void k_pass_fp8(const uint8_t* __restrict__ M,
                                                      const uint8_t* __restrict__ Ms, int64_t ldm,
                                                      const uint8_t* __restrict__ Xt,
                                                      const uint8_t* __restrict__ Xsc, int64_t ldx,
                                                      float* out, int64_t ldo, int64_t part_stride,
                                                      int64_t P, int64_t K, int64_t C,
                                                      int64_t ksplit, int nsplit) {
-  constexpr int KS = 128;
-  constexpr int XR = NT * 16;
-  constexpr int XP = KS + 16;                // LDS row pitch (bytes)
-  constexpr int XCH = XR * (KS / 16);        // 16-byte chunks per sketch stage
-  constexpr int XIT = (XCH + 255) / 256;
-  static_assert(XIT <= 4, "sketch stage larger than 4 chunks per thread");
-  __shared__ __attribute__((aligned(16))) uint8_t Xs[2][XR * XP];
-  __shared__ uint32_t Xss[2][XR];           // the 4 scale bytes of a sketch row per stage
+  static_assert(NT >= 1 && NT <= 8, "at most 8 column tiles");
+  constexpr int KS = 256;
+  constexpr int ROWS = 192;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][ROWS * 256];
+  __shared__ __attribute__((aligned(16))) uint8_t Ass[2][ROWS * 8];
+  __shared__ __attribute__((aligned(16))) uint8_t Xs[128 * 256];
+  __shared__ __attribute__((aligned(16))) uint8_t Xss[128 * 8];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
@@ -528,117 +597,163 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8
   const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
   const int npb = nwg / nsplit;
   const int split = lid / npb;
-  const int64_t p0 = (int64_t)(lid % npb) * 128;
-  const int64_t c0 = (int64_t)blockIdx.y * XR;
+  const int64_t p0 = (int64_t)(lid % npb) * ROWS;
+  const int64_t c0 = (int64_t)blockIdx.y * (NT * 16);
   const int64_t kb = (int64_t)split * ksplit;
   const int64_t ke = (kb + ksplit < K) ? kb + ksplit : K;
+  const int nst = kb < ke ? (int)((ke - kb) / KS) : 0;
   const int64_t lds_ = ldm / 32, ldxs = ldx / 32;
 
-  const int64_t pa0 = p0 + wave * 32 + r, pa1 = pa0 + 16;
-  const bool ok0 = pa0 < P, ok1 = pa1 < P;
-  const uint8_t* a0 = M + (ok0 ? pa0 : 0) * ldm + g4 * 16;
-  const uint8_t* a1 = M + (ok1 ? pa1 : 0) * ldm + g4 * 16;
-  const uint8_t* s0 = Ms + (ok0 ? pa0 : 0) * lds_ + g4;
-  const uint8_t* s1 = Ms + (ok1 ? pa1 : 0) * lds_ + g4;
-
-  uint4 ra[2][2], rn[2][2];
-  uint32_t sa[2], sn[2];
-  uint4 rx0 = {0u, 0u, 0u, 0u}, rx1 = rx0, rx2 = rx0, rx3 = rx0;
-  uint32_t rxs = 0;
-  f32x4 acc[2][NT];
+  // A codes: load t (0..5) of wave w moves rows 24 w + 4 t + l / 16 (16-row
+  // tile (24 w + 4 t) / 16), lane l into slot l % 16 of its row with chunk
+  // (l % 16) ^ rho, rho the row's index in its tile.  Rows past P read row
+  // P - 1 (valid memory whose products are never stored).
+  const uint8_t* aa[6];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 6; ++t) {
+    const int row = wave * 24 + 4 * t + g4;
+    const int rho = row & 15;
+    const int64_t ra = p0 + row;
+    aa[t] = M + (ra < P ? ra : P - 1) * ldm + kb + ((r ^ rho) * 16);
+  }
+  // A scales: waves 0..5 move 32 rows each, lane l the 4 bytes (l & 1) of
+  // row 32 w + l / 2 (8 bytes per row and stage)
+  const uint8_t* as_;
+  {
+    const int64_t ra = p0 + (wave < 6 ? wave : 0) * 32 + (lane >> 1);
+    as_ = Ms + (ra < P ? ra : P - 1) * lds_ + kb / 32 + (lane & 1) * 4;
+  }
+  // sketch codes: block q = 4 w + i (columns 4 q .. 4 q + 3 of the column
+  // block), as for A; blocks past the 4 NT real ones are not loaded
+  const uint8_t* xs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = wave * 4 + i;
+    const int rho = 4 * (q & 3) + g4;
+    xs[i] = Xt + (c0 + 4 * (q < 4 * NT ? q : 0) + g4) * ldx + kb + ((r ^ rho) * 16);
+  }
+  // sketch scales: waves 0..3 move 32 columns each (those past 16 NT read
+  // column 0 again, into slots never used)
+  const uint8_t* xss;
+  {
+    const int col = (wave < 4 ? wave : 0) * 32 + (lane >> 1);
+    xss = Xsc + (c0 + (col < 16 * NT ? col : 0)) * ldxs + kb / 32 + (lane & 1) * 4;
+  }
+
+  // wave w: rows 48 grp .. + 48 (3 row tiles), MFMA step u of each stage
+  const int grp = wave >> 1, u = wave & 1;
+  const uint32_t off1 = (uint32_t)(r * 256 + (((8 * u + g4) ^ r) * 16));
+  const uint32_t off2 = (uint32_t)(r * 256 + (((8 * u + 4 + g4) ^ r) * 16));
+  const uint32_t soff = (uint32_t)(r * 8 + 4 * u + g4);
+
+  f32x4 acc[3][NT];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  auto xsrc = [&](int it, int64_t k) __attribute__((always_inline)) {
-    const int q0 = it * 256 + tid;
-    const int q = q0 < XCH ? q0 : XCH - 1;
-    return reinterpret_cast<const uint4*>(Xt + (c0 + (q >> 3)) * ldx + k + (q & 7) * 16);
-  };
-  auto load_x = [&](int64_t k) __attribute__((always_inline)) {
-    rx0 = *xsrc(0, k);
-    if (XIT > 1) rx1 = *xsrc(1, k);
-    if (XIT > 2) rx2 = *xsrc(2, k);
-    if (XIT > 3) rx3 = *xsrc(3, k);
-    const int row = tid < XR ? tid : XR - 1;
-    rxs = *reinterpret_cast<const uint32_t*>(Xsc + (c0 + row) * ldxs + k / 32);
-  };
-  auto xdst = [&](int it, int buf) __attribute__((always_inline)) {
-    const int q = it * 256 + tid;
-    return reinterpret_cast<uint4*>(&Xs[buf][(q >> 3) * XP + (q & 7) * 16]);
-  };
-  auto store_x = [&](int buf) __attribute__((always_inline)) {
-    if (0 * 256 + tid < XCH) *xdst(0, buf) = rx0;
-    if (XIT > 1 && 1 * 256 + tid < XCH) *xdst(1, buf) = rx1;
-    if (XIT > 2 && 2 * 256 + tid < XCH) *xdst(2, buf) = rx2;
-    if (XIT > 3 && 3 * 256 + tid < XCH) *xdst(3, buf) = rx3;
-    if (tid < XR) Xss[buf][tid] = rxs;
-  };
-  auto load_a = [&](int64_t k, uint4 (&d)[2][2], uint32_t (&sc)[2]) __attribute__((always_inline)) {
-    const uint4 z = {0u, 0u, 0u, 0u};
-    d[0][0] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k) : z;
-    d[0][1] = ok0 ? *reinterpret_cast<const uint4*>(a0 + k + 64) : z;
-    d[1][0] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k) : z;
-    d[1][1] = ok1 ? *reinterpret_cast<const uint4*>(a1 + k + 64) : z;
-    sc[0] = ok0 ? (uint32_t)s0[k / 32] : 0u;
-    sc[1] = ok1 ? (uint32_t)s1[k / 32] : 0u;
-  };
-  auto compute = [&](int buf, const uint4 (&a)[2][2], const uint32_t (&sc)[2])
-      __attribute__((always_inline)) {
-    i32x8 fa[2];
+  auto issue_a = [&](int b) __attribute__((always_inline)) {
+    uint8_t* ad = As[b] + wave * 6 * 1024;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      fa[t][0] = (int)a[t][0].x; fa[t][1] = (int)a[t][0].y; fa[t][2] = (int)a[t][0].z;
-      fa[t][3] = (int)a[t][0].w; fa[t][4] = (int)a[t][1].x; fa[t][5] = (int)a[t][1].y;
-      fa[t][6] = (int)a[t][1].z; fa[t][7] = (int)a[t][1].w;
+    for (int t = 0; t < 6; ++t) {
+      __builtin_amdgcn_global_load_lds(aa[t], ad + t * 1024, 16, 0, 2);
+      aa[t] += KS;
+    }
+  };
+  // sketch and scales of a stage; the A scales ride here too (issued before
+  // the sketch's codes, so a wait for those covers them)
+  auto issue_x = [&](int b_scales) __attribute__((always_inline)) {
+    if (wave < 6) __builtin_amdgcn_global_load_lds(as_, Ass[b_scales] + wave * 256, 4, 0, 0);
+    as_ += KS / 32;
+    if (wave < 4) __builtin_amdgcn_global_load_lds(xss, Xss + wave * 256, 4, 0, 0);
+    xss += KS / 32;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (wave * 4 + i < 4 * NT) {
+        __builtin_amdgcn_global_load_lds(xs[i], Xs + (wave * 4 + i) * 1024, 16, 0, 0);
+        xs[i] += KS;
+      }
+  };
+  auto compute = [&](int b) __attribute__((always_inline)) {
+    uint32_t sa[3], sx[8];
+    lds_scales(lds_off(Ass[b]) + (uint32_t)(grp * 48 * 8) + soff, lds_off(Xss) + soff, sa, sx);
+    u32x4v ao[6];
+    const uint32_t abase = lds_off(As[b]) + (uint32_t)(grp * 3 * 4096);
+    lds_read2x3(abase + off1, abase + off2, ao);
+    i32x8 fa[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) fa[t] = cat8(ao[2 * t], ao[2 * t + 1]);
+    const uint32_t xbase = lds_off(Xs);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (half * 4 >= NT) break;
+      u32x4v xo[8];
+      lds_read2x4(xbase + (uint32_t)(half * 16384) + off1, xbase + (uint32_t)(half * 16384) + off2,
+                  xo);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = half * 4 + jj;
+        if (j < NT) {
+          const i32x8 fb = cat8(xo[2 * jj], xo[2 * jj + 1]);
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            acc[t][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                fa[t], fb, acc[t][j], 0, 0, 0, (int)sa[t], 0, (int)sx[j]);
+        } else {
+          asm volatile("" ::"v"(xo[2 * jj]), "v"(xo[2 * jj + 1]));
+        }
+      }
     }
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const uint8_t* bp = &Xs[buf][(j * 16 + r) * XP + g4 * 16];
-      const uint4 b0 = *reinterpret_cast<const uint4*>(bp);
-      const uint4 b1 = *reinterpret_cast<const uint4*>(bp + 64);
-      i32x8 fb;
-      fb[0] = (int)b0.x; fb[1] = (int)b0.y; fb[2] = (int)b0.z; fb[3] = (int)b0.w;
-      fb[4] = (int)b1.x; fb[5] = (int)b1.y; fb[6] = (int)b1.z; fb[7] = (int)b1.w;
-      const int bs = (int)((Xss[buf][j * 16 + r] >> (8 * g4)) & 0xFFu);
-      acc[0][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[0], fb, acc[0][j], 0, 0, 0,
-                                                                   (int)sc[0], 0, bs);
-      acc[1][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[1], fb, acc[1][j], 0, 0, 0,
-                                                                   (int)sc[1], 0, bs);
-    }
+    for (int j = NT; j < 8; ++j) asm volatile("" ::"v"(sx[j]));
   };
-  auto stage = [&](int64_t k, const uint4 (&cur)[2][2], const uint32_t (&cs)[2],
-                   uint4 (&nxt)[2][2], uint32_t (&ns)[2], int buf) __attribute__((always_inline)) {
-    const bool more = k + KS < ke;
-    if (more) {
-      load_x(k + KS);
-      load_a(k + KS, nxt, ns);
-    }
-    compute(buf, cur, cs);
-    if (more) store_x(buf ^ 1);
-    __syncthreads();
-  };
-  if (kb < ke) {
-    load_x(kb);
-    load_a(kb, ra, sa);
-    store_x(0);
-    __syncthreads();
-    for (int64_t k = kb;;) {
-      stage(k, ra, sa, rn, sn, 0);
-      k += KS;
-      if (k >= ke) break;
-      stage(k, rn, sn, ra, sa, 1);
-      k += KS;
-      if (k >= ke) break;
-    }
+  // stage s: wait for its loads (A of stage s + 1 may stay in flight: the
+  // last 6 loads of this wave), barrier, multiply, barrier, then the scales
+  // and sketch of stage s + 1 and A of stage s + 2.  The A scales of stage
+  // s + 1 go with the sketch of stage s + 1 into the scale buffer of stage
+  // s - 1 (free: its multiplication is past the last barrier).
+  if (nst > 0) {
+    issue_x(0);
+    issue_a(0);
+  }
+  if (nst > 1) issue_a(1);
+  for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    compute(s & 1);
+    __builtin_amdgcn_s_barrier();
+    if (s + 1 < nst) issue_x((s + 1) & 1);
+    if (s + 2 < nst) issue_a(s & 1);
   }
 
+  // the two partial products of each row block, added through LDS (every
+  // wave is past its last barrier and no load is outstanding).  Entry
+  // (t, j, e) of a lane at ((t NT + j) 4 + e) 64 + lane, group g's at 24 KB g.
+  float* const red = reinterpret_cast<float*>(As[0]) + grp * (3 * 8 * 4 * 64);
+  if (u == 1) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[((t * NT + j) * 4 + e) * 64 + lane] = acc[t][j][e];
+  }
+  __syncthreads();
+  if (u == 1) return;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[t][j][e] += red[((t * NT + j) * 4 + e) * 64 + lane];
+
+  // acc[t][j][e] is out[p][c], p = p0 + 48 grp + 16 t + 4 g4 + e, c = c0 + 16 j + r
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t p = p0 + wave * 32 + t * 16 + g4 * 4 + e;
+      const int64_t p = p0 + grp * 48 + t * 16 + g4 * 4 + e;
       if (p >= P) continue;
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -650,7 +765,365 @@ __global__ __launch_bounds__(256, (NT >= 8) ? 1 : 2) void k_pass_fp8(const uint8
           out[p * ldo + c] = acc[t][j][e];
       }
     }
+}
+
+// The wide forms of both passes (NT > 8 column tiles, sketches of more than
+// 128 columns): one workgroup holds all column tiles, so A is streamed once
+// (two column blocks would read it twice).  192 rows per workgroup (the
+// sketch stage takes up to 64 KB of LDS); wave w takes rows 48 (w / 2) ..
+// + 48 (3 row tiles) and the column tiles NTH (w % 2) .. + NTH (NTH =
+// ceil(NT / 2)) over the whole stage, so no partial sums are exchanged.
+// Loads, swizzle and stage schedule as in the narrow kernels.
+
+// 3 A fragments at a + 4 KB t and 8 sketch fragments at x + 4 KB j.
+__device__ __forceinline__ void lds_read_3_8(uint32_t a, uint32_t x, u32x4v (&ao)[3],
+                                             u32x4v (&xo)[8]) {
+  asm volatile(
+      "ds_read_b128 %0, %11\n\t"
+      "ds_read_b128 %1, %11 offset:4096\n\t"
+      "ds_read_b128 %2, %11 offset:8192\n\t"
+      "ds_read_b128 %3, %12\n\t"
+      "ds_read_b128 %4, %12 offset:4096\n\t"
+      "ds_read_b128 %5, %12 offset:8192\n\t"
+      "ds_read_b128 %6, %12 offset:12288\n\t"
+      "ds_read_b128 %7, %12 offset:16384\n\t"
+      "ds_read_b128 %8, %12 offset:20480\n\t"
+      "ds_read_b128 %9, %12 offset:24576\n\t"
+      "ds_read_b128 %10, %12 offset:28672\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(ao[0]), "=&v"(ao[1]), "=&v"(ao[2]), "=&v"(xo[0]), "=&v"(xo[1]), "=&v"(xo[2]),
+        "=&v"(xo[3]), "=&v"(xo[4]), "=&v"(xo[5]), "=&v"(xo[6]), "=&v"(xo[7])
+      : "v"(a), "v"(x)
+      : "memory");
+}
+
+template <int NT, int EPI>
+__global__ __launch_bounds__(512, 1) void k_pass_bf16_wide(const uint16_t* __restrict__ M,
+                                                           int64_t ldm,
+                                                           const uint16_t* __restrict__ Xt,
+                                                           int64_t ldx, float* out, int64_t ldo,
+                                                           int64_t part_stride, int64_t P,
+                                                           int64_t K, int64_t C, int64_t ksplit,
+                                                           int nsplit) {
+  static_assert(NT > 8 && NT <= 16, "9 to 16 column tiles");
+  constexpr int KS = 128, ROWS = 192, NTH = (NT + 1) / 2;
+  constexpr int BLK = 512;                      // uint16 per 1 KB block (4 rows of a stage)
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][48 * BLK];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[64 * BLK];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int npb = nwg / nsplit;
+  const int split = lid / npb;
+  const int64_t p0 = (int64_t)(lid % npb) * ROWS;
+  const int64_t c0 = (int64_t)blockIdx.y * (NT * 16);
+  const int64_t kb = (int64_t)split * ksplit;
+  const int64_t ke = (kb + ksplit < K) ? kb + ksplit : K;
+  const int nst = kb < ke ? (int)((ke - kb) / KS) : 0;
+
+  // A: load t (0..5) of wave w moves rows 24 w + 4 t + l / 16 into block
+  // 6 w + t; sketch: block q = 8 w + i (q < 4 NT), columns 4 q + l / 16
+  const uint16_t* aa[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int row = wave * 24 + 4 * t + g4;
+    const int rho = row & 15;
+    const int64_t ra = p0 + row;
+    aa[t] = M + (ra < P ? ra : P - 1) * ldm + kb + ((r ^ rho) * 8);
   }
+  const uint16_t* xs[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int q = wave * 8 + i;
+    const int rho = 4 * (q & 3) + g4;
+    xs[i] = Xt + (c0 + 4 * (q < 4 * NT ? q : 0) + g4) * ldx + kb + ((r ^ rho) * 8);
+  }
+  const int grp = wave >> 1, half = wave & 1;
+  uint32_t off[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) off[h] = (uint32_t)(r * 256 + (((4 * h + g4) ^ r) * 16));
+
+  f32x4 acc[3][NTH];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int j = 0; j < NTH; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto issue_a = [&](int b) __attribute__((always_inline)) {
+    uint16_t* ad = As[b] + (wave * 6) * BLK;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      __builtin_amdgcn_global_load_lds(aa[t], ad + t * BLK, 16, 0, 2);
+      aa[t] += KS;
+    }
+  };
+  auto issue_x = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (wave * 8 + i < 4 * NT) {
+        __builtin_amdgcn_global_load_lds(xs[i], Xs + (wave * 8 + i) * BLK, 16, 0, 0);
+        xs[i] += KS;
+      }
+  };
+  auto compute = [&](int b) __attribute__((always_inline)) {
+    const uint32_t abase = lds_off(As[b]) + (uint32_t)(grp * 3 * 4096);
+    const uint32_t xbase = lds_off(Xs) + (uint32_t)(half * NTH * 4096);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      u32x4v ao[3], xo[8];
+      lds_read_3_8(abase + off[h], xbase + off[h], ao, xo);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const bf16x8 f = __builtin_bit_cast(bf16x8, ao[t]);
+#pragma unroll
+        for (int j = 0; j < NTH; ++j)
+          if (half * NTH + j < NT)
+            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                f, __builtin_bit_cast(bf16x8, xo[j]), acc[t][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = NTH; j < 8; ++j) asm volatile("" ::"v"(xo[j]));
+    }
+  };
+  if (nst > 0) {
+    issue_a(0);
+    issue_x();
+  }
+  if (nst > 1) issue_a(1);
+  for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    compute(s & 1);
+    __builtin_amdgcn_s_barrier();
+    if (s + 1 < nst) issue_x();
+    if (s + 2 < nst) issue_a(s & 1);
+  }
+
+  // acc[t][j][e] is out[p][c], p = p0 + 48 grp + 16 t + 4 g4 + e,
+  // c = c0 + 16 (NTH half + j) + r
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = p0 + grp * 48 + t * 16 + g4 * 4 + e;
+      if (p >= P) continue;
+#pragma unroll
+      for (int j = 0; j < NTH; ++j) {
+        const int64_t c = c0 + (half * NTH + j) * 16 + r;
+        if (half * NTH + j >= NT || c >= C) continue;
+        if (EPI == EPI_PART)
+          out[(int64_t)split * part_stride + p * ldo + c] = acc[t][j][e];
+        else
+          out[p * ldo + c] = acc[t][j][e];
+      }
+    }
+}
+
+// Scale bytes: 3 of A at sa + 128 t, 7 of the sketch at sx + 128 j.
+__device__ __forceinline__ void lds_scales_3_7(uint32_t sa, uint32_t sx, uint32_t (&ao)[3],
+                                               uint32_t (&xo)[7]) {
+  asm volatile(
+      "ds_read_u8 %0, %10\n\t"
+      "ds_read_u8 %1, %10 offset:128\n\t"
+      "ds_read_u8 %2, %10 offset:256\n\t"
+      "ds_read_u8 %3, %11\n\t"
+      "ds_read_u8 %4, %11 offset:128\n\t"
+      "ds_read_u8 %5, %11 offset:256\n\t"
+      "ds_read_u8 %6, %11 offset:384\n\t"
+      "ds_read_u8 %7, %11 offset:512\n\t"
+      "ds_read_u8 %8, %11 offset:640\n\t"
+      "ds_read_u8 %9, %11 offset:768\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(ao[0]), "=&v"(ao[1]), "=&v"(ao[2]), "=&v"(xo[0]), "=&v"(xo[1]), "=&v"(xo[2]),
+        "=&v"(xo[3]), "=&v"(xo[4]), "=&v"(xo[5]), "=&v"(xo[6])
+      : "v"(sa), "v"(sx)
+      : "memory");
+}
+
+template <int NT, int EPI>
+__global__ __launch_bounds__(512, 1) void k_pass_fp8_wide(const uint8_t* __restrict__ M,
+                                                          const uint8_t* __restrict__ Ms,
+                                                          int64_t ldm,
+                                                          const uint8_t* __restrict__ Xt,
+                                                          const uint8_t* __restrict__ Xsc,
+                                                          int64_t ldx, float* out, int64_t ldo,
+                                                          int64_t part_stride, int64_t P,
+                                                          int64_t K, int64_t C, int64_t ksplit,
+                                                          int nsplit) {
+  static_assert(NT > 8 && NT <= 14, "9 to 14 column tiles");
+  constexpr int KS = 256, ROWS = 192, NTH = (NT + 1) / 2;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][ROWS * 256];
+  __shared__ __attribute__((aligned(16))) uint8_t Ass[2][ROWS * 8];
+  __shared__ __attribute__((aligned(16))) uint8_t Xs[14 * 4096];
+  __shared__ __attribute__((aligned(16))) uint8_t Xss[14 * 16 * 8];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  const int lid = (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int npb = nwg / nsplit;
+  const int split = lid / npb;
+  const int64_t p0 = (int64_t)(lid % npb) * ROWS;
+  const int64_t c0 = (int64_t)blockIdx.y * (NT * 16);
+  const int64_t kb = (int64_t)split * ksplit;
+  const int64_t ke = (kb + ksplit < K) ? kb + ksplit : K;
+  const int nst = kb < ke ? (int)((ke - kb) / KS) : 0;
+  const int64_t lds_ = ldm / 32, ldxs = ldx / 32;
+
+  const uint8_t* aa[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int row = wave * 24 + 4 * t + g4;
+    const int rho = row & 15;
+    const int64_t ra = p0 + row;
+    aa[t] = M + (ra < P ? ra : P - 1) * ldm + kb + ((r ^ rho) * 16);
+  }
+  const uint8_t* as_;
+  {
+    const int64_t ra = p0 + (wave < 6 ? wave : 0) * 32 + (lane >> 1);
+    as_ = Ms + (ra < P ? ra : P - 1) * lds_ + kb / 32 + (lane & 1) * 4;
+  }
+  // sketch: block q = 8 w + i (q < 4 NT), columns 4 q + l / 16; blocks i
+  // and i + 4 differ by 16 columns, same chunk order
+  const uint8_t* xs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rho = 4 * i + g4;
+    xs[i] = Xt + (c0 + 4 * (wave * 8 + i) + g4) * ldx + kb + ((r ^ rho) * 16);
+  }
+  const int64_t x16 = 16 * ldx;
+  // sketch scales: waves 0..6 move 32 columns each (16 NT columns in all;
+  // those past it read column 0 again, into slots never used)
+  const uint8_t* xss;
+  {
+    const int col = (wave < 7 ? wave : 0) * 32 + (lane >> 1);
+    xss = Xsc + (c0 + (col < 16 * NT ? col : 0)) * ldxs + kb / 32 + (lane & 1) * 4;
+  }
+
+  const int grp = wave >> 1, half = wave & 1;
+  uint32_t off1[2], off2[2], soff[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    off1[u] = (uint32_t)(r * 256 + (((8 * u + g4) ^ r) * 16));
+    off2[u] = (uint32_t)(r * 256 + (((8 * u + 4 + g4) ^ r) * 16));
+    soff[u] = (uint32_t)(r * 8 + 4 * u + g4);
+  }
+
+  f32x4 acc[3][NTH];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int j = 0; j < NTH; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto issue_a = [&](int b) __attribute__((always_inline)) {
+    uint8_t* ad = As[b] + wave * 6 * 1024;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      __builtin_amdgcn_global_load_lds(aa[t], ad + t * 1024, 16, 0, 2);
+      aa[t] += KS;
+    }
+  };
+  auto issue_x = [&](int b_scales) __attribute__((always_inline)) {
+    if (wave < 6) __builtin_amdgcn_global_load_lds(as_, Ass[b_scales] + wave * 256, 4, 0, 0);
+    as_ += KS / 32;
+    if (wave < 7) __builtin_amdgcn_global_load_lds(xss, Xss + wave * 256, 4, 0, 0);
+    xss += KS / 32;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (wave * 8 + i < 4 * NT)
+        __builtin_amdgcn_global_load_lds(xs[i & 3] + (i >= 4 ? x16 : 0),
+                                         Xs + (wave * 8 + i) * 1024, 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xs[i] += KS;
+  };
+  auto compute = [&](int b) __attribute__((always_inline)) {
+    const uint32_t abase = lds_off(As[b]) + (uint32_t)(grp * 3 * 4096);
+    const uint32_t xbase = lds_off(Xs) + (uint32_t)(half * NTH * 4096);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      uint32_t sa[3], sx[7];
+      lds_scales_3_7(lds_off(Ass[b]) + (uint32_t)(grp * 48 * 8) + soff[u],
+                     lds_off(Xss) + (uint32_t)(half * NTH * 128) + soff[u], sa, sx);
+      u32x4v ao[6];
+      lds_read2x3(abase + off1[u], abase + off2[u], ao);
+      i32x8 fa[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) fa[t] = cat8(ao[2 * t], ao[2 * t + 1]);
+      // the sketch's 7 tiles in two phases (4, then 3)
+      // (for odd NT the second half's last tile is past the sketch: LDS
+      // inside the buffer, multiplied but never stored)
+      auto mma = [&](int j, const u32x4v& lo, const u32x4v& hi) __attribute__((always_inline)) {
+        const i32x8 fb = cat8(lo, hi);
+        if (j < NTH) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            acc[t][j < NTH ? j : 0] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                fa[t], fb, acc[t][j < NTH ? j : 0], 0, 0, 0, (int)sa[t], 0, (int)sx[j]);
+        } else {
+          asm volatile("" ::"v"(fb), "v"(sx[j]));
+        }
+      };
+      {
+        u32x4v x4[8];
+        lds_read2x4(xbase + off1[u], xbase + off2[u], x4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mma(j, x4[2 * j], x4[2 * j + 1]);
+      }
+      {
+        u32x4v x3[6];
+        lds_read2x3(xbase + 16384 + off1[u], xbase + 16384 + off2[u], x3);
+#pragma unroll
+        for (int j = 4; j < 7; ++j) mma(j, x3[2 * (j - 4)], x3[2 * (j - 4) + 1]);
+      }
+      // the first step's MFMAs stay ahead of the second step's reads; those
+      // of the second may move past the stage's barrier and overlap the
+      // next loads (all of them there would keep both steps' operands live)
+      if (u == 0) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+          for (int j = 0; j < NTH; ++j) asm volatile("" : "+v"(acc[t][j]));
+      }
+    }
+  };
+  if (nst > 0) {
+    issue_x(0);
+    issue_a(0);
+  }
+  if (nst > 1) issue_a(1);
+  for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    compute(s & 1);
+    __builtin_amdgcn_s_barrier();
+    if (s + 1 < nst) issue_x((s + 1) & 1);
+    if (s + 2 < nst) issue_a(s & 1);
+  }
+
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = p0 + grp * 48 + t * 16 + g4 * 4 + e;
+      if (p >= P) continue;
+#pragma unroll
+      for (int j = 0; j < NTH; ++j) {
+        const int64_t c = c0 + (half * NTH + j) * 16 + r;
+        if (half * NTH + j >= NT || c >= C) continue;
+        if (EPI == EPI_PART)
+          out[(int64_t)split * part_stride + p * ldo + c] = acc[t][j][e];
+        else
+          out[p * ldo + c] = acc[t][j][e];
+      }
+    }
 }
 
 template <int EPI>
@@ -661,12 +1134,20 @@ hipError_t launch_fp8_nt(int nt, dim3 grid, const uint8_t* M, const uint8_t* Ms,
   switch (nt) {
 #define PLU_F8_CASE(N)                                                                     \
   case N:                                                                                  \
-    hipLaunchKernelGGL((k_pass_fp8<N, EPI>), grid, dim3(256), 0, s, M, Ms, ldm, Xt, Xsc, \
+    hipLaunchKernelGGL((k_pass_fp8<N, EPI>), grid, dim3(512), 0, s, M, Ms, ldm, Xt, Xsc, \
                        ldx, out, ldo, ps, P, K, C, ks, ns);                                \
     break;
     PLU_F8_CASE(1) PLU_F8_CASE(2) PLU_F8_CASE(3) PLU_F8_CASE(4)
     PLU_F8_CASE(5) PLU_F8_CASE(6) PLU_F8_CASE(7) PLU_F8_CASE(8)
 #undef PLU_F8_CASE
+#define PLU_F8W_CASE(N)                                                                         \
+  case N:                                                                                       \
+    hipLaunchKernelGGL((k_pass_fp8_wide<N, EPI>), grid, dim3(512), 0, s, M, Ms, ldm, Xt, Xsc, \
+                       ldx, out, ldo, ps, P, K, C, ks, ns);                                     \
+    break;
+    PLU_F8W_CASE(9) PLU_F8W_CASE(10) PLU_F8W_CASE(11) PLU_F8W_CASE(12) PLU_F8W_CASE(13)
+    PLU_F8W_CASE(14)
+#undef PLU_F8W_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -685,6 +1166,14 @@ hipError_t launch_bf16_nt(int nt, dim3 grid, const uint16_t* M, int64_t ldm,
     PLU_BF_CASE(1) PLU_BF_CASE(2) PLU_BF_CASE(3) PLU_BF_CASE(4)
     PLU_BF_CASE(5) PLU_BF_CASE(6) PLU_BF_CASE(7) PLU_BF_CASE(8)
 #undef PLU_BF_CASE
+#define PLU_BFW_CASE(N)                                                                         \
+  case N:                                                                                       \
+    hipLaunchKernelGGL((k_pass_bf16_wide<N, EPI>), grid, dim3(512), 0, s, M, ldm, Xt, ldx, out, \
+                       ldo, ps, P, K, C, ks, ns);                                               \
+    break;
+    PLU_BFW_CASE(9) PLU_BFW_CASE(10) PLU_BFW_CASE(11) PLU_BFW_CASE(12) PLU_BFW_CASE(13)
+    PLU_BFW_CASE(14) PLU_BFW_CASE(15) PLU_BFW_CASE(16)
+#undef PLU_BFW_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -696,11 +1185,12 @@ hipError_t launch_pass_bf16(int epi, const uint16_t* M, int64_t ldm, const uint1
                                 int64_t ldx, float* out, int64_t ldo, int64_t part_stride,
                                 int64_t P, int64_t K, int64_t C, const GemmPlan& pl,
                                 hipStream_t s) {
-  // pl: pblocks of 256 rows, nt <= 8 column tiles per column block, rsplit
-  // and K multiples of 128; the sketch must have gridDim.y * nt * 16 rows
-  if (K % 128 != 0 || pl.rsplit % 128 != 0 || (ldm & 7) || (ldx & 7) || pl.nt > 8 || P <= 0 ||
+  // pl: nt <= 8 column tiles per column block with pblocks of 256 rows, or
+  // 9..16 (one column block) with pblocks of 192 rows; rsplit and K
+  // multiples of 128; the sketch must have gridDim.y * nt * 16 rows
+  if (K % 128 != 0 || pl.rsplit % 128 != 0 || (ldm & 7) || (ldx & 7) || pl.nt > 16 || P <= 0 ||
       (reinterpret_cast<uintptr_t>(M) & 15u) || (reinterpret_cast<uintptr_t>(Xt) & 15u) ||
-      (int64_t)pl.pblocks * 256 < P)
+      (int64_t)pl.pblocks * (pl.nt > 8 ? 192 : 256) < P)
     return hipErrorInvalidValue;
   dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
   if (epi == EPI_PART)
@@ -746,8 +1236,12 @@ hipError_t launch_pass_fp8(int epi, const uint8_t* M, const uint8_t* Ms, int64_t
                            const uint8_t* Xt, const uint8_t* Xsc, int64_t ldx, float* out,
                            int64_t ldo, int64_t part_stride, int64_t P, int64_t K, int64_t C,
                            const GemmPlan& pl, hipStream_t s) {
-  if (K % 128 != 0 || pl.rsplit % 128 != 0 || (ldm % 128) || (ldx % 128) ||
-      (reinterpret_cast<uintptr_t>(M) & 15u) || (reinterpret_cast<uintptr_t>(Xt) & 15u) ||
+  // pl: pblocks of 192 rows, nt <= 14 (above 8: the wide kernel, one column
+  // block), rsplit and K multiples of 256, the leading dimensions multiples
+  // of 256 (4-byte aligned scale rows)
+  if (K % 256 != 0 || pl.rsplit % 256 != 0 || (ldm % 256) || (ldx % 256) || pl.nt > 14 ||
+      P <= 0 || (int64_t)pl.pblocks * 192 < P || (reinterpret_cast<uintptr_t>(M) & 15u) ||
+      (reinterpret_cast<uintptr_t>(Xt) & 15u) || (reinterpret_cast<uintptr_t>(Ms) & 3u) ||
       (reinterpret_cast<uintptr_t>(Xsc) & 3u))
     return hipErrorInvalidValue;
   dim3 grid(pl.pblocks * pl.nsplit, pl.cblocks);
