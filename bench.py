@@ -722,6 +722,39 @@ def cpu_baseline(A_host, k, p_over, v, seed):
     }
 
 
+def profile_lowp(m, n):
+    """The precision-form pass kernels only: for BF16 and FP8, one pass per
+    direction that makes the rounded copies of A, then 3 passes A X and 3
+    passes A^T X on the kept copies (PLU_PREC_A_UNCHANGED), at the workload
+    shape (l = 110) and at 32768^2 with l = 220 (the wide kernels); then 3
+    copies of 1 GiB (the calibration kernel for the HBM byte counters)."""
+    import torch
+    import paper_2002_07138_amd as plu
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    h = plu.Handle(0)
+    for (mm, nn, l) in ((m, n, K_RANK + P_OVER), (32768, 32768, 220)):
+        A = torch.randn((mm, nn), device=dev, generator=g)
+        X_n = _sketch(nn, l, dev, g)
+        X_m = _sketch(mm, l, dev, g)
+        out_m = _sketch(mm, l, dev, fill=False)
+        out_n = _sketch(nn, l, dev, fill=False)
+        for prec in (1, 2):
+            h.pass_(A, X_n, trans=False, out=out_m, prec=prec)
+            for _ in range(3):
+                h.pass_(A, X_n, trans=False, out=out_m, prec=prec | A_UNCHANGED)
+            for _ in range(3):
+                h.pass_(A, X_m, trans=True, out=out_n, prec=prec | A_UNCHANGED)
+        del A, X_n, X_m, out_m, out_n
+        torch.cuda.empty_cache()
+    src = torch.empty(2 ** 28, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def profile_pass(m, n):
     """Dominant kernel only: one tuning pass per direction, then 3 passes A X
     and 3 passes A^T X at the workload
@@ -836,6 +869,10 @@ def main():
     ap.add_argument("--profile-lu", action="store_true",
                     help="run only the LU of a 20000 x 110 Gaussian matrix (10 calls) and a plain "
                          "1 GiB copy, for kernel-trace and hardware-counter runs")
+    ap.add_argument("--profile-lowp", action="store_true",
+                    help="run only the BF16 and FP8 pass kernels (20000^2, l = 110 and "
+                         "32768^2, l = 220) and a plain 1 GiB copy, for kernel-trace and "
+                         "hardware-counter runs")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run only the pass kernels at the workload shape (3 launches per "
                          "direction) and a plain 1 GiB copy, for hardware-counter runs")
@@ -854,6 +891,9 @@ def main():
     m = n = args.size
     if args.profile_pass:
         profile_pass(m, n)
+        return
+    if args.profile_lowp:
+        profile_lowp(m, n)
         return
     if args.profile_single_pass:
         profile_single_pass(m, n)

@@ -339,7 +339,8 @@ Ws layout(Layout& L, int64_t m, int64_t n, int64_t l, int prec = PLU_PREC_FP32,
     w.x8_rows = std::max(lowp_xt_rows(m, w.lda8, l), lowp_xt_rows(n, w.lda8t, l));
     w.x8 = L.take<uint8_t>((size_t)w.x8_rows * w.ldx8);
     w.x8s = L.take<uint8_t>((size_t)w.x8_rows * (w.ldx8 / 32));
-    w.sumsq_cap = std::max<int64_t>(w.sumsq_cap, 1);
+    w.cvt_cap = ((std::max(ru(m, 256), ru(n, 256)) + 63) / 64) * 8;   // either storage order
+    w.cvt_part = L.take<double>(w.cvt_cap);
   }
   if (basis_store) {
     w.vall = L.take<float>(n * lp);
@@ -370,7 +371,7 @@ bool stream_capturing(hipStream_t s) {
 // graph then never sees the messages of an earlier replay).
 int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
               int prec = PLU_PREC_FP32, bool basis_store = false, void* work = nullptr,
-              size_t work_bytes = 0) {
+              size_t work_bytes = 0, bool init_status = true) {
   Layout dry;
   layout(dry, m, n, l, prec, basis_store);
   const size_t need = dry.off + 256;
@@ -423,11 +424,13 @@ int ensure_ws(plu_handle h, int64_t m, int64_t n, int64_t l, Ws* out,
     }
   }
   out->capturing = capturing;
-  // per-call status words: zero-pivot slots to "none", flags to 0
-  if (launch_fill_u32(reinterpret_cast<uint32_t*>(out->status), 32, 0x7FFFFFFFu, h->stream) !=
-          hipSuccess ||
-      launch_fill_u32(reinterpret_cast<uint32_t*>(out->status + 32), 32, 0u, h->stream) !=
-          hipSuccess)
+  // per-call status words (read by the LU steps): zero-pivot slots to
+  // "none", flags to 0
+  if (init_status &&
+      (launch_fill_u32(reinterpret_cast<uint32_t*>(out->status), 32, 0x7FFFFFFFu, h->stream) !=
+           hipSuccess ||
+       launch_fill_u32(reinterpret_cast<uint32_t*>(out->status + 32), 32, 0u, h->stream) !=
+           hipSuccess))
     return PLU_ERR_HIP;
   return PLU_OK;
 }
@@ -793,20 +796,17 @@ hipError_t run_pass_bf16(plu_handle h, const Ws& w, int trans, int64_t m, int64_
 hipError_t convert_a_fp8(plu_handle h, const Ws& w, int64_t m, int64_t n, const float* A,
                          int64_t lda, double* normA2_dev) {
   hipError_t e;
+  int64_t np = 0;
+  double* part = normA2_dev ? w.cvt_part : nullptr;
   if (w.acol)   // the storage is A^T: its row-major copy is the transposed one
-    e = launch_cvt_fp8(A, lda, n, m, w.a8t, w.a8ts, w.lda8t, w.a8, w.a8s, w.lda8, m, h->stream);
+    e = launch_cvt_fp8(A, lda, n, m, w.a8t, w.a8ts, w.lda8t, w.a8, w.a8s, w.lda8, m, part, &np,
+                       h->stream);
   else
-    e = launch_cvt_fp8(A, lda, m, n, w.a8, w.a8s, w.lda8, w.a8t, w.a8ts, w.lda8t, n, h->stream);
+    e = launch_cvt_fp8(A, lda, m, n, w.a8, w.a8s, w.lda8, w.a8t, w.a8ts, w.lda8t, n, part, &np,
+                       h->stream);
   if (e != hipSuccess) return e;
-  if (normA2_dev) {
-    const int nb = 1024;
-    if (nb > w.sumsq_cap) return hipErrorInvalidValue;
-    if ((e = w.acol ? launch_sumsq_matrix(A, lda, n, m, w.sumsq_part, nb, h->stream)
-                    : launch_sumsq_matrix(A, lda, m, n, w.sumsq_part, nb, h->stream)) !=
-        hipSuccess)
-      return e;
-    return launch_sum_doubles(w.sumsq_part, nb, normA2_dev, h->stream);
-  }
+  if (np > w.cvt_cap) return hipErrorInvalidValue;
+  if (normA2_dev) return launch_sum_doubles(w.cvt_part, np, normA2_dev, h->stream);
   return hipSuccess;
 }
 
@@ -850,7 +850,8 @@ hipError_t run_pass_fp8(plu_handle h, const Ws& w, int trans, int64_t m, int64_t
   const int64_t ct = ru((int64_t)pl.cblocks * pl.nt * 16, 64);
   if (ct > w.x8_rows || K > w.ldx8 || K > ldm) return hipErrorInvalidValue;
   hipError_t e;
-  if ((e = launch_cvt_fp8(X, ldx, Kl, l, nullptr, nullptr, 0, w.x8, w.x8s, K, ct, h->stream)) !=
+  if ((e = launch_cvt_fp8(X, ldx, Kl, l, nullptr, nullptr, 0, w.x8, w.x8s, K, ct, nullptr,
+                         nullptr, h->stream)) !=
       hipSuccess)
     return e;
   if (pl.nsplit > 1) {
@@ -2164,7 +2165,8 @@ int plu_pass(plu_handle h, int32_t trans, int64_t m, int64_t n, const float* A, 
   if (fmt != PLU_PREC_FP32 && fmt != PLU_PREC_BF16 && fmt != PLU_PREC_FP8_E4M3) return -12;
   PLU_TRY_HIP(hipSetDevice(h->device));
   Ws w;
-  int st = ensure_ws(h, m, n, std::max<int64_t>(l, ru4(ldo)), &w, fmt);
+  // a pass alone runs no LU step: no status words to initialize
+  int st = ensure_ws(h, m, n, std::max<int64_t>(l, ru4(ldo)), &w, fmt, false, nullptr, 0, false);
   if (st) return st;
   if (fmt != PLU_PREC_FP32) {
     PLU_TRY_HIP(lowp_copies(h, w, fmt, m, n, A, lda, (prec & PLU_PREC_A_UNCHANGED) != 0,
@@ -2197,10 +2199,10 @@ int plu_quantize(plu_handle h, int32_t fmt, int64_t rows, int64_t cols, const fl
     uint8_t* sc = reinterpret_cast<uint8_t*>(scales);
     if (transpose)
       PLU_TRY_HIP(launch_cvt_fp8(src, lds, rows, cols, nullptr, nullptr, 0, d, sc, ldd, cols,
-                                 h->stream));
+                                 nullptr, nullptr, h->stream));
     else
       PLU_TRY_HIP(launch_cvt_fp8(src, lds, rows, cols, d, sc, ldd, nullptr, nullptr, 0, 0,
-                                 h->stream));
+                                 nullptr, nullptr, h->stream));
     return PLU_OK;
   }
   uint16_t* d = reinterpret_cast<uint16_t*>(dst);

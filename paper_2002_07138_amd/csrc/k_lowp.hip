@@ -430,12 +430,17 @@ __device__ __forceinline__ uint32_t pack4_e4m3(const float* v, int e) {
 //   rm/rsc (nullable): R x ldr codes and R x ldr/32 scales, blocks of 32
 //     along each row (j), zero codes and scale byte 0 past C;
 //   tr/tsc (nullable): Ct x ldt codes and Ct x ldt/32 scales of src^T,
-//     blocks of 32 along i, zero past R and for rows j >= C.
+//     blocks of 32 along i, zero past R and for rows j >= C;
+// and optionally the float64 sum of squares of src, one partial per
+// workgroup (as k_cvt_bf16).
 __global__ __launch_bounds__(256) void k_cvt_fp8(const float* __restrict__ src, int64_t lds,
                                                  int64_t R, int64_t C, uint8_t* rm, uint8_t* rsc,
                                                  int64_t ldr, uint8_t* tr, uint8_t* tsc,
-                                                 int64_t ldt, int64_t Ct, int64_t ncol_tiles) {
+                                                 int64_t ldt, int64_t Ct, int64_t ncol_tiles,
+                                                 double* sumsq_part) {
   __shared__ float T[64][64 + 1];
+  __shared__ double red[4];
+  double ss = 0.0;
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * 64;
   const int tr_row = tid >> 4, tc4 = (tid & 15) * 4;
@@ -459,7 +464,13 @@ __global__ __launch_bounds__(256) void k_cvt_fp8(const float* __restrict__ src, 
         }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) T[tc4 + e][rr] = v[e];
+      for (int e = 0; e < 4; ++e) {
+        T[tc4 + e][rr] = v[e];
+        if (sumsq_part) {
+          const double d = v[e];
+          ss = fma(d, d, ss);
+        }
+      }
       if (rm) {
         float am = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
         am = max8(am);
@@ -489,6 +500,10 @@ __global__ __launch_bounds__(256) void k_cvt_fp8(const float* __restrict__ src, 
       }
     }
     __syncthreads();
+  }
+  if (sumsq_part) {
+    const double t = wg_sum_double(ss, red);
+    if (tid == 0) sumsq_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -775,21 +790,22 @@ __global__ __launch_bounds__(512, 1) void k_pass_fp8(const uint8_t* __restrict__
 // ceil(NT / 2)) over the whole stage, so no partial sums are exchanged.
 // Loads, swizzle and stage schedule as in the narrow kernels.
 
-// 3 A fragments at a + 4 KB t and 8 sketch fragments at x + 4 KB j.
-__device__ __forceinline__ void lds_read_3_8(uint32_t a, uint32_t x, u32x4v (&ao)[3],
-                                             u32x4v (&xo)[8]) {
+// 3 A fragments at a + 4 KB t and 8 sketch fragments at x + 2 KB j (the
+// sketch half-stage layout: 16 columns of 128 bytes per tile).
+__device__ __forceinline__ void lds_read_3_8h(uint32_t a, uint32_t x, u32x4v (&ao)[3],
+                                              u32x4v (&xo)[8]) {
   asm volatile(
       "ds_read_b128 %0, %11\n\t"
       "ds_read_b128 %1, %11 offset:4096\n\t"
       "ds_read_b128 %2, %11 offset:8192\n\t"
       "ds_read_b128 %3, %12\n\t"
-      "ds_read_b128 %4, %12 offset:4096\n\t"
-      "ds_read_b128 %5, %12 offset:8192\n\t"
-      "ds_read_b128 %6, %12 offset:12288\n\t"
-      "ds_read_b128 %7, %12 offset:16384\n\t"
-      "ds_read_b128 %8, %12 offset:20480\n\t"
-      "ds_read_b128 %9, %12 offset:24576\n\t"
-      "ds_read_b128 %10, %12 offset:28672\n\t"
+      "ds_read_b128 %4, %12 offset:2048\n\t"
+      "ds_read_b128 %5, %12 offset:4096\n\t"
+      "ds_read_b128 %6, %12 offset:6144\n\t"
+      "ds_read_b128 %7, %12 offset:8192\n\t"
+      "ds_read_b128 %8, %12 offset:10240\n\t"
+      "ds_read_b128 %9, %12 offset:12288\n\t"
+      "ds_read_b128 %10, %12 offset:14336\n\t"
       "s_waitcnt lgkmcnt(0)"
       : "=&v"(ao[0]), "=&v"(ao[1]), "=&v"(ao[2]), "=&v"(xo[0]), "=&v"(xo[1]), "=&v"(xo[2]),
         "=&v"(xo[3]), "=&v"(xo[4]), "=&v"(xo[5]), "=&v"(xo[6]), "=&v"(xo[7])
@@ -797,6 +813,13 @@ __device__ __forceinline__ void lds_read_3_8(uint32_t a, uint32_t x, u32x4v (&ao
       : "memory");
 }
 
+// The sketch stage is kept in two half-stages (64 entries of K each, 32 KB
+// for 16 column tiles), reloaded separately: the next stage's first half
+// streams in while the second half is multiplied, and its second half while
+// the next stage's first half is, so the L2 latency of the sketch overlaps
+// the matrix-core work.  A half-stage column is 128 bytes; chunk c (0..7) of
+// column q sits at slot c ^ ((q / 2) mod 8), which keeps the operand reads
+// of 16 columns in 16 distinct bank groups.
 template <int NT, int EPI>
 __global__ __launch_bounds__(512, 1) void k_pass_bf16_wide(const uint16_t* __restrict__ M,
                                                            int64_t ldm,
@@ -807,9 +830,9 @@ __global__ __launch_bounds__(512, 1) void k_pass_bf16_wide(const uint16_t* __res
                                                            int nsplit) {
   static_assert(NT > 8 && NT <= 16, "9 to 16 column tiles");
   constexpr int KS = 128, ROWS = 192, NTH = (NT + 1) / 2;
-  constexpr int BLK = 512;                      // uint16 per 1 KB block (4 rows of a stage)
+  constexpr int BLK = 512;                      // uint16 per 1 KB block
   __shared__ __attribute__((aligned(16))) uint16_t As[2][48 * BLK];
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[64 * BLK];
+  __shared__ __attribute__((aligned(16))) uint16_t Xh[2][32 * BLK];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g4 = lane >> 4;
@@ -826,7 +849,7 @@ __global__ __launch_bounds__(512, 1) void k_pass_bf16_wide(const uint16_t* __res
   const int nst = kb < ke ? (int)((ke - kb) / KS) : 0;
 
   // A: load t (0..5) of wave w moves rows 24 w + 4 t + l / 16 into block
-  // 6 w + t; sketch: block q = 8 w + i (q < 4 NT), columns 4 q + l / 16
+  // 6 w + t (256 bytes per row, chunk (l % 16) ^ (row mod 16) at slot l % 16)
   const uint16_t* aa[6];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
@@ -835,17 +858,23 @@ __global__ __launch_bounds__(512, 1) void k_pass_bf16_wide(const uint16_t* __res
     const int64_t ra = p0 + row;
     aa[t] = M + (ra < P ? ra : P - 1) * ldm + kb + ((r ^ rho) * 8);
   }
-  const uint16_t* xs[8];
+  // sketch half-stage: block b = 4 w + i (0..31) holds columns 8 b .. 8 b + 7,
+  // lane l column 8 b + l / 8 at slot l % 8; columns past 16 NT load column
+  // 0 (into slots never read), so every wave issues 4 loads per half
+  const uint16_t* xs[4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int q = wave * 8 + i;
-    const int rho = 4 * (q & 3) + g4;
-    xs[i] = Xt + (c0 + 4 * (q < 4 * NT ? q : 0) + g4) * ldx + kb + ((r ^ rho) * 8);
+  for (int i = 0; i < 4; ++i) {
+    const int col = 8 * (4 * wave + i) + (lane >> 3);
+    const int slot = lane & 7;
+    const int chunk = slot ^ ((col >> 1) & 7);
+    xs[i] = Xt + (c0 + (col < 16 * NT ? col : 0)) * ldx + kb + chunk * 8;
   }
   const int grp = wave >> 1, half = wave & 1;
-  uint32_t off[4];
+  uint32_t off[4], xoff[2];
 #pragma unroll
   for (int h = 0; h < 4; ++h) off[h] = (uint32_t)(r * 256 + (((4 * h + g4) ^ r) * 16));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) xoff[h] = (uint32_t)(r * 128 + (((4 * h + g4) ^ ((r >> 1) & 7)) * 16));
 
   f32x4 acc[3][NTH];
 #pragma unroll
@@ -861,46 +890,59 @@ __global__ __launch_bounds__(512, 1) void k_pass_bf16_wide(const uint16_t* __res
       aa[t] += KS;
     }
   };
-  auto issue_x = [&]() __attribute__((always_inline)) {
+  // half-stage hx (0, 1) of the next sketch stage; the pointers advance a
+  // stage after the second half
+  auto issue_x = [&](int hx) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (wave * 8 + i < 4 * NT) {
-        __builtin_amdgcn_global_load_lds(xs[i], Xs + (wave * 8 + i) * BLK, 16, 0, 0);
-        xs[i] += KS;
-      }
+    for (int i = 0; i < 4; ++i)
+      __builtin_amdgcn_global_load_lds(xs[i] + hx * 64, Xh[hx] + (wave * 4 + i) * BLK, 16, 0, 0);
+    if (hx == 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xs[i] += KS;
+    }
   };
-  auto compute = [&](int b) __attribute__((always_inline)) {
+  // the two 32-deep steps of half-stage hx
+  auto compute = [&](int b, int hx) __attribute__((always_inline)) {
     const uint32_t abase = lds_off(As[b]) + (uint32_t)(grp * 3 * 4096);
-    const uint32_t xbase = lds_off(Xs) + (uint32_t)(half * NTH * 4096);
+    const uint32_t xbase = lds_off(Xh[hx]) + (uint32_t)(half * NTH * 2048);
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
+    for (int h = 0; h < 2; ++h) {
       u32x4v ao[3], xo[8];
-      lds_read_3_8(abase + off[h], xbase + off[h], ao, xo);
+      lds_read_3_8h(abase + off[2 * hx + h], xbase + xoff[h], ao, xo);
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const bf16x8 f = __builtin_bit_cast(bf16x8, ao[t]);
 #pragma unroll
         for (int j = 0; j < NTH; ++j)
-          if (half * NTH + j < NT)
-            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                f, __builtin_bit_cast(bf16x8, xo[j]), acc[t][j], 0, 0, 0);
+          acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              f, __builtin_bit_cast(bf16x8, xo[j]), acc[t][j], 0, 0, 0);
       }
 #pragma unroll
       for (int j = NTH; j < 8; ++j) asm volatile("" ::"v"(xo[j]));
     }
   };
+  // issue order per wave: ... [X(s) half 1, A(s+1)] [X(s+1) half 0]
+  // [X(s+1) half 1, A(s+2)] ...; loads complete in order, so at the top of
+  // stage s (A(s) and X(s) half 0 needed) X(s) half 1 and A(s + 1) may be
+  // outstanding, and before its second half only A(s + 1)
   if (nst > 0) {
     issue_a(0);
-    issue_x();
+    issue_x(0);
+    issue_x(1);
   }
   if (nst > 1) issue_a(1);
   for (int s = 0; s < nst; ++s) {
+    if (s + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F7A);   // vmcnt(10)
+    else __builtin_amdgcn_s_waitcnt(0x0F74);               // vmcnt(4)
+    __builtin_amdgcn_s_barrier();
+    compute(s & 1, 0);
     if (s + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
     else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
     __builtin_amdgcn_s_barrier();
-    compute(s & 1);
+    if (s + 1 < nst) issue_x(0);
+    compute(s & 1, 1);
     __builtin_amdgcn_s_barrier();
-    if (s + 1 < nst) issue_x();
+    if (s + 1 < nst) issue_x(1);
     if (s + 2 < nst) issue_a(s & 1);
   }
 
@@ -1219,7 +1261,7 @@ hipError_t launch_cvt_bf16(const float* src, int64_t lds, int64_t R, int64_t C, 
 
 hipError_t launch_cvt_fp8(const float* src, int64_t lds, int64_t R, int64_t C, uint8_t* rm,
                           uint8_t* rsc, int64_t ldr, uint8_t* tr, uint8_t* tsc, int64_t ldt,
-                          int64_t Ct, hipStream_t s) {
+                          int64_t Ct, double* sumsq_part, int64_t* nparts, hipStream_t s) {
   if ((rm && (ldr % 128 != 0 || ldr < C || !rsc)) ||
       (tr && (ldt % 128 != 0 || ldt < R || Ct < C || !tsc)))
     return hipErrorInvalidValue;
@@ -1227,8 +1269,9 @@ hipError_t launch_cvt_fp8(const float* src, int64_t lds, int64_t R, int64_t C, u
   const int64_t cols = std::max<int64_t>(rm ? ldr : 0, tr ? Ct : 0);
   const int64_t bands = (rows + 63) / 64, ctiles = (cols + 63) / 64;
   const int groups = (int)std::min<int64_t>(ctiles, 8);
+  if (nparts) *nparts = bands * groups;
   hipLaunchKernelGGL(k_cvt_fp8, dim3((unsigned)groups, (unsigned)bands), dim3(256), 0, s, src,
-                     lds, R, C, rm, rsc, ldr, tr, tsc, ldt, Ct, ctiles);
+                     lds, R, C, rm, rsc, ldr, tr, tsc, ldt, Ct, ctiles, sumsq_part);
   return hipGetLastError();
 }
 

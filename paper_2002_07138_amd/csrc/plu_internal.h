@@ -94,11 +94,16 @@ hipError_t launch_cvt_bf16(const float* src, int64_t lds, int64_t R, int64_t C, 
 // Block-scaled FP8 E4M3 copies (blocks of 32 along the contraction index,
 // E8M0 scale bytes): rm/rsc row-major R x ldr (+ R x ldr/32 scales),
 // tr/tsc transposed Ct x ldt (+ Ct x ldt/32); ldr, ldt multiples of 128.
+// sumsq_part (nullable): float64 partial sums of squares of src, *nparts of
+// them (as launch_cvt_bf16).
 hipError_t launch_cvt_fp8(const float* src, int64_t lds, int64_t R, int64_t C, uint8_t* rm,
                           uint8_t* rsc, int64_t ldr, uint8_t* tr, uint8_t* tsc, int64_t ldt,
-                          int64_t Ct, hipStream_t s);
-// out = sum_k dequant(M)[p][k] dequant(Xt)[c][k] on the scaled FP8 MFMA
-// (K a multiple of 128; plan from plan_gemm(P, K, C, ..., 128)).
+                          int64_t Ct, double* sumsq_part, int64_t* nparts, hipStream_t s);
+// out = sum_k dequant(M)[p][k] dequant(Xt)[c][k] on the scaled FP8 MFMA, A
+// and the sketch staged through LDS by direct loads: workgroups of 512
+// threads and 192 rows (pl.pblocks counts those, from plan_lowp), K and
+// pl.rsplit multiples of 256, leading dimensions multiples of 256, pl.nt
+// <= 14 (above 8 the wide kernel); epi EPI_STORE or EPI_PART.
 hipError_t launch_pass_fp8(int epi, const uint8_t* M, const uint8_t* Ms, int64_t ldm,
                            const uint8_t* Xt, const uint8_t* Xsc, int64_t ldx, float* out,
                            int64_t ldo, int64_t part_stride, int64_t P, int64_t K, int64_t C,
