@@ -363,9 +363,11 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
  * cooperative batched launch.  Each problem's result is bit-identical to the
  * single-problem call with the same arguments.
  *   A, Omega, p, q, L, U   device pointers as in the single calls.
- *   prec                   PLU_PREC_FP32 only (the batched path has no
- *                          rounded copies); others give status
- *                          PLU_ERR_NOT_IMPLEMENTED.
+ *   prec                   any form of the single calls except
+ *                          PLU_PREC_FP64_INDICATOR (status
+ *                          PLU_ERR_NOT_IMPLEMENTED).  A rounded form makes
+ *                          the problem's copies of A in its own workspace
+ *                          on every call (PLU_PREC_A_UNCHANGED is ignored).
  * Outputs (host, in each request): rank, status and info; the call
  * synchronizes once, at the end (the fixed-precision ranks stay on the
  * device until then, as in plu_fixed_precision).
@@ -375,12 +377,15 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
  * latency-bound steps (the LU panels, the thin QR) overlap other problems'
  * passes over A.  A stream with one problem launches its kernels as the
  * single call does; a stream with several merges their launch sequences into
- * grouped launches.  Results are bitwise those of the single calls either way.
+ * grouped launches, unless one of them is in a rounded form: that stream runs
+ * its problems one after the other as single calls.  Results are bitwise
+ * those of the single calls either way.
  * flags: PLU_BATCH_GRAPH captures the batch's launches (fixed-rank and
  * fixed-precision problems alike, every stream) into a HIP graph kept by the
  * handle and replays it when the next call has the same requests (same
  * shapes and pointers).  PLU_BATCH_ONE_STREAM keeps every problem on the
- * handle's stream, in one merged launch sequence.
+ * handle's stream, in one merged launch sequence (one after the other when
+ * some problem is in a rounded form).
  * Returns PLU_OK, or -3 when some request is invalid (its status then holds
  * -i for its i-th field, counted from 1 in declaration order).             */
 /* ---- Pivot trace: the pivot rows and relative pivot gaps of every GETRF of

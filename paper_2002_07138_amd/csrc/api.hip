@@ -1183,6 +1183,8 @@ int check_request(const plu_request& r, int64_t* l_out) {
 struct BatchProblem {
   plu_request* r = nullptr;
   int64_t l = 0;
+  int prec = PLU_PREC_FP32;   // the request's precision form (its rounded
+                              // copies are made in the problem's workspace)
   size_t off = 0, bytes = 0;
   plu_handle_s hs;
   Ws w{};
@@ -1199,11 +1201,11 @@ hipError_t batch_phase_a(BatchProblem& b) {
   plu_request& r = *b.r;
   plu_handle hs = &b.hs;
   hipError_t e;
-  int st = ensure_ws(hs, r.m, r.n, b.l, &b.w);
+  int st = ensure_ws(hs, r.m, r.n, b.l, &b.w, b.prec);
   if (st) return hipErrorOutOfMemory;
   b.w.acol = r.layout == PLU_COL_MAJOR;
   if ((e = range_basis(hs, b.w, r.m, r.n, r.A, r.lda, (int)b.l, r.v, r.Omega, r.seed, &b.V,
-                       &b.np)) != hipSuccess)
+                       &b.np, b.prec)) != hipSuccess)
     return e;
   if (r.mode == 0) {
     if ((e = run_pass(hs, b.w, 0, r.m, r.n, r.A, r.lda, b.V, b.w.lp, r.k, b.w.ym, b.w.lp, nullptr,
@@ -1263,15 +1265,23 @@ hipError_t ensure_side_streams(plu_handle h) {
 // the caller's stream (and joined back into it): the longest problem first,
 // each to the least loaded stream (work estimated as m n l v).  A stream with
 // one problem launches its kernels directly; a stream with several runs their
-// merged launch sequence.  The LU panels' workgroups wait on each other, so
-// the merged panels of one stream are held to cu_count / streams workgroups
-// at a time, and a direct problem's panel has at most 64: the panels in
-// flight at once always fit on the device.
+// merged launch sequence, unless one of them is in a rounded precision form:
+// the reduced-precision kernels are launched directly (they are not recorded
+// for merging), so such a stream runs its problems directly, one after the
+// other.  The LU panels' workgroups wait on each other, so the merged panels
+// of one stream are held to cu_count / streams workgroups at a time, and a
+// direct problem's panel has at most 64: the panels in flight at once always
+// fit on the device.
 struct SidePlan {
   int S = 0;
   std::vector<std::vector<BatchProblem*>> groups;
   std::vector<std::vector<const Recorder*>> lists;
+  std::vector<char> direct;
 };
+
+bool rounded_form(const BatchProblem* b) {
+  return (b->prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32;
+}
 
 // Partition, recording of the merged streams' launches, and (for a graph
 // capture, which may allocate nothing) their table buffers: all before any
@@ -1295,8 +1305,12 @@ hipError_t side_prepare(plu_handle h, std::vector<BatchProblem*>& all, bool capt
     sp.groups[g].push_back(b);
     load[g] += work(b);
   }
+  sp.direct.assign((size_t)sp.S, 0);
   for (int g = 0; g < sp.S; ++g) {
-    if (sp.groups[(size_t)g].size() < 2) continue;
+    const auto& grp = sp.groups[(size_t)g];
+    sp.direct[(size_t)g] =
+        grp.size() < 2 || std::any_of(grp.begin(), grp.end(), rounded_form) ? 1 : 0;
+    if (sp.direct[(size_t)g]) continue;
     for (BatchProblem* b : sp.groups[(size_t)g]) {
       b->rec.ops.clear();
       thread_recorder() = &b->rec;
@@ -1322,10 +1336,11 @@ hipError_t side_launch(plu_handle h, hipStream_t s, SidePlan& sp, bool capture) 
   for (int g = 0; g < sp.S; ++g)
     if ((e = hipStreamWaitEvent(h->side[g], h->fork_ev, 0)) != hipSuccess) return e;
   for (int g = 0; g < sp.S; ++g) {
-    if (sp.groups[(size_t)g].size() == 1) {
-      BatchProblem& b = *sp.groups[(size_t)g][0];
-      b.hs.stream = h->side[g];
-      if ((e = batch_phase_a(b)) != hipSuccess) return e;
+    if (sp.direct[(size_t)g]) {
+      for (BatchProblem* b : sp.groups[(size_t)g]) {
+        b->hs.stream = h->side[g];
+        if ((e = batch_phase_a(*b)) != hipSuccess) return e;
+      }
     } else {
       MergeBuffers& buf = capture ? h->sgbuf[g] : h->sbuf[g];
       buf.capturing = capture;
@@ -3001,7 +3016,7 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       bad = true;
       continue;
     }
-    if ((r.prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32 || (r.prec & PLU_PREC_FP64_INDICATOR)) {
+    if (r.prec & PLU_PREC_FP64_INDICATOR) {
       r.status = PLU_ERR_NOT_IMPLEMENTED;
       bad = true;
       continue;
@@ -3009,8 +3024,11 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
     BatchProblem& b = probs[(size_t)i];
     b.r = &r;
     b.l = l;
+    // each problem rounds its own A into its own workspace on every call
+    // (a batch keeps no copies between calls: PLU_PREC_A_UNCHANGED is moot)
+    b.prec = r.prec & ~PLU_PREC_A_UNCHANGED;
     Layout dry;
-    layout(dry, r.m, r.n, l);
+    layout(dry, r.m, r.n, l, b.prec);
     b.bytes = ru((int64_t)(dry.off + 256), 256);
     b.off = total;
     total += b.bytes;
@@ -3048,7 +3066,7 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       const plu_request& r = *b.r;
       Layout L;
       L.base = h->batch_arena + b.off;
-      Ws w = layout(L, r.m, r.n, b.l);
+      Ws w = layout(L, r.m, r.n, b.l, b.prec);
       w.acol = r.layout == PLU_COL_MAJOR;
       pretune_pass(h, w, 0, r.m, r.n, r.A, r.lda, w.om, w.lp, b.l, w.ym, w.lp);
       pretune_pass(h, w, 1, r.m, r.n, r.A, r.lda, w.om, w.lp, b.l, w.zn, w.lp);
@@ -3101,6 +3119,41 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags) {
       hipError_t e = side_prepare(h, all, false, sp);
       if (e == hipSuccess) e = side_launch(h, h->stream, sp, false);
       if (e != hipSuccess) return e == hipErrorOutOfMemory ? PLU_ERR_OOM : PLU_ERR_HIP;
+    } else if (std::any_of(all.begin(), all.end(), rounded_form)) {
+      // one stream with a rounded-form problem: every problem directly, one
+      // after the other (captured as they are launched for a graph)
+      hipStream_t s = h->stream;
+      if (use_graph) {
+        drop_graph(h);
+        if (!h->gstream) PLU_TRY_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        s = h->gstream;
+        PLU_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      }
+      hipError_t ce = hipSuccess;
+      for (BatchProblem* b : all) {
+        b->hs.stream = s;
+        if ((ce = batch_phase_a(*b)) != hipSuccess) break;
+      }
+      if (use_graph) {
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(s, &g);
+        if (ce != hipSuccess || ee != hipSuccess || !g) {
+          if (g) (void)hipGraphDestroy(g);
+          (void)hipGetLastError();
+          std::fprintf(stderr, "libpowerlu: batch graph capture failed: %s / %s\n",
+                       hipGetErrorString(ce), hipGetErrorString(ee));
+          if (ce == hipErrorOutOfMemory) return PLU_ERR_OOM;
+          return ce == hipErrorStreamCaptureUnsupported || ee == hipErrorStreamCaptureUnsupported
+                     ? PLU_ERR_NOT_IMPLEMENTED
+                     : PLU_ERR_HIP;
+        }
+        h->graph = g;
+        PLU_TRY_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+        h->gsig = sig;
+        PLU_TRY_HIP(hipGraphLaunch(h->gexec, h->stream));
+      } else if (ce != hipSuccess) {
+        return ce == hipErrorOutOfMemory ? PLU_ERR_OOM : PLU_ERR_HIP;
+      }
     } else if (use_graph) {
       drop_graph(h);
       // record, size the tables outside the capture, then capture the launches
@@ -3146,7 +3199,7 @@ finish:
     Layout L;
     L.base = h->batch_arena + probs[(size_t)i].off;
     int64_t l = probs[(size_t)i].l;
-    const Ws w = layout(L, r.m, r.n, l);
+    const Ws w = layout(L, r.m, r.n, l, probs[(size_t)i].prec);
     if (r.mode == 0) {
       r.rank = r.k;
       r.status = finish_info(h, w, PLU_OK, r.k, r.v, (int)l, false, &r.info);

@@ -1,7 +1,7 @@
 """Batched problems (plu_batched): many fixed-rank and fixed-precision
-problems of uneven shapes, side by side on the handle's streams (a stream
-with several problems merges them into grouped launches), or all merged on
-one stream (one_stream).  Every problem runs
+problems of uneven shapes, in FP32 or a precision form, side by side on the
+handle's streams (a stream with several FP32 problems merges them into
+grouped launches), or all on one stream (one_stream).  Every problem runs
 the same kernels on the same data as its single-problem call, so each result
 must be bit-identical to that call; the single-problem path is itself
 checked against the oracle by the other GPU tests, and one problem here is
@@ -47,10 +47,22 @@ def _problems(seed):
 
 
 def _single(h, pr):
+    prec = pr.get("prec", 0)
     if pr["mode"] == 0:
-        return h.fixed_rank(pr["A"], pr["k"], pr["p_over"], pr["v"], seed=pr["seed"])
+        return h.fixed_rank(pr["A"], pr["k"], pr["p_over"], pr["v"], seed=pr["seed"], prec=prec)
     return h.fixed_precision(pr["A"], pr["eps"], pr["b"], l=pr["l"], v=pr["v"],
-                             column_exact=pr["column_exact"], seed=pr["seed"])
+                             column_exact=pr["column_exact"], seed=pr["seed"], prec=prec)
+
+
+# the precision forms cycled over a batch: FP32, BF16, FP8, BF16 with the last
+# rounded pass exact, FP8 with the last two exact
+_FORMS = [0, 1, 2, 1 | 16, 2 | 32]
+
+
+def _with_forms(probs):
+    for i, pr in enumerate(probs):
+        pr["prec"] = _FORMS[i % len(_FORMS)]
+    return probs
 
 
 def _same(f, g):
@@ -71,6 +83,39 @@ def test_batch_matches_single_calls_bitwise(h, one_stream, count):
         _same(f, g)
         assert f.info["passes"] == pr["v"]
         assert f.info["status"] in (0, 1, 2)
+
+
+@pytest.mark.parametrize("one_stream", [False, True])
+@pytest.mark.parametrize("count", [4, 8])
+def test_batch_precision_forms_match_single_calls_bitwise(h, one_stream, count):
+    """Problems in the precision forms (BF16 / FP8 passes, with and without
+    exact trailing passes) mixed with FP32 ones: each rounds its own A in
+    its own workspace and runs the reduced-precision kernels directly on its
+    stream (count 8: streams holding a rounded-form problem run their
+    problems one after the other; FP32-only streams merge), so every result
+    equals its single call bitwise."""
+    probs = _with_forms(_problems(4)[:count])
+    singles = [_single(h, pr) for pr in probs]
+    outs = h.batched(probs, one_stream=one_stream)
+    for pr, f, g in zip(probs, outs, singles):
+        _same(f, g)
+        assert f.info["passes"] == pr["v"]
+
+
+@pytest.mark.parametrize("one_stream", [False, True])
+def test_batch_precision_forms_graph_replays(h, one_stream):
+    """A batch with precision-form problems captured into a HIP graph and
+    replayed (eager work and synchronizations between the replays): every
+    replay equals the single calls."""
+    probs = _with_forms(_problems(5)[:5])
+    singles = [_single(h, pr) for pr in probs]
+    for rep in range(3):
+        outs = h.batched(probs, graph=True, one_stream=one_stream)
+        for f, g in zip(outs, singles):
+            _same(f, g)
+        x = torch.randn(1000, 1000, device="cuda:0")
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
 
 
 def test_batch_problem_matches_oracle(h):
@@ -120,6 +165,10 @@ def test_batch_rejects_invalid_request(h):
     A = dev(np.ones((100, 80), dtype=np.float32))
     with pytest.raises(plu.PowerLUError):
         h.batched([dict(A=A, mode=0, k=70, p_over=20, v=3)])
+    # the float64 indicator has no batched form
+    B = dev(np.ones((300, 280), dtype=np.float32))
+    with pytest.raises(plu.PowerLUError):
+        h.batched([dict(A=B, mode=1, eps=1e-3, b=8, l=80, v=4, prec=128)])
 
 
 @pytest.mark.parametrize("one_stream", [False, True])
