@@ -443,7 +443,9 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags);
  * iteration first admits what arrived, then advances all admitted problems
  * through a bounded number of grouped launches (the merged launch sequence
  * of plu_batched), so a request that arrives while others run joins them at
- * the next iteration.  Results are bit-identical to the single calls.
+ * the next iteration.  A request in a rounded precision form is not merged:
+ * all its launches go out on its lane at its first issue (its kernels are
+ * launched directly).  Results are bit-identical to the single calls.
  *   plu_server_create   hbm_budget_bytes: device memory the server may use;
  *                       max_slots: problems admitted at once (>= 1).
  *   plu_server_submit   req: as for plu_batched, but A, p, q, L, U are HOST
@@ -453,7 +455,8 @@ int plu_batched(plu_handle h, int32_t count, plu_request* reqs, int32_t flags);
  *                       rank columns of L with leading dimension ldl and
  *                       rows of U with ldu).  Never blocks.  Returns -i for
  *                       an invalid field i, PLU_ERR_OOM when the request
- *                       alone exceeds the budget.
+ *                       alone exceeds the budget, PLU_ERR_NOT_IMPLEMENTED
+ *                       for PLU_PREC_FP64_INDICATOR.
  *   plu_server_poll     PLU_PENDING, or PLU_OK with *res filled.
  *   plu_server_wait     blocks until the ticket completes.
  *   plu_server_destroy  finishes all submitted work, then frees.

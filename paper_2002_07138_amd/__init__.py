@@ -690,10 +690,11 @@ class Server:
         return x.ctypes.data
 
     def submit(self, A, mode=0, k=0, p_over=0, v=4, eps=0.0, b=1, l=0, column_exact=True,
-               seed=0, out=None):
+               seed=0, out=None, prec=PREC_FP32):
         """A: host fp32 m x n, rows or columns contiguous.  out: optional
         (p, q, L, U) host arrays (int32 m, int32 n, fp32 m x cap, fp32 cap x n);
-        allocated (numpy) when omitted.  Returns the ticket."""
+        allocated (numpy) when omitted.  prec: as for the single calls (not
+        PREC_FP64_INDICATOR).  Returns the ticket."""
         import numpy as np
         m, n = A.shape
         cap = k if mode == 0 else (l if l else min(50 * b, b * ((min(m, n) - 1) // b)))
@@ -711,7 +712,7 @@ class Server:
         r.layout, r.lda = _a_layout((m, n), strides)
         r.A = self._hptr(A)
         r.k, r.p_over, r.v, r.b, r.l, r.eps = k, p_over, v, b, l, float(eps)
-        r.prec, r.Omega, r.seed = PREC_FP32, None, seed
+        r.prec, r.Omega, r.seed = int(prec), None, seed
         r.p, r.q, r.L, r.U = self._hptr(p), self._hptr(q), self._hptr(L), self._hptr(U)
         r.ldl = max(cap, 1)
         r.ldu = n

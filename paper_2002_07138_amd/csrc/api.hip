@@ -1435,6 +1435,8 @@ struct ServerJob {
   double t_up = 0, t_issued = 0, t_computed = 0;   // server-side timestamps
   int lane = 0;                // the stream its launches go to
   double work = 0;             // m n l v: its share of that lane's load
+  bool direct = false;         // a rounded precision form: not recorded; all
+                               // its launches go out at its first issue
   plu_result res{};
 };
 
@@ -1453,7 +1455,7 @@ int64_t a_span_elems(const plu_request& r) {
 
 size_t server_footprint(const plu_request& r, int64_t l, int64_t cap, size_t* ws_bytes) {
   Layout dry;
-  layout(dry, r.m, r.n, l);
+  layout(dry, r.m, r.n, l, r.prec & ~PLU_PREC_A_UNCHANGED);
   *ws_bytes = (size_t)ru((int64_t)(dry.off + 256), 256);
   auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
   const int64_t span = a_span_elems(r);
@@ -1730,6 +1732,9 @@ void server_loop(plu_server S) {
       int64_t l = 0;
       (void)check_request(d, &l);
       bp.l = l;
+      // a rounded form makes its copies of A in its own workspace each time
+      bp.prec = d.prec & ~PLU_PREC_A_UNCHANGED;
+      j->direct = rounded_form(&bp);
       j->work = (double)d.m * (double)d.n * (double)l * (double)d.v;
       j->lane = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       load[(size_t)j->lane] += j->work;
@@ -1738,7 +1743,7 @@ void server_loop(plu_server S) {
         // once A has landed), so the recorded launches equal the single calls
         Layout L;
         L.base = ws;
-        Ws w = layout(L, d.m, d.n, l);
+        Ws w = layout(L, d.m, d.n, l, bp.prec);
         w.acol = d.layout == PLU_COL_MAJOR;
         // (only a size class not tuned yet waits for the copy of A)
         if (pass_needs_tuning(&bp.hs, w, 0, d.m, d.n, l) ||
@@ -1752,9 +1757,12 @@ void server_loop(plu_server S) {
         }
       }
       bp.rec.ops.clear();
-      thread_recorder() = &bp.rec;
-      hipError_t e = batch_phase_a(bp);
-      thread_recorder() = nullptr;
+      hipError_t e = hipSuccess;
+      if (!j->direct) {
+        thread_recorder() = &bp.rec;
+        e = batch_phase_a(bp);
+        thread_recorder() = nullptr;
+      }
       j->head = 0;
       j->waiting = false;
       if (e != hipSuccess) j->res.status = PLU_ERR_HIP;
@@ -1766,23 +1774,40 @@ void server_loop(plu_server S) {
     for (int ln = 0; ln < kLanes; ++ln) {
       std::vector<const Recorder*> lists;
       std::vector<size_t> heads;
-      std::vector<ServerJob*> js;
+      std::vector<ServerJob*> js, direct;
       for (auto& up : S->active)
         if (up->lane == ln && ready(up.get())) {
+          if (up->direct) {
+            direct.push_back(up.get());
+            continue;
+          }
           lists.push_back(&up->bp.rec);
           heads.push_back(up->head);
           js.push_back(up.get());
         }
-      if (js.empty()) continue;
+      if (js.empty() && direct.empty()) continue;
       issued = true;
       const hipStream_t ls = lane_stream(ln);
       // bound the lane's queue: wait for its batch before last
       while (inflight[ln].size() >= 2) retire(ln, true);
       const auto ti = std::chrono::steady_clock::now();
-      hipError_t e = run_merged_steps(lists, heads, ls, h->cu_count / kLanes, kGroupsPerIter,
-                                      h->sbuf[ln], &S->stats);
+      hipError_t e = hipSuccess;
+      // rounded-form problems: every launch of the single call, in order, on
+      // the lane's stream (their kernels are not recorded for merging)
+      for (ServerJob* j : direct) {
+        j->bp.hs.stream = ls;
+        if ((e = batch_phase_a(j->bp)) != hipSuccess) break;
+      }
+      if (e == hipSuccess && !js.empty())
+        e = run_merged_steps(lists, heads, ls, h->cu_count / kLanes, kGroupsPerIter, h->sbuf[ln],
+                             &S->stats);
       // problems with all steps issued: queue the copies of their small
       // results behind them, so that the event below covers those too
+      for (ServerJob* j : direct) {
+        if (e != hipSuccess || !S->stage[j->slot]) continue;
+        const int nst = j->dev.mode == 0 ? j->dev.k : (int)j->bp.l;
+        e = stage_info(j->bp.w, nst, S->stage[j->slot], ls);
+      }
       for (size_t i = 0; i < js.size() && e == hipSuccess; ++i) {
         ServerJob* j = js[i];
         if (heads[i] < j->bp.rec.ops.size() || !S->stage[j->slot]) continue;
@@ -1792,7 +1817,7 @@ void server_loop(plu_server S) {
       }
       S->t_issue += std::chrono::duration<double>(std::chrono::steady_clock::now() - ti).count();
       ++S->batches;
-      S->sum_ready += js.size();
+      S->sum_ready += js.size() + direct.size();
       S->sum_active += S->active.size();
       {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -1806,6 +1831,11 @@ void server_loop(plu_server S) {
         S->fatal = PLU_ERR_HIP;
       }
       inflight[ln].push_back({++seq[ln], ev});
+      for (ServerJob* j : direct) {
+        j->waiting = true;
+        j->done_seq = seq[ln];
+        j->t_issued = now_s(S->t0);
+      }
       for (size_t i = 0; i < js.size(); ++i) {
         js[i]->head = heads[i];
         if (js[i]->head >= js[i]->bp.rec.ops.size()) {
@@ -3272,8 +3302,7 @@ int plu_server_submit(plu_server S, const plu_request* req, uint64_t* ticket) {
   int64_t l = 0;
   const int c = check_request(*req, &l);
   if (c) return c;
-  if ((req->prec & PLU_PREC_FORMAT_MASK) != PLU_PREC_FP32 || (req->prec & PLU_PREC_FP64_INDICATOR))
-    return PLU_ERR_NOT_IMPLEMENTED;
+  if (req->prec & PLU_PREC_FP64_INDICATOR) return PLU_ERR_NOT_IMPLEMENTED;
   auto j = std::make_unique<ServerJob>();
   j->host = *req;
   j->cap = req->mode == 0 ? req->k : l;

@@ -34,10 +34,12 @@ def _requests(seed, count):
 
 def _alone(h, rq):
     A = dev(rq["A"])
+    prec = rq.get("prec", 0)
     if rq["mode"] == 0:
-        f = h.fixed_rank(A, rq["k"], rq["p_over"], rq["v"], seed=rq["seed"])
+        f = h.fixed_rank(A, rq["k"], rq["p_over"], rq["v"], seed=rq["seed"], prec=prec)
     else:
-        f = h.fixed_precision(A, rq["eps"], rq["b"], l=rq["l"], v=rq["v"], seed=rq["seed"])
+        f = h.fixed_precision(A, rq["eps"], rq["b"], l=rq["l"], v=rq["v"], seed=rq["seed"],
+                              prec=prec)
     return f
 
 
@@ -82,6 +84,41 @@ def test_server_mix_equals_alone():
         _check_same(res, f)
     # latencies are measured from submission
     assert all(r["t_done"] >= r["t_admit"] >= r["t_submit"] for r in results)
+
+
+def test_server_precision_forms_equal_alone():
+    """Requests in the precision forms (BF16 / FP8 passes, with and without
+    exact trailing passes) mixed with FP32 ones: a rounded-form request is
+    issued whole on its lane (not merged), and every result equals the
+    single call in the same form, bit for bit."""
+    import paper_2002_07138_amd as plu
+    forms = [1, 0, 2, 1 | 16, 2 | 32, 0, 1, 2]
+    reqs = _requests(14, len(forms))
+    for rq, f in zip(reqs, forms):
+        rq["prec"] = f
+    h = handle()
+    alone = [_alone(h, rq) for rq in reqs]
+    h.close()
+    srv = plu.Server(0, hbm_budget_bytes=4 << 30, max_slots=16)
+    tickets = []
+    for i, rq in enumerate(reqs):
+        tickets.append(_submit(srv, rq))
+        if i % 3 == 2:
+            time.sleep(0.002)
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for res, f in zip(results, alone):
+        _check_same(res, f)
+
+
+def test_server_rejects_fp64_indicator():
+    import paper_2002_07138_amd as plu
+    rq = _requests(15, 2)[1]
+    srv = plu.Server(0, hbm_budget_bytes=1 << 30, max_slots=2)
+    with pytest.raises(plu.PowerLUError) as e:
+        _submit(srv, dict(rq, prec=128))
+    srv.close()
+    assert e.value.code == plu.PLU_ERR_NOT_IMPLEMENTED
 
 
 def test_server_admission_by_budget():
