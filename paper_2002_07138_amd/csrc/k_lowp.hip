@@ -1,5 +1,6 @@
 // Precision form of the passes over A: reduced-precision copies of A and of
-// the sketch, and the pass kernel on the bfloat16 matrix cores.
+// the sketch, and the pass kernels on the bfloat16 and scaled FP8 matrix
+// cores.
 //
 // The v - 1 passes of Alg. 7 (Sec. 3.4) run on rounded operands with fp32
 // accumulation; the final product with A (Alg. 5 step 3, Alg. 9 step 2) stays
@@ -7,9 +8,10 @@
 //
 // Both operands of a pass are read with the contraction index contiguous:
 // A is kept twice, row-major (for A X) and transposed (for A^T Y), and the
-// sketch X (K x l) is stored transposed (l x K).  Every copy is zero-padded to
-// a multiple of 64 along the contraction index, and the sketch to whole
-// column tiles, so the pass kernel has no bounds checks along K.
+// sketch X (K x l) is stored transposed (l x K).  Every copy is zero-padded
+// along the contraction index to whole stages of the pass kernel (128
+// entries for bfloat16, 256 for FP8), and the sketch to whole column tiles,
+// so the pass kernels have no bounds checks along K.
 #include "plu_internal.h"
 
 #include <algorithm>
