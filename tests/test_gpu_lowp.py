@@ -240,7 +240,12 @@ def test_pass_fp8_matches_rounded_product(h, m, n, l, trans):
     rng = np.random.default_rng(m * 5 + n + l + 2)
     A = (rng.standard_normal((m, n)) * np.exp(rng.uniform(-3, 3, (m, 1)))).astype(np.float32)
     X = rng.standard_normal((m if trans else n, l)).astype(np.float32)
-    out = host(h.pass_(dev(A), dev(X), trans=trans, prec=FP8))
+    nA2 = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    out = host(h.pass_(dev(A), dev(X), trans=trans, prec=FP8, normA2=nA2))
+    # ||A||_F^2 accumulated in float64 by the conversion kernel from the
+    # float32 values it reads
+    nref = np.sum(A.astype(np.float64) ** 2)
+    assert abs(float(nA2.cpu()) - nref) <= 1e-12 * nref
     Ar = LP.round_mx_e4m3(A, 0 if trans else 1)
     Xr = LP.round_mx_e4m3(X, 0)
     ref = (Ar.T if trans else Ar) @ Xr
