@@ -106,7 +106,7 @@ def test_quantize_bf16_bit_exact(h, rows, cols, transpose):
 # ---------------------------------------------------------------- one pass
 @pytest.mark.parametrize("m,n,l", [(1000, 777, 30), (3001, 2500, 110), (517, 4133, 13),
                                    (256, 256, 16), (9000, 300, 133), (300, 9000, 250),
-                                   (2001, 1500, 220), (70, 65, 1)])
+                                   (2001, 1500, 220), (70, 65, 1), (1, 700, 5), (700, 1, 5)])
 @pytest.mark.parametrize("trans", [False, True])
 def test_pass_bf16_matches_rounded_product(h, m, n, l, trans):
     rng = np.random.default_rng(m * 7 + n + l + 1)
@@ -234,7 +234,7 @@ def test_quantize_fp8_bit_exact(h, rows, cols, transpose):
 
 @pytest.mark.parametrize("m,n,l", [(1000, 777, 30), (3001, 2500, 110), (517, 4133, 13),
                                    (300, 9000, 250), (9000, 300, 133), (2001, 1500, 220),
-                                   (70, 65, 1)])
+                                   (70, 65, 1), (1, 700, 5), (700, 1, 5)])
 @pytest.mark.parametrize("trans", [False, True])
 def test_pass_fp8_matches_rounded_product(h, m, n, l, trans):
     rng = np.random.default_rng(m * 5 + n + l + 2)
