@@ -428,9 +428,11 @@ __device__ void b_chol_inv(const CholArgs& ca, const Grid& gr) {
 // R^{-1} (upper triangular, bw x bw <= 128 x 128) is staged in LDS as float32
 // with its diagonal kept in float64 (in the last CholeskyQR round R is close
 // to I, so the off-diagonal entries are tiny and their float32 rounding is a
-// second-order effect); each thread owns one row and 16 interleaved columns
-// of a block of 64 rows.
-constexpr int APPLY_ROWS = 64;
+// second-order effect); each thread owns two rows (r and r + 64) and 16
+// interleaved columns of a block of 128 rows.  A block takes about 131 KB of
+// LDS, one per CU: 128 rows keep a 20000-row product to one round of the
+// device's CUs (64-row blocks took two).
+constexpr int APPLY_ROWS = 128;
 constexpr size_t APPLY_LDS = (size_t)QB * QB * sizeof(float) + QB * sizeof(double) +
                              (size_t)APPLY_ROWS * (QB + 1) * sizeof(float);
 
@@ -462,23 +464,33 @@ __device__ void b_apply_rinv64(const ApplyArgs& aa, const Grid& gr) {
     for (int c = t & 31; c < bw; c += 32) Vs[rr * (QB + 1) + c] = (row < M) ? src[row * lds + c] : 0.f;
   }
   __syncthreads();
-  const int rr = t & 63;          // row within the block
+  const int rr = t & 63;          // rows rr and rr + 64 of the block
   const int cg = t >> 6;          // column group: columns cg, cg+8, ...
-  double acc[QB / 8];
+  double acc[2][QB / 8];
 #pragma unroll
-  for (int jj = 0; jj < QB / 8; ++jj) acc[jj] = 0.0;
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int jj = 0; jj < QB / 8; ++jj) acc[h][jj] = 0.0;
   for (int tt = 0; tt < bw; ++tt) {
-    const double v = Vs[rr * (QB + 1) + tt];
+    const double v0 = Vs[rr * (QB + 1) + tt];
+    const double v1 = Vs[(rr + 64) * (QB + 1) + tt];
     const float* Rr = R + tt * QB + cg;
 #pragma unroll
-    for (int jj = 0; jj < QB / 8; ++jj) acc[jj] = fma(v, (double)Rr[8 * jj], acc[jj]);
+    for (int jj = 0; jj < QB / 8; ++jj) {
+      const double rv = (double)Rr[8 * jj];
+      acc[0][jj] = fma(v0, rv, acc[0][jj]);
+      acc[1][jj] = fma(v1, rv, acc[1][jj]);
+    }
   }
-  const int64_t row = r0 + rr;
-  if (row < M) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int rb = rr + 64 * h;
+    const int64_t row = r0 + rb;
+    if (row >= M) continue;
 #pragma unroll
     for (int jj = 0; jj < QB / 8; ++jj) {
       const int j = cg + 8 * jj;
-      if (j < bw) dst[row * ldd + j] = (float)fma((double)Vs[rr * (QB + 1) + j], Dg[j], acc[jj]);
+      if (j < bw) dst[row * ldd + j] = (float)fma((double)Vs[rb * (QB + 1) + j], Dg[j], acc[h][jj]);
     }
   }
 }
