@@ -419,7 +419,10 @@ def sparse_section(h, n=20000, density=0.003, k=100, p_over=10, reps=3):
 
 def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
     """The precision form (rounded passes, fp32 refinement pass) on the same
-    workload and seeds as the fp32 step; residuals against the fp32 path's."""
+    workload and seeds as the fp32 step; residuals against the fp32 path's.
+    Timed both as four single calls in turn and as one plu_batched call
+    (side by side, as the fp32 step), whose results must equal the single
+    calls' bit for bit."""
     import torch
     l = k + p_over
     flops_step = sum(flops_fixed_rank(m, n, k, l, v) for v in VS)
@@ -429,6 +432,13 @@ def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
             for v in VS:
                 h.fixed_rank(A, k, p_over, v, seed=seed * 16 + v, prec=prec, sync_info=False,
                              out=outs[v])
+        probs = [dict(A=A, mode=0, k=k, p_over=p_over, v=v, seed=0, prec=prec, out=outs[v])
+                 for v in VS]
+
+        def step_batched(seed):
+            for v, pr in zip(VS, probs):
+                pr["seed"] = seed * 16 + v
+            h.batched(probs)
         step(999)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -436,6 +446,18 @@ def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
             step(i)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        step_batched(7)
+        torch.cuda.synchronize()
+        got = {v: [t.clone() for t in outs[v]] for v in VS}
+        step(7)
+        torch.cuda.synchronize()
+        identical = all(all(torch.equal(a, b) for a, b in zip(got[v], outs[v])) for v in VS)
+        del got
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step_batched(i)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t0) / steps
         rr = {}
         for v in VS:
             f = h.fixed_rank(A, k, p_over, v, seed=5 + v, prec=prec, sync_info=True, out=outs[v])
@@ -443,6 +465,9 @@ def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
         res[name] = {
             "ms_per_step": round(dt * 1e3, 3),
             "gflops": round(flops_step / dt / 1e9, 2),
+            "batched_ms_per_step": round(dtb * 1e3, 3),
+            "batched_gflops": round(flops_step / dtb / 1e9, 2),
+            "batched_equals_single_calls": bool(identical),
             "residual": rr,
             "residual_ratio_vs_fp32": {v_: rr[v_] / resid_fp32[v_] for v_ in rr},
         }
