@@ -580,10 +580,11 @@ class Handle:
         """Solve many problems in one batched call (plu_batched).  Each
         problem is a dict with A (device fp32 matrix) and either
         mode=0, k, p_over, v or mode=1, eps, b, l (0: default), v,
-        column_exact; optional Omega, seed, out = (p, q, L, U) device
-        buffers.  one_stream: every problem on the handle's stream (no side
-        streams).  Returns a list of Factors (the fixed-precision ones
-        trimmed to their rank)."""
+        column_exact; optional Omega, seed, prec (any form but
+        PREC_FP64_INDICATOR), out = (p, q, L, U) device buffers.
+        one_stream: every problem on the handle's stream (no side streams).
+        Returns a list of Factors (the fixed-precision ones trimmed to their
+        rank)."""
         t = self._torch
         reqs = (PluRequest * len(problems))()
         keep = []
