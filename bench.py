@@ -844,6 +844,34 @@ def profile_lu(M=20000, c=110, reps=10):
                       "algorithmic_bytes": 8.0 * M * c, "copy_bytes_each_direction": 4 * 2 ** 28}))
 
 
+def profile_residual(m, n, k=K_RANK, reps=3):
+    """The residual kernel alone (plu_residual: ||A - L U||_F recomputed tile
+    by tile with float64 accumulation, the bench's error measure): one
+    fixed-rank factorization of a seeded Gaussian m x n matrix, one warm
+    residual, then reps residuals, then 3 copies of 1 GiB (the byte
+    counters' calibration kernel)."""
+    import torch
+    import paper_2002_07138_amd as plu
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(m + k)
+    A = torch.randn((m, n), device=dev, generator=g)
+    h = plu.Handle(0)
+    f = h.fixed_rank(A, k, P_OVER, 2, seed=3)
+    h.residual(A, f)
+    for _ in range(reps):
+        h.residual(A, f)
+    src = torch.empty(2 ** 28, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    h.close()
+    print(json.dumps({"profile_residual": True, "m": m, "n": n, "k": k, "reps": reps,
+                      "bytes_of_A": 4.0 * m * n, "flops": 2.0 * m * n * k,
+                      "copy_bytes_each_direction": 4 * 2 ** 28}))
+
+
 def profile_single_pass(m, n, k=100):
     """HBM bytes of the single-pass LU: after a 1 GiB fill (the start mark),
     one call on a column-major A (one pass), a 1 GiB copy (calibration, and
@@ -894,6 +922,9 @@ def main():
     ap.add_argument("--profile-lu", action="store_true",
                     help="run only the LU of a 20000 x 110 Gaussian matrix (10 calls) and a plain "
                          "1 GiB copy, for kernel-trace and hardware-counter runs")
+    ap.add_argument("--profile-residual", action="store_true",
+                    help="run only plu_residual on a 20000^2 fixed-rank factorization and a "
+                         "plain 1 GiB copy, for kernel-trace and hardware-counter runs")
     ap.add_argument("--profile-lowp", action="store_true",
                     help="run only the BF16 and FP8 pass kernels (20000^2, l = 110 and "
                          "32768^2, l = 220) and a plain 1 GiB copy, for kernel-trace and "
@@ -919,6 +950,9 @@ def main():
         return
     if args.profile_lowp:
         profile_lowp(m, n)
+        return
+    if args.profile_residual:
+        profile_residual(m, n)
         return
     if args.profile_single_pass:
         profile_single_pass(m, n)

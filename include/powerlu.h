@@ -347,7 +347,9 @@ int plu_sparse_randsvd(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, i
 /* ---- Relative residual ||A[p][:, q] - L U||_F / ||A||_F (eq. "error",
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
  *   all matrix/vector pointers device; rel_resid host; layout of A as in
- *   plu_fixed_rank (L and U row-major).  Synchronizes.                      */
+ *   plu_fixed_rank (L and U row-major).  p and q must be permutations of
+ *   0..m-1 and 0..n-1 (as the factorizations return them): ||A||_F is summed
+ *   from the entries the same pass reads through them.  Synchronizes.       */
 int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
                  int64_t lda,
                  const int32_t* p, const int32_t* q, int32_t k,

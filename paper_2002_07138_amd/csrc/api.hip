@@ -2944,8 +2944,7 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
   char* extra = nullptr;
   const GemmPlan pl = plan_gemm(m, k, n, 1, 1);
   const int64_t nparts = (int64_t)pl.pblocks * pl.cblocks;
-  const int sq_blocks = 1024;
-  const size_t bytes = (nparts + sq_blocks + 2) * sizeof(double) + 1024;
+  const size_t bytes = (2 * nparts + 2) * sizeof(double) + 1024;
   if (hipMalloc(reinterpret_cast<void**>(&extra), bytes) != hipSuccess) {
     hipGetLastError();
     return PLU_ERR_OOM;
@@ -2953,7 +2952,7 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
   Layout lay;
   lay.base = extra;
   double* rpart = lay.take<double>(nparts);
-  double* spart = lay.take<double>(sq_blocks);
+  double* spart = lay.take<double>(nparts);
   double* sums = lay.take<double>(2);
   int rc = PLU_OK;
   do {
@@ -2961,16 +2960,12 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
     g.A = L; g.lda = ldl; g.X = U; g.ldx = ldu;
     g.P = m; g.R = k; g.C = n;
     g.Aref = A; g.pidx = p; g.qidx = q; g.resid_part = rpart;
+    g.aref_sq_part = spart;   // ||A||_F^2 from the entries the same pass reads
     g.ldaref = col ? 1 : lda;     // element (i, j) of A at i * ldaref + j * aref_cs
     g.aref_cs = col ? lda : 1;
     if (launch_gemm(0, EPI_RESID, 0, g, pl, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
     if (launch_sum_doubles(rpart, nparts, sums + 0, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
-    if ((col ? launch_sumsq_matrix(A, lda, n, m, spart, sq_blocks, h->stream)
-             : launch_sumsq_matrix(A, lda, m, n, spart, sq_blocks, h->stream)) != hipSuccess) {
-      rc = PLU_ERR_HIP;
-      break;
-    }
-    if (launch_sum_doubles(spart, sq_blocks, sums + 1, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
+    if (launch_sum_doubles(spart, nparts, sums + 1, h->stream) != hipSuccess) { rc = PLU_ERR_HIP; break; }
     double hs[2];
     if (hipStreamSynchronize(h->stream) != hipSuccess ||
         hipMemcpy(hs, sums, sizeof(hs), hipMemcpyDeviceToHost) != hipSuccess) {

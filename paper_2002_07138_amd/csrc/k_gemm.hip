@@ -241,7 +241,7 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
 
   // Epilogue: acc[i][j][e] is out[p][c] with p = p0 + 16 RT wave + 16 i + 4 g4 + e,
   // c = c0 + 16 j + pr (the 16x16 MFMA output layout).
-  double rs = 0.0;
+  double rs = 0.0, as = 0.0;
 #pragma unroll
   for (int i = 0; i < RT; ++i) {
 #pragma unroll
@@ -264,8 +264,12 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
         } else if (epi == EPI_SUB) {
           g.out[p * g.ldo + c] -= v;
         } else {
-          const double d = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + (int64_t)g.qidx[c] * g.aref_cs] - (double)v;
+          // every entry of A is read by exactly one (p, c): p and q are
+          // permutations, so ||A||_F^2 comes along
+          const double a = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + (int64_t)g.qidx[c] * g.aref_cs];
+          const double d = a - (double)v;
           rs = fma(d, d, rs);
+          as = fma(a, a, as);
         }
       }
     }
@@ -278,6 +282,10 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
   if (epi == EPI_RESID) {
     const double t = block_sum_double(rs, red);
     if (tid == 0) g.resid_part[wg] = t;
+    if (g.aref_sq_part) {
+      const double ta = block_sum_double(as, red);
+      if (tid == 0) g.aref_sq_part[wg] = ta;
+    }
   }
 }
 

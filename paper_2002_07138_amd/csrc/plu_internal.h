@@ -41,6 +41,7 @@ struct GemmArgs {
   const float* Aref = nullptr; int64_t ldaref = 0, aref_cs = 1;   // element (i, j) at i*ldaref + j*aref_cs
   const int32_t* pidx = nullptr; const int32_t* qidx = nullptr;
   double* resid_part = nullptr;
+  double* aref_sq_part = nullptr;     // nullable: ||Aref||_F^2, one partial per workgroup
   // set by launch_gemm: rows of A / X start 16-byte aligned (vector loads allowed)
   int avec = 0, xvec = 0;
   // grouped form only: direction, column tiles per block
