@@ -348,8 +348,11 @@ int plu_sparse_randsvd(plu_handle h, plu_sparse sp, int32_t k, int32_t p_over, i
  * Sec. 6.2), recomputing L U tile by tile with float64 accumulation.
  *   all matrix/vector pointers device; rel_resid host; layout of A as in
  *   plu_fixed_rank (L and U row-major).  p and q must be permutations of
- *   0..m-1 and 0..n-1 (as the factorizations return them): ||A||_F is summed
- *   from the entries the same pass reads through them.  Synchronizes.       */
+ *   0..m-1 and 0..n-1 (as the factorizations return them): the call moves
+ *   row i of L to row p[i] and column j of U to column q[j] in a workspace
+ *   of its own, then reads A once, in place, summing ||A - L' U'||_F^2 and
+ *   ||A||_F^2 together.  Indices out of range are skipped (those rows or
+ *   columns of L U count as zero).  Allocates its workspace; synchronizes. */
 int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float* A,
                  int64_t lda,
                  const int32_t* p, const int32_t* q, int32_t k,

@@ -2944,7 +2944,12 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
   char* extra = nullptr;
   const GemmPlan pl = plan_gemm(m, k, n, 1, 1);
   const int64_t nparts = (int64_t)pl.pblocks * pl.cblocks;
-  const size_t bytes = (2 * nparts + 2) * sizeof(double) + 1024;
+  // L and U moved to A's own order (row p[i] of L, column q[j] of U), so
+  // that the pass reads A in place: ||A - P^T L U Q^T||_F equals the
+  // residual of A[p][:, q] when p and q are permutations
+  const int64_t ldlp = ru(k, 4), ldup = ru(n, 4);
+  const size_t bytes = (2 * nparts + 2) * sizeof(double) +
+                       (size_t)(m * ldlp + (int64_t)k * ldup) * sizeof(float) + 3 * 1024;
   if (hipMalloc(reinterpret_cast<void**>(&extra), bytes) != hipSuccess) {
     hipGetLastError();
     return PLU_ERR_OOM;
@@ -2954,12 +2959,22 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
   double* rpart = lay.take<double>(nparts);
   double* spart = lay.take<double>(nparts);
   double* sums = lay.take<double>(2);
+  float* Lp = lay.take<float>(m * ldlp);
+  float* Up = lay.take<float>((int64_t)k * ldup);
   int rc = PLU_OK;
   do {
+    // cleared first, so that entries a malformed p or q never reaches read as zero
+    if (hipMemsetAsync(Lp, 0, (size_t)(m * ldlp) * sizeof(float), h->stream) != hipSuccess ||
+        hipMemsetAsync(Up, 0, (size_t)((int64_t)k * ldup) * sizeof(float), h->stream) != hipSuccess ||
+        launch_scatter_perm(L, ldl, Lp, ldlp, m, k, p, nullptr, h->stream) != hipSuccess ||
+        launch_scatter_perm(U, ldu, Up, ldup, k, n, nullptr, q, h->stream) != hipSuccess) {
+      rc = PLU_ERR_HIP;
+      break;
+    }
     GemmArgs g;
-    g.A = L; g.lda = ldl; g.X = U; g.ldx = ldu;
+    g.A = Lp; g.lda = ldlp; g.X = Up; g.ldx = ldup;
     g.P = m; g.R = k; g.C = n;
-    g.Aref = A; g.pidx = p; g.qidx = q; g.resid_part = rpart;
+    g.Aref = A; g.resid_part = rpart;
     g.aref_sq_part = spart;   // ||A||_F^2 from the entries the same pass reads
     g.ldaref = col ? 1 : lda;     // element (i, j) of A at i * ldaref + j * aref_cs
     g.aref_cs = col ? lda : 1;

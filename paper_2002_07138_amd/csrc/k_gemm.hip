@@ -264,9 +264,9 @@ __device__ __forceinline__ void pass_body(const GemmArgs& g, const Grid& gr) {
         } else if (epi == EPI_SUB) {
           g.out[p * g.ldo + c] -= v;
         } else {
-          // every entry of A is read by exactly one (p, c): p and q are
-          // permutations, so ||A||_F^2 comes along
-          const double a = (double)g.Aref[(int64_t)g.pidx[p] * g.ldaref + (int64_t)g.qidx[c] * g.aref_cs];
+          // every entry of Aref is read by exactly one (p, c), so
+          // ||Aref||_F^2 comes along
+          const double a = (double)g.Aref[p * g.ldaref + c * g.aref_cs];
           const double d = a - (double)v;
           rs = fma(d, d, rs);
           as = fma(a, a, as);

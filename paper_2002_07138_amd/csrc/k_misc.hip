@@ -74,6 +74,25 @@ __device__ void b_copy_pad(const CopyPadArgs& a, const Grid& gr) {
   a.dst[i * a.ldd + j] = (j < a.cols) ? a.src[i * a.lds + j] : 0.f;
 }
 
+// dst[rperm[i]][cperm[j]] = src[i][j] for i < rows, j < cols; a null
+// permutation is the identity.  Indices outside [0, rows) or [0, cols) are
+// skipped, so a malformed permutation leaves entries unwritten but never
+// writes outside dst.
+struct ScatterArgs {
+  const float* src; int64_t lds; float* dst; int64_t ldd, rows, cols;
+  const int32_t* rperm; const int32_t* cperm;
+};
+
+__device__ void b_scatter_perm(const ScatterArgs& a, const Grid& gr) {
+  const int64_t e = (int64_t)gr.bx * 256 + threadIdx.x;
+  if (e >= a.rows * a.cols) return;
+  const int64_t i = e / a.cols, j = e - i * a.cols;
+  const int64_t di = a.rperm ? (int64_t)a.rperm[i] : i;
+  const int64_t dj = a.cperm ? (int64_t)a.cperm[j] : j;
+  if (di < 0 || di >= a.rows || dj < 0 || dj >= a.cols) return;
+  a.dst[di * a.ldd + dj] = a.src[i * a.lds + j];
+}
+
 // U[t][r] = V[rowidx[r]][t] for t < k, r < nrows (32 x 32 LDS tiles).
 struct TGatherArgs {
   const float* V; int64_t ldv; const int32_t* rowidx; int64_t nrows; int k; float* U;
@@ -246,6 +265,16 @@ hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ld
   return dispatch<CopyPadArgs, b_copy_pad, 256>(
       CopyPadArgs{src, lds, dst, ldd, rows, cols, cols_pad}, dim3((unsigned)((tot + 255) / 256)),
       0, s);
+}
+
+hipError_t launch_scatter_perm(const float* src, int64_t lds, float* dst, int64_t ldd,
+                               int64_t rows, int64_t cols, const int32_t* rperm,
+                               const int32_t* cperm, hipStream_t s) {
+  const int64_t tot = rows * cols;
+  if (tot <= 0) return hipSuccess;
+  return dispatch<ScatterArgs, b_scatter_perm, 256>(
+      ScatterArgs{src, lds, dst, ldd, rows, cols, rperm, cperm},
+      dim3((unsigned)((tot + 255) / 256)), 0, s);
 }
 
 hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,

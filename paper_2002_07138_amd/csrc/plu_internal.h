@@ -39,7 +39,6 @@ struct GemmArgs {
   double* sumsq_part = nullptr;       // fused ||A||_F^2: one partial per workgroup (column block 0)
   // EPI_RESID
   const float* Aref = nullptr; int64_t ldaref = 0, aref_cs = 1;   // element (i, j) at i*ldaref + j*aref_cs
-  const int32_t* pidx = nullptr; const int32_t* qidx = nullptr;
   double* resid_part = nullptr;
   double* aref_sq_part = nullptr;     // nullable: ||Aref||_F^2, one partial per workgroup
   // set by launch_gemm: rows of A / X start 16-byte aligned (vector loads allowed)
@@ -178,6 +177,11 @@ hipError_t launch_gaussian(float* out, int64_t ldo, int64_t rows, int64_t cols, 
                            hipStream_t s);
 hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ldd,
                            int64_t rows, int64_t cols, int64_t cols_pad, hipStream_t s);
+// dst[rperm[i]][cperm[j]] = src[i][j] (rows x cols; null permutation =
+// identity; out-of-range indices are skipped)
+hipError_t launch_scatter_perm(const float* src, int64_t lds, float* dst, int64_t ldd,
+                               int64_t rows, int64_t cols, const int32_t* rperm,
+                               const int32_t* cperm, hipStream_t s);
 // kcap (nullable, device): rows t >= *kcap of U are not written
 hipError_t launch_transpose_gather(const float* V, int64_t ldv, const int32_t* rowidx,
                                    int64_t nrows, int k, float* U, int64_t ldu, hipStream_t s,
