@@ -844,6 +844,26 @@ def profile_lu(M=20000, c=110, reps=10):
                       "algorithmic_bytes": 8.0 * M * c, "copy_bytes_each_direction": 4 * 2 ** 28}))
 
 
+def measured_peaks(h, dev):
+    """What this GPU sustains next to the datasheet peaks (plu_measure_peak):
+    back-to-back matrix-core instructions of the kinds the passes issue, and
+    a streaming read of 2 GiB from HBM; best of 5 launches each."""
+    import torch
+    import paper_2002_07138_amd as plu
+    buf = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
+    out = {
+        "mfma_fp32_tflops": round(h.measure_peak(plu.PEAK_MFMA_FP32), 2),
+        "mfma_bf16_tflops": round(h.measure_peak(plu.PEAK_MFMA_BF16), 1),
+        "mfma_fp8_tflops": round(h.measure_peak(plu.PEAK_MFMA_FP8), 1),
+        "hbm_read_gbs": round(h.measure_peak(plu.PEAK_HBM_READ, buf), 1),
+        "datasheet": {"mfma_fp32_tflops": PEAK_FP32_MFMA_TFLOPS,
+                      "mfma_bf16_tflops": PEAK_BF16_MFMA_TFLOPS,
+                      "mfma_fp8_tflops": PEAK_FP8_MFMA_TFLOPS, "hbm_gbs": PEAK_HBM_GBS},
+    }
+    del buf
+    return out
+
+
 def profile_residual(m, n, k=K_RANK, reps=3):
     """The residual kernel alone (plu_residual: ||A - L U||_F recomputed tile
     by tile with float64 accumulation, the bench's error measure): one
@@ -1093,6 +1113,7 @@ def main():
         forms = precision_forms(h, A, outs, m, n, k, p_over, resid)
         single = single_pass_section(h, A, k)
     traffic = load_traffic()
+    peaks = measured_peaks(h, dev)
     roofline = {
         "bound": "mfma",
         "achieved": round(achieved_tflops, 3),
@@ -1103,6 +1124,8 @@ def main():
         "kernel": "pass over A (k_pass + split-K reduction), FP32 MFMA 16x16x4",
         "flops_per_launch": pass_flops,
         "avg_launch_ms": {"N": round(pass_ms["N"], 4), "T": round(pass_ms["T"], 4)},
+        "peak_measured": peaks["mfma_fp32_tflops"],
+        "frac_of_measured": round(achieved_tflops / peaks["mfma_fp32_tflops"], 4),
     }
 
     result = {
@@ -1129,6 +1152,7 @@ def main():
                    "v": list(VS), "signal_rank": w.rank, "sigma": "exp(-i/40)",
                    "noise": "1e-4*N(0,1)/sqrt(n)", "omega": "Philox4x32-10 on device"},
         "roofline": roofline,
+        "measured_peaks": peaks,
         "per_v_ms": {k_: round(v_, 3) for k_, v_ in per_v.items()},
         "residual": resid,
         "input_generation_s": round(t_gen, 2),

@@ -115,6 +115,14 @@ typedef enum {
   PLU_COL_MAJOR = 1
 } plu_layout;
 
+/* What plu_measure_peak measures. */
+typedef enum {
+  PLU_PEAK_MFMA_FP32 = 0,
+  PLU_PEAK_MFMA_BF16 = 1,
+  PLU_PEAK_MFMA_FP8 = 2,
+  PLU_PEAK_HBM_READ = 3
+} plu_peak_kind;
+
 typedef struct plu_handle_s* plu_handle;
 
 /* Filled on request after the stream has synchronized. */
@@ -393,6 +401,23 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
  * some problem is in a rounded form).
  * Returns PLU_OK, or -3 when some request is invalid (its status then holds
  * -i for its i-th field, counted from 1 in declaration order).             */
+/* ---- Measured ceilings for the rooflines of the pass kernels (the
+ * datasheet peaks are the reference; these are what this GPU sustains).
+ *   kind  PLU_PEAK_MFMA_FP32 / _BF16 / _FP8: back-to-back matrix-core
+ *         instructions of the kinds the passes issue
+ *         (v_mfma_f32_16x16x4f32, v_mfma_f32_16x16x32_bf16, the scaled
+ *         v_mfma_scale_f32_16x16x128_f8f6f4), 8 independent accumulators
+ *         per wave, 8 workgroups of 4 waves per CU, hashed operands;
+ *         *rate in TFLOP/s (dense, 2 m n k per instruction).
+ *         PLU_PEAK_HBM_READ: a streaming read of `bytes` (at least 1 MiB)
+ *         from the device buffer buf (16-byte aligned; contents ignored),
+ *         16-byte non-temporal loads; *rate in GB/s.
+ *   reps  timed launches after one warm-up; *rate is the best of them.
+ * Runs on the handle's stream and synchronizes.  Returns PLU_OK, a negative
+ * argument index, or PLU_ERR_HIP.                                          */
+int plu_measure_peak(plu_handle h, int32_t kind, const void* buf, int64_t bytes, int32_t reps,
+                     double* rate);
+
 /* ---- Pivot trace: the pivot rows and relative pivot gaps of every GETRF of
  * the last plu_fixed_rank / plu_fixed_precision / plu_range_basis /
  * plu_getrf call on the handle, in the order the paper's algorithm makes

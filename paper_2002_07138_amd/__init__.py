@@ -34,6 +34,10 @@ PREC_A_UNCHANGED = 64
 PREC_FP64_INDICATOR = 128
 LAYOUT_ROW = 0
 LAYOUT_COL = 1
+PEAK_MFMA_FP32 = 0
+PEAK_MFMA_BF16 = 1
+PEAK_MFMA_FP8 = 2
+PEAK_HBM_READ = 3
 
 _ENTRY_POINTS = [
     "plu_create", "plu_destroy", "plu_set_stream", "plu_workspace_size", "plu_status_string",
@@ -44,7 +48,7 @@ _ENTRY_POINTS = [
     "plu_sparse_fixed_rank", "plu_sparse_fixed_precision", "plu_sparse_randlu",
     "plu_sparse_randsvd", "plu_server_create",
     "plu_server_submit", "plu_server_poll",
-    "plu_server_wait", "plu_server_destroy", "plu_fixed_rank_static",
+    "plu_server_wait", "plu_server_destroy", "plu_fixed_rank_static", "plu_measure_peak",
 ]
 BATCH_GRAPH = 1
 BATCH_ONE_STREAM = 2
@@ -157,6 +161,7 @@ def _lib():
             "plu_server_poll": [vp, u64, ctypes.POINTER(PluResult)],
             "plu_server_wait": [vp, u64, ctypes.POINTER(PluResult)],
             "plu_server_destroy": [vp],
+            "plu_measure_peak": [vp, i32, vp, i64, i32, ctypes.POINTER(dbl)],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -656,6 +661,15 @@ class Handle:
             gaps.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n.value, ctypes.byref(n)),
             "plu_pivot_trace")
         return piv, gaps
+
+    def measure_peak(self, kind: int, buf=None, reps: int = 5) -> float:
+        """plu_measure_peak: TFLOP/s of a matrix-core loop (PEAK_MFMA_*) or
+        GB/s of a streaming read of the device tensor buf (PEAK_HBM_READ)."""
+        r = ctypes.c_double()
+        nbytes = 0 if buf is None else buf.numel() * buf.element_size()
+        self._rc(_lib().plu_measure_peak(self._h, kind, None if buf is None else _ptr(buf),
+                                         nbytes, reps, ctypes.byref(r)), "plu_measure_peak")
+        return r.value
 
     def residual(self, A, f: Factors):
         lay, lda = _layout_of(A)

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpowerlu.so")
 SOURCES = ["k_gemm.hip", "k_getrf.hip", "k_qr.hip", "k_misc.hip", "k_lowp.hip", "k_svd.hip",
-           "k_sparse.hip", "k_f64.hip", "batch.hip", "api.hip"]
+           "k_sparse.hip", "k_f64.hip", "k_peaks.hip", "batch.hip", "api.hip"]
 ARCH = os.environ.get("PLU_OFFLOAD_ARCH", "gfx950")
 
 CXXFLAGS = [

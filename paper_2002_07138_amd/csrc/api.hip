@@ -2994,6 +2994,53 @@ int plu_residual(plu_handle h, int32_t layout, int64_t m, int64_t n, const float
   return rc;
 }
 
+int plu_measure_peak(plu_handle h, int32_t kind, const void* buf, int64_t bytes, int32_t reps,
+                     double* rate) {
+  if (!h) return -1;
+  if (kind < PLU_PEAK_MFMA_FP32 || kind > PLU_PEAK_HBM_READ) return -2;
+  const bool hbm = kind == PLU_PEAK_HBM_READ;
+  if (hbm && (!buf || (reinterpret_cast<uintptr_t>(buf) & 15u))) return -3;
+  if (hbm && bytes < (int64_t)1 << 20) return -4;
+  if (reps < 1) return -5;
+  if (!rate) return -6;
+  PLU_TRY_HIP(hipSetDevice(h->device));
+  const int blocks = h->cu_count * 8;
+  // about 3 ms per launch at the datasheet rates
+  const int iters = kind == PLU_PEAK_MFMA_BF16 ? 8192 : 4096;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return PLU_ERR_HIP;
+  }
+  auto launch = [&]() {
+    return hbm ? launch_peak_read(buf, bytes, blocks, h->stream)
+               : launch_peak_mfma(kind, blocks, iters, h->stream);
+  };
+  int rc = PLU_OK;
+  float best = 0.f;
+  if (launch() != hipSuccess) rc = PLU_ERR_HIP;   // warm-up (clocks, caches, code)
+  for (int r = 0; r < reps && rc == PLU_OK; ++r) {
+    float ms = 0.f;
+    if (hipEventRecord(e0, h->stream) != hipSuccess || launch() != hipSuccess ||
+        hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = PLU_ERR_HIP;
+      break;
+    }
+    if (r == 0 || ms < best) best = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PLU_OK) return rc;
+  if (hbm) {
+    *rate = (double)(bytes / 16 * 16) / (best * 1e-3) / 1e9;   // GB/s
+  } else {
+    const double flop = (double)blocks * 4 * iters * peak_chains() * peak_flop_per_mfma(kind);
+    *rate = flop / (best * 1e-3) / 1e12;   // TFLOP/s
+  }
+  return PLU_OK;
+}
+
 int plu_set_pivot_trace(plu_handle h, int64_t capacity) {
   if (!h) return -1;
   if (capacity < 0) return -2;

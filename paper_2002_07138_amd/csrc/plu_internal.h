@@ -177,6 +177,13 @@ hipError_t launch_gaussian(float* out, int64_t ldo, int64_t rows, int64_t cols, 
                            hipStream_t s);
 hipError_t launch_copy_pad(const float* src, int64_t lds, float* dst, int64_t ldd,
                            int64_t rows, int64_t cols, int64_t cols_pad, hipStream_t s);
+// Measured ceilings (k_peaks.hip): kind 0 / 1 / 2 = the fp32 / bfloat16 /
+// scaled FP8 matrix-core loop (blocks x 4 waves, each iters x chains
+// instructions), the streaming read of `bytes` from buf.
+double peak_flop_per_mfma(int kind);
+int peak_chains();
+hipError_t launch_peak_mfma(int kind, int blocks, int iters, hipStream_t s);
+hipError_t launch_peak_read(const void* buf, int64_t bytes, int blocks, hipStream_t s);
 // dst[rperm[i]][cperm[j]] = src[i][j] (rows x cols; null permutation =
 // identity; out-of-range indices are skipped)
 hipError_t launch_scatter_perm(const float* src, int64_t lds, float* dst, int64_t ldd,
