@@ -471,6 +471,16 @@ def precision_forms(h, A, outs, m, n, k, p_over, resid_fp32, steps=3):
             "residual": rr,
             "residual_ratio_vs_fp32": {v_: rr[v_] / resid_fp32[v_] for v_ in rr},
         }
+    # one rounded pass of each format over the kept copies (sketch rounding and
+    # split-K sum included) against HBM
+    passes = {}
+    for name, prec, bytes_a in (("bf16", 1, 2.0 * m * n), ("fp8_e4m3", 2, m * n * (1 + 1 / 32.0))):
+        t = _pass_times(h, A, l, prec=prec)
+        ms = 0.5 * (t["N"] + t["T"])
+        passes[name] = {"ms": t, "bound": "hbm", "algorithmic_bytes": bytes_a,
+                        "achieved_gbs": round(bytes_a / (ms * 1e-3) / 1e9, 1),
+                        "frac": round(bytes_a / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    res["passes"] = passes
     return res
 
 
