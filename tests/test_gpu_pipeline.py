@@ -114,6 +114,57 @@ def test_residual_kernel_matches_oracle(h):
     assert abs(r_dev - r_ref) <= 1e-4 * r_ref
 
 
+@pytest.mark.parametrize("col_major", [False, True])
+def test_residual_kernel_permuted_ragged(h, col_major):
+    """plu_residual against the definition ||A[p][:, q] - L U||_F / ||A||_F
+    (eq. "error", Sec. 6.2) in float64, for arbitrary permutations and
+    factors (not from a factorization: the residual is O(1)), on a shape
+    that spans several output tiles with ragged edges, in both storage
+    orders of A."""
+    import paper_2002_07138_amd as plu
+    m, n, k = 1000, 777, 37
+    g = np.random.default_rng(71)
+    A = g.standard_normal((m, n)).astype(np.float32)
+    L = g.standard_normal((m, k)).astype(np.float32)
+    U = g.standard_normal((k, n)).astype(np.float32)
+    p = g.permutation(m).astype(np.int32)
+    q = g.permutation(n).astype(np.int32)
+    Ad = dev(np.ascontiguousarray(A.T)).t() if col_major else dev(A)
+    f = plu.Factors(dev(p), dev(q), dev(L), dev(U), k, {})
+    r_dev = h.residual(Ad, f)
+    A64 = A.astype(np.float64)
+    R = A64[p][:, q] - L.astype(np.float64) @ U.astype(np.float64)
+    r_ref = np.linalg.norm(R) / np.linalg.norm(A64)
+    assert abs(r_dev - r_ref) <= 1e-6 * r_ref, (r_dev, r_ref)
+
+
+def test_residual_kernel_skips_out_of_range_pivots(h):
+    """An index of p outside [0, m) is skipped: the row of L U it would have
+    filled counts as zero (the behaviour the header documents)."""
+    import paper_2002_07138_amd as plu
+    m, n, k = 600, 500, 20
+    g = np.random.default_rng(72)
+    A = g.standard_normal((m, n)).astype(np.float32)
+    L = g.standard_normal((m, k)).astype(np.float32)
+    U = g.standard_normal((k, n)).astype(np.float32)
+    p = g.permutation(m).astype(np.int32)
+    q = g.permutation(n).astype(np.int32)
+    lost = int(p[5])
+    p[5] = m + 3
+    f = plu.Factors(dev(p), dev(q), dev(L), dev(U), k, {})
+    r_dev = h.residual(dev(A), f)
+    Lp = np.zeros((m, k))
+    for i in range(m):
+        if 0 <= p[i] < m:
+            Lp[p[i]] = L[i]
+    Up = np.zeros((k, n))
+    Up[:, q] = U
+    assert not Lp[lost].any()
+    A64 = A.astype(np.float64)
+    r_ref = np.linalg.norm(A64 - Lp @ Up) / np.linalg.norm(A64)
+    assert abs(r_dev - r_ref) <= 1e-6 * r_ref, (r_dev, r_ref)
+
+
 # The fp32 path's stopping indicator E_k = ||A||^2 - sum_{j<=k} ||A v_j||^2 differs
 # from the fp64 oracle's by about eta ||A||^2, eta the loss of orthogonality of
 # the stored fp32 basis (single Gram-Schmidt block: final CholeskyQR product in
