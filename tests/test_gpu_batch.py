@@ -195,3 +195,26 @@ def test_batch_tuned_plans_match_single_calls(h, rows, one_stream, monkeypatch):
         _same(f, g)
     del A, U, V
     torch.cuda.empty_cache()
+
+
+def test_batch_before_single_calls_of_an_untuned_shape(h, monkeypatch):
+    """The batch runs first on a shape whose size class no earlier call has
+    tuned: the batch tunes the passes' splits eagerly, before recording, so
+    the single calls that follow take the same plans and still equal the
+    batch bitwise (the split changes the float32 summation order)."""
+    monkeypatch.setenv("PLU_AUTOTUNE_ROWS", "128")
+    m, n = 12500, 7500
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(77)
+    U = torch.randn(m, 80, device="cuda:0", generator=gen)
+    V = torch.randn(80, n, device="cuda:0", generator=gen)
+    A = (U @ V) / 80.0 + 1e-3 * torch.randn(m, n, device="cuda:0", generator=gen)
+    assert 2.0 * m * n * 110 >= 2e10
+    probs = [dict(A=A, mode=0, k=100, p_over=10, v=3, seed=3),
+             dict(A=A, mode=0, k=100, p_over=10, v=4, seed=4)]
+    outs = h.batched(probs)
+    singles = [_single(h, pr) for pr in probs]
+    for f, g in zip(outs, singles):
+        _same(f, g)
+    del A, U, V
+    torch.cuda.empty_cache()
