@@ -20,7 +20,10 @@ namespace {
 
 constexpr int QB = 128;   // column block of the Gram-Schmidt sweep
 
-// part[chunk][a][b] = sum over the chunk's rows of V[i][a] V[i][b] (float64).
+// part[chunk][a][b] = sum over the chunk's rows of V[i][a] V[i][b] (float64),
+// for a / 16 <= b / 16 only (the Gram is symmetric: b_gram_reduce reads the
+// other entries from their mirror, which the same products in the same
+// order give bit for bit).
 struct GramArgs {
   const float* V; int64_t ldv, M; int bw; int64_t rows_per_chunk; double* part;
   const int32_t* run_if;   // nullable: nothing is done when it reads 0
@@ -51,7 +54,10 @@ __device__ void b_gram(const GramArgs& ga, const Grid& gr) {
       S[rr][cc] = (row < r1 && cc < bw) ? V[row * ldv + cc] : 0.f;
     }
     __syncthreads();
-    for (int rr = 0; rr < 64; ++rr) {
+    // the tile's rows past the chunk are zeros: adding their products would
+    // change no sum, so they are skipped
+    const int nr = (r1 - rb < 64) ? (int)(r1 - rb) : 64;
+    for (int rr = 0; rr < nr; ++rr) {
       double av[8], bv[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) av[i] = S[rr][ta + 16 * i];
@@ -60,7 +66,7 @@ __device__ void b_gram(const GramArgs& ga, const Grid& gr) {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int j = i; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
     }
   }
   double* out = part + (int64_t)gr.bx * bw * bw;
@@ -69,7 +75,7 @@ __device__ void b_gram(const GramArgs& ga, const Grid& gr) {
     const int a = ta + 16 * i;
     if (a >= bw) continue;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = i; j < 8; ++j) {
       const int b = tb + 16 * j;
       if (b < bw) out[a * bw + b] = acc[i][j];
     }
@@ -87,6 +93,10 @@ __device__ void b_gram_reduce(const GramReduceArgs& ga, const Grid& gr) {
   if (ga.run_if && *ga.run_if == 0) return;
   const int e = gr.bx * 256 + threadIdx.x;
   if (e >= bw * bw) return;
+  // b_gram keeps entry (a, b) only for a / 16 <= b / 16; the thread of such
+  // an entry also writes its mirror
+  const int a = e / bw, b = e % bw;
+  if (a / 16 > b / 16) return;
   // eight independent partial sums keep eight loads in flight; fixed order
   double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t st = (int64_t)bw * bw;
@@ -96,7 +106,9 @@ __device__ void b_gram_reduce(const GramReduceArgs& ga, const Grid& gr) {
     for (int u = 0; u < 8; ++u) s8[u] += part[(int64_t)(c + u) * st + e];
   }
   for (int u = 0; c < nchunk; ++c, ++u) s8[u] += part[(int64_t)c * st + e];
-  W[e] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  const double t = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  W[e] = t;
+  if (a / 16 < b / 16) W[b * bw + a] = t;
 }
 
 // Cholesky W = L L^T and Y = L^{-1} in float64 inside one workgroup; R^{-1}
