@@ -483,15 +483,25 @@ __device__ void b_apply_rinv64(const ApplyArgs& aa, const Grid& gr) {
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int jj = 0; jj < QB / 8; ++jj) acc[h][jj] = 0.0;
-  for (int tt = 0; tt < bw; ++tt) {
-    const double v0 = Vs[rr * (QB + 1) + tt];
-    const double v1 = Vs[(rr + 64) * (QB + 1) + tt];
-    const float* Rr = R + tt * QB + cg;
+  // R^{-1} is upper triangular (its diagonal applied below): column j takes
+  // the terms tt < j only.  Segment s covers the tt with columns jj >= s of
+  // this thread's group still open; every column's chain keeps the order of
+  // tt, and the skipped terms are exact zeros, so the sums are those of the
+  // full loop.
 #pragma unroll
-    for (int jj = 0; jj < QB / 8; ++jj) {
-      const double rv = (double)Rr[8 * jj];
-      acc[0][jj] = fma(v0, rv, acc[0][jj]);
-      acc[1][jj] = fma(v1, rv, acc[1][jj]);
+  for (int sg = 0; sg < QB / 8; ++sg) {
+    const int lo = sg == 0 ? 0 : cg + 8 * (sg - 1);
+    const int hi = (cg + 8 * sg < bw) ? cg + 8 * sg : bw;
+    for (int tt = lo; tt < hi; ++tt) {
+      const double v0 = Vs[rr * (QB + 1) + tt];
+      const double v1 = Vs[(rr + 64) * (QB + 1) + tt];
+      const float* Rr = R + tt * QB + cg;
+#pragma unroll
+      for (int jj = sg; jj < QB / 8; ++jj) {
+        const double rv = (double)Rr[8 * jj];
+        acc[0][jj] = fma(v0, rv, acc[0][jj]);
+        acc[1][jj] = fma(v1, rv, acc[1][jj]);
+      }
     }
   }
 #pragma unroll
